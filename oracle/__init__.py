@@ -1,0 +1,156 @@
+"""FP64 CPU oracle for the batched mesh rasterizer and the silhouette blend.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU-baseline
+leg of the benchmark may import this package.  The product path (the HIP
+library and its Python binding) never imports, links or calls it, and it never
+imports the product path: the two share nothing but the seeded input
+generator, which holds none of the method's arithmetic.
+
+The rasterizer oracle is plain C (``oracle_rast.c``, built here with gcc and
+loaded with ctypes); the blend oracle is NumPy in float64 (``blend.py``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle_rast.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle_rast.c into liboracle.so (gcc, -O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+               "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", tmp, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    ci = ctypes.c_int
+    lib.oracle_rasterize.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, ctypes.c_double, ci, P, i64,
+                                     P, P, P, P, P, P, ci]
+    lib.oracle_rasterize.restype = ci
+    lib.oracle_fragments_fixed.argtypes = [P, P, ci, ci, ci, ci, P, P, P, P, P, ci]
+    lib.oracle_fragments_fixed.restype = ci
+    lib.oracle_backward.argtypes = [P, i64, P, ci, ci, ci, ci, P, P, P, P, P, ci]
+    lib.oracle_backward.restype = ci
+    lib.oracle_max_threads.argtypes = []
+    lib.oracle_max_threads.restype = ci
+    _lib = lib
+    return lib
+
+
+def default_threads() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i64(a):
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+def rasterize(verts, faces, first_idx, num_faces, image_size, blur_radius, faces_per_pixel,
+              pixels=None, nthreads: Optional[int] = None):
+    """Brute-force FP64 rasterization.
+
+    verts (V,3) (float32 inputs are promoted exactly), faces (F,3) global ids,
+    first_idx/num_faces (N,).  ``pixels``: optional 1-D array of linear pixel
+    ids n*H*W + r*W + c; default every pixel.  Returns a dict with p2f (int64),
+    zbuf, bary, dists (float64), amb (uint8 bit mask M1..M5) and nhits (int64),
+    shaped (N,H,W,K[,3]) for full images or (npix,K[,3]) for a pixel list.
+    """
+    lib = _load()
+    H, W = image_size
+    K = int(faces_per_pixel)
+    N = int(np.asarray(first_idx).shape[0])
+    v = _f64(verts)
+    f = _i64(faces)
+    fi = _i64(first_idx)
+    nf = _i64(num_faces)
+    pix = None if pixels is None else _i64(pixels)
+    npix = N * H * W if pix is None else pix.shape[0]
+    p2f = np.empty((npix, K), np.int64)
+    zbuf = np.empty((npix, K), np.float64)
+    bary = np.empty((npix, K, 3), np.float64)
+    dists = np.empty((npix, K), np.float64)
+    amb = np.empty((npix,), np.uint8)
+    nh = np.empty((npix,), np.int64)
+    rc = lib.oracle_rasterize(_ptr(v), v.shape[0], _ptr(f), f.shape[0], _ptr(fi), _ptr(nf), N, H, W,
+                              float(blur_radius), K, _ptr(pix), npix, _ptr(p2f), _ptr(zbuf), _ptr(bary),
+                              _ptr(dists), _ptr(amb), _ptr(nh), nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("oracle_rasterize rejected its arguments")
+    out = dict(p2f=p2f, zbuf=zbuf, bary=bary, dists=dists, amb=amb, nhits=nh)
+    if pix is None:
+        out = {k: a.reshape((N, H, W) + a.shape[1:]) for k, a in out.items()}
+    return out
+
+
+def fragments_fixed(verts, faces, image_size, p2f, nthreads: Optional[int] = None):
+    """zbuf, bary, dists (float64) and the per-slot edge-tie mask for a given
+    face choice p2f (N,H,W,K); the forward map with the selection frozen."""
+    lib = _load()
+    H, W = image_size
+    p = _i64(p2f)
+    N, K = p.shape[0], p.shape[-1]
+    v = _f64(verts)
+    f = _i64(faces)
+    zbuf = np.empty(p.shape, np.float64)
+    bary = np.empty(p.shape + (3,), np.float64)
+    dists = np.empty(p.shape, np.float64)
+    tie = np.empty(p.shape, np.uint8)
+    lib.oracle_fragments_fixed(_ptr(v), _ptr(f), N, H, W, K, _ptr(p), _ptr(zbuf), _ptr(bary), _ptr(dists),
+                               _ptr(tie), nthreads or default_threads())
+    return zbuf, bary, dists, tie
+
+
+def backward(verts, faces, image_size, p2f, grad_zbuf=None, grad_bary=None, grad_dists=None,
+             nthreads: Optional[int] = None):
+    """Analytic FP64 dL/dverts (V,3) for L = <gz,zbuf> + <gb,bary> + <gd,dists>
+    over the slots of p2f (N,H,W,K)."""
+    lib = _load()
+    H, W = image_size
+    p = _i64(p2f)
+    N, K = p.shape[0], p.shape[-1]
+    v = _f64(verts)
+    f = _i64(faces)
+    gz = None if grad_zbuf is None else _f64(grad_zbuf)
+    gb = None if grad_bary is None else _f64(grad_bary)
+    gd = None if grad_dists is None else _f64(grad_dists)
+    out = np.empty(v.shape, np.float64)
+    rc = lib.oracle_backward(_ptr(v), v.shape[0], _ptr(f), N, H, W, K, _ptr(p), _ptr(gz), _ptr(gb), _ptr(gd),
+                             _ptr(out), nthreads or default_threads())
+    if rc != 0:
+        raise MemoryError("oracle_backward failed")
+    return out
+
+
+from .blend import silhouette_blend, silhouette_blend_backward, iou_loss  # noqa: E402,F401

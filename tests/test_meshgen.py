@@ -1,0 +1,61 @@
+"""Synthetic-input generator: sizes, topology, orientation, determinism."""
+import numpy as np
+import pytest
+
+from paper_2007_08501_amd import meshgen
+
+
+@pytest.mark.parametrize("level", [0, 1, 2, 3, 4, 5])
+def test_icosphere_counts_and_topology(level):
+    v, f = meshgen.icosphere(level)
+    assert v.shape == (10 * 4**level + 2, 3)
+    assert f.shape == (20 * 4**level, 3)
+    edges = set()
+    for a, b, c in f:
+        for x, y in ((a, b), (b, c), (c, a)):
+            edges.add((min(x, y), max(x, y)))
+    assert len(v) - len(edges) + len(f) == 2  # Euler characteristic of a sphere
+    np.testing.assert_allclose(np.linalg.norm(v, axis=1), 1.0, rtol=0, atol=1e-12)
+    n = np.cross(v[f[:, 1]] - v[f[:, 0]], v[f[:, 2]] - v[f[:, 0]])
+    assert (np.einsum("ij,ij->i", n, v[f].mean(1)) > 0).all()  # outward winding
+
+
+def test_paper_sphere_template_sizes():
+    # Sphere templates of 642 verts / 1280 faces and 2562 / 5120 (Section 4.1)
+    assert meshgen.icosphere(3)[0].shape[0] == 642 and meshgen.icosphere(3)[1].shape[0] == 1280
+    assert meshgen.icosphere(4)[0].shape[0] == 2562 and meshgen.icosphere(4)[1].shape[0] == 5120
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 5])
+def test_config_determinism_and_packing(cfg):
+    a = meshgen.make_config(cfg)
+    b = meshgen.make_config(cfg)
+    assert a.verts.dtype == np.float32 and a.faces.dtype == np.int32
+    assert np.array_equal(a.verts, b.verts) and np.array_equal(a.faces, b.faces)
+    assert a.first_idx[0] == 0
+    assert np.array_equal(np.cumsum(a.num_faces)[:-1], a.first_idx[1:])
+    for n in range(a.N):
+        fs = a.faces[a.first_idx[n]:a.first_idx[n] + a.num_faces[n]]
+        assert fs.min() >= a.verts_first_idx[n]
+        assert fs.max() < a.verts_first_idx[n] + a.num_verts[n]
+    c = meshgen.make_config(cfg, batch=1)
+    assert not np.array_equal(a.verts, c.verts) or cfg == 5
+
+
+def test_config_sizes():
+    assert meshgen.make_config(1).faces.shape[0] == 320
+    assert meshgen.make_config(2).faces.shape[0] == 8 * 5120
+    c3 = meshgen.make_config(3)
+    assert set(c3.levels) <= {2, 3, 4, 5} and c3.N == 32
+    assert c3.faces.shape[0] == sum(20 * 4**L for L in c3.levels)
+    c5 = meshgen.make_config(5)
+    assert c5.N == 20 and c5.faces_per_pixel == 50
+
+
+def test_upstream_grads_seeded():
+    b = meshgen.make_config(2, image_override=32)
+    g1 = meshgen.upstream_grads(b)
+    g2 = meshgen.upstream_grads(b)
+    for x, y in zip(g1, g2):
+        assert x.dtype == np.float32 and np.array_equal(x, y)
+    assert g1[1].shape == (8, 32, 32, 4, 3)
