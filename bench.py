@@ -1,0 +1,301 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched differentiable mesh rasterizer on one MI355X.
+
+One step = forward (face setup, coarse binning, per-pixel K-nearest pass) plus
+backward (fragment gradients -> vertex gradients) over one synthetic batch,
+all through the C ABI of librast.so with inputs resident in HBM.
+
+Default workload: 4 icospheres at subdivision level 7 (327,680 faces each),
+1024x1024 images, K = 16 nearest faces per pixel, blur radius 1e-5 -- the
+large configuration on which the HBM roofline is measured.  ``--config`` picks
+one of the other synthetic workloads instead.
+
+Prints ONE JSON line: throughput in Mpixel*K/s (N*H*W*K / step time), ms per
+step, the roofline of the dominant kernel (timed live with HIP events the
+library records around its launch), the per-mesh plain form (one single-pass
+call per mesh, no bins, no graph) timed on the same GPU, a sampled parity
+check against the FP64 oracle, and the oracle's own throughput on a bounded
+sample of the workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd rasterized Mpixel·K/s and ms/batch, batched vs per-mesh, at oracle tol"
+UNIT = "Mpixel·K/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class HipEvents:
+    """Raw hipEvent_t handles through the HIP runtime torch already loaded."""
+
+    def __init__(self):
+        import torch  # noqa: F401  (loads libamdhip64)
+        self.rt = ctypes.CDLL("libamdhip64.so")
+        self.rt.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.rt.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.rt.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        self.rt.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+        self.rt.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+
+    def create(self):
+        e = ctypes.c_void_p()
+        assert self.rt.hipEventCreate(ctypes.byref(e)) == 0
+        return e.value
+
+    def record(self, e, stream):
+        assert self.rt.hipEventRecord(ctypes.c_void_p(e), ctypes.c_void_p(stream)) == 0
+
+    def elapsed(self, a, b):
+        assert self.rt.hipEventSynchronize(ctypes.c_void_p(b)) == 0
+        ms = ctypes.c_float()
+        assert self.rt.hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(a), ctypes.c_void_p(b)) == 0
+        return float(ms.value)
+
+    def destroy(self, e):
+        self.rt.hipEventDestroy(ctypes.c_void_p(e))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=4, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--batch", type=int, default=0, help="seeded batch index 0..4")
+    ap.add_argument("--bin-size", type=int, default=None, help="fixed bin size (default: autotune)")
+    ap.add_argument("--max-faces-per-bin", type=int, default=None)
+    ap.add_argument("--sched", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-mesh", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported: this rasterizer runs on one GPU; the batch would "
+              "shard by image across GPUs but no multi-GPU path is built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2007_08501_amd import _lib, meshgen
+    from paper_2007_08501_amd.autotune import autotune
+    from paper_2007_08501_amd.raster import count_max_faces_per_bin, empty_fragments, round_up
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    b = meshgen.make_config(args.config, batch=args.batch)
+    N, (H, W), K = b.N, b.image_size, b.faces_per_pixel
+    log(f"[bench] cfg{args.config}: N={N} {H}x{W} K={K} blur={b.blur_radius:g} V={b.verts.shape[0]} "
+        f"F={b.faces.shape[0]}")
+    v = torch.from_numpy(b.verts).to(dev)
+    f = torch.from_numpy(b.faces).to(dev)
+    fi = torch.from_numpy(b.first_idx).to(dev)
+    nf = torch.from_numpy(b.num_faces).to(dev)
+    gz_np, gb_np, gd_np = meshgen.upstream_grads(b)
+    gz = torch.from_numpy(gz_np).to(dev)
+    gb = torch.from_numpy(gb_np).to(dev)
+    gd = torch.from_numpy(gd_np).to(dev)
+
+    # ---------------------------------------------------------------- setup (untimed)
+    t0 = time.time()
+    if args.bin_size is None:
+        ch = autotune(v, f, fi, nf, H, W, b.blur_radius, K, reps=3)
+        bs, M, sched = ch.bin_size, ch.max_faces_per_bin, ch.sched
+        log(f"[bench] autotune -> bin_size={bs} M={M} sched={sched} ({ch.ms:.3f} ms) in {time.time() - t0:.1f}s")
+    else:
+        bs = args.bin_size
+        sched = args.sched or 0
+        M = args.max_faces_per_bin
+        if bs > 0 and M is None:
+            M = round_up(count_max_faces_per_bin(v, f, fi, nf, H, W, b.blur_radius, bs), 32)
+    if args.sched is not None:
+        sched = args.sched
+    M = M or 0
+    out = empty_fragments(N, H, W, K, dev)
+    ws = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, f.shape[0], bs, M), dev)
+    bws = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, f.shape[0], 0, 0), dev)
+    gv = torch.empty_like(v)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def step():
+        _lib.rasterize_meshes_fwd(v, f, fi, nf, H, W, b.blur_radius, K, bs, M, sched, out.pix_to_face, out.zbuf,
+                                  out.bary, out.dists, ws)
+        _lib.rasterize_meshes_bwd(v, f, N, H, W, K, out.pix_to_face, gz, gb, gd, gv, bws)
+
+    ev = HipEvents()
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # ---------------------------------------------------------------- timed region
+    n = args.steps
+    kev = [[ev.create() for _ in range(4)] for _ in range(n)]
+    e_start, e_end = ev.create(), ev.create()
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ev.record(e_start, stream)
+    for i in range(n):
+        _lib.rast_set_kernel_events(_lib.RAST_KERNEL_FINE, kev[i][0], kev[i][1])
+        _lib.rast_set_kernel_events(_lib.RAST_KERNEL_BWD, kev[i][2], kev[i][3])
+        step()
+    ev.record(e_end, stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    _lib.rast_set_kernel_events(_lib.RAST_KERNEL_FINE, None, None)
+    _lib.rast_set_kernel_events(_lib.RAST_KERNEL_BWD, None, None)
+    total_ms = ev.elapsed(e_start, e_end)
+    ms_step = total_ms / n
+    fine_ms = sum(ev.elapsed(k[0], k[1]) for k in kev) / n
+    bwd_ms = sum(ev.elapsed(k[2], k[3]) for k in kev) / n
+    for k in kev:
+        for e in k:
+            ev.destroy(e)
+    st, mx = _lib.rast_query_status(ws)
+    if st != _lib.RAST_OK:
+        log(f"[bench] device status: {_lib.status_string(st)} (max bin count {mx})")
+        sys.exit(1)
+    log(f"[bench] {n} steps: {ms_step:.4f} ms/step (wall {wall * 1e3 / n:.4f}); fine {fine_ms:.4f} ms, "
+        f"bwd {bwd_ms:.4f} ms")
+
+    S = N * H * W * K
+    S_valid = int((out.pix_to_face >= 0).sum().item())
+    V, F = b.verts.shape[0], b.faces.shape[0]
+    fine_bytes = 24 * S + 12 * V + 12 * F
+    bwd_bytes = 4 * S + 20 * S_valid + 24 * V + 12 * F
+    step_bytes = fine_bytes + bwd_bytes
+    kernels = {"fine": (fine_ms, fine_bytes), "backward": (bwd_ms, bwd_bytes)}
+    dom = max(kernels, key=lambda k: kernels[k][0])
+    dom_ms, dom_bytes = kernels[dom]
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel_ms": round(dom_ms, 5), "algorithmic_bytes": dom_bytes}
+
+    # ---------------------------------------------------------------- parity spot check
+    import oracle
+    nthr = min(16, oracle.default_threads())
+    rng = np.random.default_rng(1234)
+    cov = torch.nonzero((out.pix_to_face[..., 0] >= 0).reshape(-1)).reshape(-1).cpu().numpy()
+    pix = np.unique(np.concatenate([rng.integers(0, N * H * W, 128),
+                                    rng.choice(cov, size=min(128, cov.size), replace=False)]))
+    tq = time.perf_counter()
+    o = oracle.rasterize(b.verts, b.faces, b.first_idx, b.num_faces, (H, W), b.blur_radius, K, pixels=pix,
+                         nthreads=nthr)
+    t_spot = time.perf_counter() - tq
+    pix_t = torch.from_numpy(pix).to(dev)
+    g = {k: t.reshape((N * H * W,) + tuple(t.shape[3:]))[pix_t].cpu().numpy()
+         for k, t in zip(("p2f", "zbuf", "bary", "dists"), out)}
+    amb = o["amb"] != 0
+    p_ok = bool(((g["p2f"] == o["p2f"]).all(-1) | amb).all())
+    same = (g["p2f"] == o["p2f"]) & (o["p2f"] >= 0)
+    wv = o["bary"][same]
+    v_ok = bool((np.abs(g["bary"][same] - wv) <= 1e-5 * np.maximum(1, np.abs(wv))).all()
+                and (np.abs(g["dists"][same] - o["dists"][same]) <= 1e-5).all())
+    fz = b.verts.astype(np.float64)[b.faces[o["p2f"][same]]][..., 2]
+    z_ok = bool((np.abs(g["zbuf"][same] - o["zbuf"][same]) <= 1e-5 * np.maximum(1, np.abs(wv * fz).sum(-1))).all())
+    # backward on the sampled pixels only (upstream grads zeroed elsewhere), both sides
+    keep = torch.zeros(N * H * W, dtype=torch.bool, device=dev)
+    keep[pix_t] = True
+    p2f_s = torch.where(keep.view(N, H, W, 1), out.pix_to_face, torch.full_like(out.pix_to_face, -1))
+    gv_s = torch.empty_like(v)
+    _lib.rasterize_meshes_bwd(v, f, N, H, W, K, p2f_s, gz, gb, gd, gv_s, bws)
+    rows = lambda a: a.reshape((N * H * W,) + a.shape[3:])[pix]
+    p2f_rows = rows(out.pix_to_face.cpu().numpy()).astype(np.int64)
+    ref = oracle.backward(b.verts, b.faces, (H, W), p2f_rows, rows(gz_np), rows(gb_np), rows(gd_np), nthreads=nthr,
+                          pixels=pix, N=N)
+    gvs = gv_s.cpu().numpy().astype(np.float64)
+    gerr = float(np.abs(gvs - ref).max() / max(1e-30, np.abs(ref).max()))
+    parity = {"pixels": int(pix.size), "pix_to_face_ok": p_ok, "values_ok": v_ok and z_ok,
+              "ambiguous_frac": round(float(amb.mean()), 5), "grad_max_rel_err": gerr,
+              "grad_ok": gerr <= 1e-3}
+    log(f"[bench] parity {parity}")
+
+    # ---------------------------------------------------------------- per-mesh plain form
+    per_mesh = None
+    if not args.no_per_mesh:
+        one_ws = None
+        outs, gvs1, calls = [], [], []
+        for m in range(N):
+            a0, cnt = int(b.first_idx[m]), int(b.num_faces[m])
+            fm = f[a0:a0 + cnt].contiguous()
+            o1 = empty_fragments(1, H, W, K, dev)
+            calls.append((fm, o1, torch.zeros(1, dtype=torch.int64, device=dev),
+                          torch.full((1,), cnt, dtype=torch.int64, device=dev)))
+        need = max(_lib.rast_workspace_size(1, H, W, c[0].shape[0], 0, 0) for c in calls)
+        one_ws = _lib.alloc_workspace(need, dev)
+        gvm = torch.empty_like(v)
+
+        def per_mesh_step():
+            for fm, o1, z0, c1 in calls:
+                _lib.rasterize_meshes_fwd(v, fm, z0, c1, H, W, b.blur_radius, K, 0, 0, 0, o1.pix_to_face, o1.zbuf,
+                                          o1.bary, o1.dists, one_ws)
+                _lib.rasterize_meshes_bwd(v, fm, 1, H, W, K, o1.pix_to_face, gz[:1], gb[:1], gd[:1], gvm, one_ws)
+
+        per_mesh_step()
+        torch.cuda.synchronize()
+        reps = 2
+        a, c = ev.create(), ev.create()
+        ev.record(a, stream)
+        for _ in range(reps):
+            per_mesh_step()
+        ev.record(c, stream)
+        pm_ms = ev.elapsed(a, c) / reps
+        per_mesh = {"ms_per_batch": round(pm_ms, 4), "value": round(S / (pm_ms * 1e-3) / 1e6, 2),
+                    "form": "one single-pass fwd+bwd call per mesh (no bins, no graph)",
+                    "speedup_batched": round(pm_ms / ms_step, 2)}
+        log(f"[bench] per-mesh plain {pm_ms:.3f} ms/batch")
+
+    # ---------------------------------------------------------------- CPU baseline (oracle)
+    cpu = None
+    if not args.no_cpu_baseline:
+        per_px = t_spot / max(1, pix.size)
+        P = int(min(N * H * W, max(256, args.cpu_seconds / max(per_px, 1e-9))))
+        pixc = np.sort(rng.choice(N * H * W, size=P, replace=False))
+        tq = time.perf_counter()
+        oc = oracle.rasterize(b.verts, b.faces, b.first_idx, b.num_faces, (H, W), b.blur_radius, K, pixels=pixc,
+                              nthreads=nthr)
+        t_f = time.perf_counter() - tq
+        sel = lambda a: a.reshape((N * H * W,) + a.shape[3:])[pixc]
+        gzs, gbs, gds = sel(gz_np), sel(gb_np), sel(gd_np)
+        tq = time.perf_counter()
+        oracle.backward(b.verts, b.faces, (H, W), oc["p2f"], gzs, gbs, gds, nthreads=nthr, pixels=pixc, N=N)
+        t_b = time.perf_counter() - tq
+        cpu = {"value": round(P * K / (t_f + t_b) / 1e6, 6), "unit": UNIT, "cores": nthr, "kind": "oracle",
+               "sample": f"{P} of {N * H * W} pixels (seeded uniform), FP64 brute force forward over every face "
+                         f"of the pixel's mesh + analytic backward of their slots; fwd {t_f:.2f}s, bwd {t_b:.2f}s"}
+        log(f"[bench] cpu baseline {cpu}")
+
+    res = {
+        "metric": METRIC, "value": round(S / (ms_step * 1e-3) / 1e6, 2), "unit": UNIT, "n_gpus": 1,
+        "steps": n, "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"cfg{args.config}: {meshgen.CONFIG_NAMES[args.config]}", "meshes": N,
+                   "image": [H, W], "faces_per_pixel": K, "blur_radius": b.blur_radius, "faces": F, "verts": V,
+                   "bin_size": bs, "max_faces_per_bin": M, "sched": sched, "parallelism": "single GPU"},
+        "slots": S, "slots_valid": S_valid, "step_algorithmic_bytes": step_bytes,
+        "step_hbm_frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "kernels_ms": {"fine": round(fine_ms, 5), "backward": round(bwd_ms, 5)},
+        "roofline": roofline, "cpu_baseline": cpu, "per_mesh": per_mesh, "parity": parity,
+    }
+    print(json.dumps(res), flush=True)
+    if not (parity["pix_to_face_ok"] and parity["values_ok"] and parity["grad_ok"]):
+        sys.exit(3)
+
+
+if __name__ == "__main__":
+    main()

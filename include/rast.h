@@ -1,0 +1,182 @@
+/*
+ * rast.h -- C ABI of the MI355X (gfx950) batched differentiable mesh rasterizer.
+ *
+ * The operation (paper, Section 3.2, "Rasterizer"): for every pixel of every
+ * image in a heterogeneous batch of triangle meshes, find the K faces nearest
+ * along z among the faces that cover the pixel or lie within a blur radius of
+ * it, and return "Fragment data" for them: face id, barycentric coordinates of
+ * the pixel in the face, z, and the signed xy distance from the pixel to the
+ * face.  The forward works in two passes, image tiles first and pixels second
+ * (same section); the backward turns gradients of the fragments into gradients
+ * of the vertex positions, re-using the stored face ids rather than searching
+ * again (same section).  The silhouette blend of Algorithm 1 (same section) is
+ * exported beside it.
+ *
+ * Conventions shared by every entry point:
+ *  - All array arguments are DEVICE pointers to memory the caller owns.  The
+ *    library never allocates, frees or synchronises inside these calls (except
+ *    rast_query_status, which says so) and launches only on `stream` (a
+ *    hipStream_t; NULL = the default stream), so the calls can be captured in a
+ *    HIP graph.  Host-side validation happens before any launch.
+ *  - Return value: RAST_OK (0) or a negative rast_status.  A negative return
+ *    means nothing was launched, except RAST_EHIP (a launch itself failed).
+ *  - Conditions only the device can see (a bin overflow, inconsistent mesh
+ *    ranges) are written to a sticky status word inside the workspace and
+ *    read back with rast_query_status; the outputs of such a call are invalid.
+ *  - Calls that share a workspace must not overlap; calls with distinct
+ *    workspaces may run concurrently.
+ *
+ * Geometry conventions:
+ *  - verts_packed (V,3) float32, view space: x, y in normalised device
+ *    coordinates, z the depth (faces count only where their interpolated
+ *    z >= 0).  Pixel (r, c) of an H x W image has its centre at
+ *    x = 1 - (2c+1)/W, y = 1 - (2r+1)/H (+x to the left, +y up, row 0 at the
+ *    top).
+ *  - faces_packed (F,3) int32: global (packed) vertex ids.
+ *  - mesh n owns faces [mesh_to_face_first_idx[n], ... + num_faces_per_mesh[n])
+ *    (int64, device); ranges must be ascending and non-overlapping.  Image n
+ *    is rendered from mesh n only.
+ *  - Barycentrics are raw screen-space ones (no clipping, no perspective
+ *    correction); z is interpolated with them.  dists is the squared xy
+ *    distance to the nearest point of the triangle boundary, negative when the
+ *    pixel is strictly inside (all barycentrics > 0), positive otherwise.
+ *    blur_radius is in the same squared-NDC units: an outside face counts iff
+ *    its squared distance is < blur_radius.  Faces with abs(2 * signed area)
+ *    < 1e-8 never count.
+ *  - Slots are ordered by ascending z, ties by ascending face id.  Empty slots
+ *    hold pix_to_face = -1 and -1 in zbuf, all three bary and dists.
+ */
+#ifndef RAST_H
+#define RAST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum rast_status {
+    RAST_OK = 0,
+    RAST_EINVAL = -1,      /* an argument is out of range or a required pointer is NULL */
+    RAST_EWORKSPACE = -2,  /* workspace NULL, too small or not 256-byte aligned */
+    RAST_EHIP = -3,        /* a HIP launch failed */
+    RAST_EOVERFLOW = -4,   /* device: a bin received more than max_faces_per_bin faces */
+    RAST_EMESH = -5,       /* device: mesh face ranges out of [0, F) or not ascending */
+};
+
+#define RAST_KMAX 64     /* largest faces_per_pixel */
+#define RAST_TILE 8      /* the forward's work unit is an 8x8 pixel tile */
+#define RAST_MAX_BIN 512 /* largest bin_size */
+
+/* Scheduling flags for rasterize_meshes_fwd. */
+#define RAST_SCHED_GRID 0       /* one workgroup per tile, hardware dispatch order */
+#define RAST_SCHED_PERSISTENT 1 /* device-sized grid pulling tiles, most-loaded bins first */
+
+/*
+ * Bytes of workspace needed by rasterize_meshes_fwd / _bwd / rast_bin_count
+ * for these sizes.  bin_size 0 selects the single-pass form (every pixel
+ * against every face of its mesh).  bin_size > 0 must be a multiple of
+ * RAST_TILE, at most RAST_MAX_BIN; max_faces_per_bin (M) > 0 then sizes the
+ * per-bin face lists (N * ceil(H/bs) * ceil(W/bs) * M int32).
+ */
+int rast_workspace_size(int N, int H, int W, int64_t F, int bin_size, int max_faces_per_bin,
+                        size_t* bytes_out);
+
+/*
+ * Forward (paper, Section 3.2: two passes, tiles then pixels, per-pixel
+ * K-nearest selection, Fragment outputs).
+ *   verts_packed (V,3) f32, faces_packed (F,3) i32, mesh_to_face_first_idx (N) i64,
+ *   num_faces_per_mesh (N) i64 -- inputs, see the conventions above.
+ *   N, H, W > 0; blur_radius >= 0 (squared NDC); faces_per_pixel K in [1, RAST_KMAX];
+ *   bin_size 0 or a multiple of RAST_TILE <= RAST_MAX_BIN; max_faces_per_bin > 0 if bin_size > 0;
+ *   sched: RAST_SCHED_GRID or RAST_SCHED_PERSISTENT (ignored when bin_size == 0).
+ *   Outputs, row-major, fully overwritten:
+ *     pix_to_face (N,H,W,K) i32 packed face id or -1
+ *     zbuf (N,H,W,K) f32, bary (N,H,W,K,3) f32, dists (N,H,W,K) f32
+ *   workspace: device memory of at least rast_workspace_size() bytes, 256-byte aligned.
+ * An overflowing bin makes the call's outputs invalid and sets RAST_EOVERFLOW
+ * in the workspace status (it is never a silent truncation).
+ */
+int rasterize_meshes_fwd(const float* verts_packed, int64_t V, const int32_t* faces_packed, int64_t F,
+                         const int64_t* mesh_to_face_first_idx, const int64_t* num_faces_per_mesh,
+                         int N, int H, int W, float blur_radius, int faces_per_pixel, int bin_size,
+                         int max_faces_per_bin, int sched, int32_t* pix_to_face, float* zbuf, float* bary,
+                         float* dists, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Backward (paper, Section 3.2: gradients with respect to the inputs, from the
+ * stored face ids).  For L = <grad_zbuf, zbuf> + <grad_bary, bary> +
+ * <grad_dists, dists> over the slots with pix_to_face >= 0, writes dL/dverts
+ * into grad_verts (V,3) f32, which is overwritten.  Each slot's barycentrics,
+ * z and nearest edge are recomputed from the vertices; the choice of faces is
+ * held fixed.  grad_zbuf (N,H,W,K), grad_bary (N,H,W,K,3) and grad_dists
+ * (N,H,W,K) may each be NULL (= zero).  The result accumulates with float
+ * atomics, so its last bits may differ between runs.
+ * workspace: at least rast_workspace_size(N, H, W, F, 0, 0) bytes.
+ */
+int rasterize_meshes_bwd(const float* verts_packed, int64_t V, const int32_t* faces_packed, int64_t F,
+                         int N, int H, int W, int faces_per_pixel, const int32_t* pix_to_face,
+                         const float* grad_zbuf, const float* grad_bary, const float* grad_dists,
+                         float* grad_verts, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Coarse pass only, counting: fills the workspace status with the largest
+ * number of faces any bin of this bin_size receives (read it with
+ * rast_query_status).  Used to size max_faces_per_bin exactly.  Needs
+ * rast_workspace_size(N, H, W, F, bin_size, 1) bytes.
+ */
+int rast_bin_count(const float* verts_packed, int64_t V, const int32_t* faces_packed, int64_t F,
+                   const int64_t* mesh_to_face_first_idx, const int64_t* num_faces_per_mesh,
+                   int N, int H, int W, float blur_radius, int bin_size,
+                   void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Synchronises `stream`, then reads the sticky status of the last call that
+ * used this workspace: *status = RAST_OK, RAST_EOVERFLOW or RAST_EMESH;
+ * *max_bin_count (may be NULL) = the largest bin count seen by the last
+ * binned forward or rast_bin_count.
+ */
+int rast_query_status(const void* workspace, int* status, int* max_bin_count, void* stream);
+
+/* Static text for a status code. */
+const char* rast_status_string(int status);
+
+/*
+ * Instrumentation (not part of the method): on the calling host thread, make
+ * every later rasterize_meshes_fwd (kernel = RAST_KERNEL_FINE) or
+ * rasterize_meshes_bwd (kernel = RAST_KERNEL_BWD) call record `begin` and
+ * `end` (hipEvent_t created by the caller) on its stream immediately before
+ * and after the launch of its per-pixel kernel, so the caller can time that
+ * kernel alone.  Pass NULL for both to switch it off.  Do not leave events set
+ * while capturing a graph.  Returns RAST_EINVAL for an unknown kernel or a
+ * single NULL.
+ */
+#define RAST_KERNEL_FINE 0
+#define RAST_KERNEL_BWD 1
+int rast_set_kernel_events(int kernel, void* begin, void* end);
+
+/*
+ * Silhouette blend (paper, Section 3.2, Algorithm 1): per pixel,
+ * prob_k = sigmoid(-dists_k / sigma) for slots with pix_to_face >= 0 (0 for
+ * empty slots) and alpha = 1 - prod_k (1 - prob_k).
+ *   pix_to_face, dists: (P,K) with P = N*H*W pixels; alpha: (P) f32 output.
+ *   sigma > 0; K in [1, RAST_KMAX].
+ */
+int silhouette_blend_fwd(const int32_t* pix_to_face, const float* dists, int64_t P, int K, float sigma,
+                         float* alpha, void* stream);
+
+/*
+ * Backward of silhouette_blend_fwd: grad_dists (P,K) = grad_alpha * d alpha / d dists,
+ * d alpha / d dists_k = -(1/sigma) prob_k (1 - prob_k) prod_{j != k} (1 - prob_j),
+ * formed with prefix and suffix products (no division), 0 for empty slots.
+ * grad_dists is overwritten.
+ */
+int silhouette_blend_bwd(const int32_t* pix_to_face, const float* dists, const float* grad_alpha, int64_t P,
+                         int K, float sigma, float* grad_dists, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAST_H */

@@ -50,7 +50,7 @@ def _load():
     lib.oracle_rasterize.restype = ci
     lib.oracle_fragments_fixed.argtypes = [P, P, ci, ci, ci, ci, P, P, P, P, P, ci]
     lib.oracle_fragments_fixed.restype = ci
-    lib.oracle_backward.argtypes = [P, i64, P, ci, ci, ci, ci, P, P, P, P, P, ci]
+    lib.oracle_backward.argtypes = [P, i64, P, ci, ci, ci, ci, P, i64, P, P, P, P, P, ci]
     lib.oracle_backward.restype = ci
     lib.oracle_max_threads.argtypes = []
     lib.oracle_max_threads.restype = ci
@@ -133,21 +133,28 @@ def fragments_fixed(verts, faces, image_size, p2f, nthreads: Optional[int] = Non
 
 
 def backward(verts, faces, image_size, p2f, grad_zbuf=None, grad_bary=None, grad_dists=None,
-             nthreads: Optional[int] = None):
+             nthreads: Optional[int] = None, pixels=None, N: Optional[int] = None):
     """Analytic FP64 dL/dverts (V,3) for L = <gz,zbuf> + <gb,bary> + <gd,dists>
-    over the slots of p2f (N,H,W,K)."""
+    over the slots of p2f (N,H,W,K).  With ``pixels`` (linear pixel ids),
+    p2f and the grads are (npix,K[,3]) rows of those pixels instead; N is
+    then the number of images."""
     lib = _load()
     H, W = image_size
     p = _i64(p2f)
-    N, K = p.shape[0], p.shape[-1]
+    K = p.shape[-1]
+    pix = None if pixels is None else _i64(pixels)
+    if pix is None:
+        N = p.shape[0]
+    elif N is None:
+        N = int(pix.max()) // (H * W) + 1 if pix.size else 1
     v = _f64(verts)
     f = _i64(faces)
     gz = None if grad_zbuf is None else _f64(grad_zbuf)
     gb = None if grad_bary is None else _f64(grad_bary)
     gd = None if grad_dists is None else _f64(grad_dists)
     out = np.empty(v.shape, np.float64)
-    rc = lib.oracle_backward(_ptr(v), v.shape[0], _ptr(f), N, H, W, K, _ptr(p), _ptr(gz), _ptr(gb), _ptr(gd),
-                             _ptr(out), nthreads or default_threads())
+    rc = lib.oracle_backward(_ptr(v), v.shape[0], _ptr(f), N, H, W, K, _ptr(pix), 0 if pix is None else pix.shape[0],
+                             _ptr(p), _ptr(gz), _ptr(gb), _ptr(gd), _ptr(out), nthreads or default_threads())
     if rc != 0:
         raise MemoryError("oracle_backward failed")
     return out

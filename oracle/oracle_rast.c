@@ -325,10 +325,13 @@ int oracle_fragments_fixed(const double* verts, const int64_t* faces, int N, int
  *   d d2/d s0 = -2 (1-u) (p-q),  d d2/d t = -2 u (p-q)   (also at clamped u)
  */
 int oracle_backward(const double* verts, int64_t V, const int64_t* faces, int N, int H, int W, int K,
+                    const int64_t* pix, int64_t npix,
                     const int64_t* p2f, const double* gz, const double* gb, const double* gd,
                     double* grad_verts, int nthreads) {
     int nt = nthreads > 0 ? nthreads : 1;
-    int64_t S = (int64_t)N * H * W * K;
+    /* pix == NULL: slots cover every pixel in order, S = N*H*W*K; otherwise
+     * slot s belongs to linear pixel pix[s / K] and S = npix*K */
+    int64_t S = pix ? npix * K : (int64_t)N * H * W * K;
     double* part = (double*)calloc((size_t)nt * (size_t)V * 3, sizeof(double));
     if (!part && V > 0) return -1;
 #pragma omp parallel num_threads(nt)
@@ -347,7 +350,7 @@ int oracle_backward(const double* verts, int64_t V, const int64_t* faces, int N,
             double gb1 = gb ? gb[3 * s + 1] : 0.0;
             double gb2 = gb ? gb[3 * s + 2] : 0.0;
             double gds = gd ? gd[s] : 0.0;
-            int64_t lin = s / K;
+            int64_t lin = pix ? pix[s / K] : s / K;
             int64_t rem = lin % ((int64_t)H * W);
             double px, py;
             pixel_center(rem / W, rem % W, H, W, &px, &py);

@@ -1,0 +1,208 @@
+"""ctypes binding of librast.so (the C ABI in include/rast.h).
+
+Argument marshalling only: every step of the rasterizer runs in the HIP
+library.  There is no fallback of any kind -- if the library is missing or
+cannot be loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librast.so")
+
+RAST_OK = 0
+RAST_EINVAL = -1
+RAST_EWORKSPACE = -2
+RAST_EHIP = -3
+RAST_EOVERFLOW = -4
+RAST_EMESH = -5
+RAST_KMAX = 64
+RAST_TILE = 8
+RAST_MAX_BIN = 512
+RAST_SCHED_GRID = 0
+RAST_SCHED_PERSISTENT = 1
+
+_lock = threading.Lock()
+_lib = None
+
+
+class RastError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn}: {msg} (status {code})")
+        self.code = code
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is missing; build it with "
+                               "`python -m paper_2007_08501_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        ci = ctypes.c_int
+        cf = ctypes.c_float
+        sz = ctypes.c_size_t
+        L.rast_workspace_size.argtypes = [ci, ci, ci, i64, ci, ci, ctypes.POINTER(sz)]
+        L.rasterize_meshes_fwd.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, cf, ci, ci, ci, ci, P, P, P, P, P, sz, P]
+        L.rasterize_meshes_bwd.argtypes = [P, i64, P, i64, ci, ci, ci, ci, P, P, P, P, P, P, sz, P]
+        L.rast_bin_count.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, cf, ci, P, sz, P]
+        L.rast_query_status.argtypes = [P, ctypes.POINTER(ci), ctypes.POINTER(ci), P]
+        L.rast_status_string.argtypes = [ci]
+        L.rast_status_string.restype = ctypes.c_char_p
+        L.rast_set_kernel_events.argtypes = [ci, P, P]
+        L.silhouette_blend_fwd.argtypes = [P, P, i64, ci, cf, P, P]
+        L.silhouette_blend_bwd.argtypes = [P, P, P, i64, ci, cf, P, P]
+        for fn in ("rast_workspace_size", "rasterize_meshes_fwd", "rasterize_meshes_bwd", "rast_bin_count",
+                   "rast_query_status", "silhouette_blend_fwd", "silhouette_blend_bwd", "rast_set_kernel_events"):
+            getattr(L, fn).restype = ci
+        _lib = L
+        return L
+
+
+EXPORTS = ("rast_workspace_size", "rasterize_meshes_fwd", "rasterize_meshes_bwd", "rast_bin_count",
+           "rast_query_status", "rast_status_string", "silhouette_blend_fwd", "silhouette_blend_bwd",
+           "rast_set_kernel_events")
+RAST_KERNEL_FINE = 0
+RAST_KERNEL_BWD = 1
+
+
+def status_string(code: int) -> str:
+    return lib().rast_status_string(int(code)).decode()
+
+
+def _check(fn: str, rc: int):
+    if rc != RAST_OK:
+        raise RastError(fn, rc, status_string(rc))
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _require(t, name, dtype, device=None):
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+
+
+def rast_workspace_size(N, H, W, F, bin_size, max_faces_per_bin) -> int:
+    out = ctypes.c_size_t(0)
+    _check("rast_workspace_size",
+           lib().rast_workspace_size(int(N), int(H), int(W), int(F), int(bin_size), int(max_faces_per_bin or 0),
+                                     ctypes.byref(out)))
+    return int(out.value)
+
+
+def alloc_workspace(nbytes: int, device) -> torch.Tensor:
+    """Device bytes for a workspace (torch allocations are 256-byte aligned)."""
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def rasterize_meshes_fwd(verts, faces, first_idx, num_faces, H, W, blur_radius, K, bin_size, max_faces_per_bin,
+                         sched, pix_to_face, zbuf, bary, dists, workspace):
+    dev = verts.device
+    _require(verts, "verts", torch.float32, dev)
+    _require(faces, "faces", torch.int32, dev)
+    _require(first_idx, "mesh_to_face_first_idx", torch.int64, dev)
+    _require(num_faces, "num_faces_per_mesh", torch.int64, dev)
+    for t, n, d in ((pix_to_face, "pix_to_face", torch.int32), (zbuf, "zbuf", torch.float32),
+                    (bary, "bary", torch.float32), (dists, "dists", torch.float32), (workspace, "workspace", torch.uint8)):
+        _require(t, n, d, dev)
+    N = first_idx.shape[0]
+    rc = lib().rasterize_meshes_fwd(_p(verts), verts.shape[0], _p(faces), faces.shape[0], _p(first_idx),
+                                    _p(num_faces), int(N), int(H), int(W), float(blur_radius), int(K), int(bin_size),
+                                    int(max_faces_per_bin or 0), int(sched), _p(pix_to_face), _p(zbuf), _p(bary),
+                                    _p(dists), _p(workspace), workspace.numel(), _stream(dev))
+    _check("rasterize_meshes_fwd", rc)
+
+
+def rasterize_meshes_bwd(verts, faces, N, H, W, K, pix_to_face, grad_zbuf, grad_bary, grad_dists, grad_verts,
+                         workspace):
+    dev = verts.device
+    _require(verts, "verts", torch.float32, dev)
+    _require(faces, "faces", torch.int32, dev)
+    _require(pix_to_face, "pix_to_face", torch.int32, dev)
+    for t, n in ((grad_zbuf, "grad_zbuf"), (grad_bary, "grad_bary"), (grad_dists, "grad_dists"),
+                 (grad_verts, "grad_verts")):
+        _require(t, n, torch.float32, dev)
+    _require(workspace, "workspace", torch.uint8, dev)
+    rc = lib().rasterize_meshes_bwd(_p(verts), verts.shape[0], _p(faces), faces.shape[0], int(N), int(H), int(W),
+                                    int(K), _p(pix_to_face), _p(grad_zbuf), _p(grad_bary), _p(grad_dists),
+                                    _p(grad_verts), _p(workspace), workspace.numel(), _stream(dev))
+    _check("rasterize_meshes_bwd", rc)
+
+
+def rast_bin_count(verts, faces, first_idx, num_faces, H, W, blur_radius, bin_size, workspace):
+    dev = verts.device
+    _require(verts, "verts", torch.float32, dev)
+    _require(faces, "faces", torch.int32, dev)
+    _require(first_idx, "mesh_to_face_first_idx", torch.int64, dev)
+    _require(num_faces, "num_faces_per_mesh", torch.int64, dev)
+    _require(workspace, "workspace", torch.uint8, dev)
+    rc = lib().rast_bin_count(_p(verts), verts.shape[0], _p(faces), faces.shape[0], _p(first_idx), _p(num_faces),
+                              int(first_idx.shape[0]), int(H), int(W), float(blur_radius), int(bin_size),
+                              _p(workspace), workspace.numel(), _stream(dev))
+    _check("rast_bin_count", rc)
+
+
+def rast_query_status(workspace):
+    """(status, max_bin_count) of the last call on this workspace; synchronises the stream."""
+    st = ctypes.c_int(0)
+    mx = ctypes.c_int(0)
+    _check("rast_query_status", lib().rast_query_status(_p(workspace), ctypes.byref(st), ctypes.byref(mx),
+                                                         _stream(workspace.device)))
+    return int(st.value), int(mx.value)
+
+
+def silhouette_blend_fwd(pix_to_face, dists, sigma, alpha):
+    dev = dists.device
+    _require(pix_to_face, "pix_to_face", torch.int32, dev)
+    _require(dists, "dists", torch.float32, dev)
+    _require(alpha, "alpha", torch.float32, dev)
+    K = dists.shape[-1]
+    P = dists.numel() // K
+    _check("silhouette_blend_fwd",
+           lib().silhouette_blend_fwd(_p(pix_to_face), _p(dists), P, int(K), float(sigma), _p(alpha), _stream(dev)))
+
+
+def silhouette_blend_bwd(pix_to_face, dists, grad_alpha, sigma, grad_dists):
+    dev = dists.device
+    _require(pix_to_face, "pix_to_face", torch.int32, dev)
+    _require(dists, "dists", torch.float32, dev)
+    _require(grad_alpha, "grad_alpha", torch.float32, dev)
+    _require(grad_dists, "grad_dists", torch.float32, dev)
+    K = dists.shape[-1]
+    P = dists.numel() // K
+    _check("silhouette_blend_bwd",
+           lib().silhouette_blend_bwd(_p(pix_to_face), _p(dists), _p(grad_alpha), P, int(K), float(sigma),
+                                      _p(grad_dists), _stream(dev)))
+
+
+def rast_set_kernel_events(kernel: int, begin, end):
+    """begin/end: raw hipEvent_t handles (ints) or None to switch off."""
+    b = None if begin is None else ctypes.c_void_p(begin)
+    e = None if end is None else ctypes.c_void_p(end)
+    _check("rast_set_kernel_events", lib().rast_set_kernel_events(int(kernel), b, e))

@@ -1,0 +1,146 @@
+"""Autotuner for the forward's bin size, bin capacity and scheduler.
+
+For each candidate bin size the counting pass gives the exact largest bin
+count, which sizes max_faces_per_bin (rounded up to 32); each candidate
+(bin size, scheduler) is then timed forward+backward with HIP events on the
+current stream, and the fastest is cached per device and problem signature
+(image size, K, blur, face count, spread of faces per mesh).  The
+single-pass form (bin_size 0) is a candidate when its work is small.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from dataclasses import asdict, dataclass
+from typing import Dict, Iterable, Optional, Tuple
+
+import torch
+
+from . import _lib
+from .raster import count_max_faces_per_bin, empty_fragments, forward_into, round_up, workspace
+
+DEFAULT_BIN_SIZES = (8, 16, 24, 32, 48, 64)
+
+
+@dataclass
+class Choice:
+    bin_size: int
+    max_faces_per_bin: int
+    sched: int
+    ms: float
+
+
+_cache: Dict[str, Choice] = {}
+
+
+def _cache_path() -> Optional[str]:
+    return os.environ.get("RAST_AUTOTUNE_CACHE")
+
+
+def _load_file():
+    p = _cache_path()
+    if p and os.path.exists(p):
+        try:
+            with open(p) as fh:
+                for k, v in json.load(fh).items():
+                    _cache.setdefault(k, Choice(**v))
+        except (OSError, ValueError, TypeError):
+            pass
+
+
+def _save_file():
+    p = _cache_path()
+    if p:
+        tmp = p + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump({k: asdict(v) for k, v in _cache.items()}, fh, indent=1)
+        os.replace(tmp, p)
+
+
+def signature(verts, faces, first_idx, num_faces, H, W, blur, K) -> str:
+    dev = torch.cuda.get_device_name(verts.device)
+    nf = num_faces.detach().to("cpu", torch.float64)
+    mean = float(nf.mean()) if nf.numel() else 0.0
+    spread = float(nf.std()) / mean if nf.numel() > 1 and mean > 0 else 0.0
+    bucket = int(round(math.log2(max(mean, 1.0)) * 2)), int(round(spread * 4))
+    return f"{dev}|N{first_idx.shape[0]}|{H}x{W}|K{K}|b{blur:.3e}|F{faces.shape[0]}|h{bucket[0]}.{bucket[1]}"
+
+
+def _time_candidate(verts, faces, first_idx, num_faces, H, W, blur, K, bs, M, sched, grads, reps) -> float:
+    N = first_idx.shape[0]
+    out = empty_fragments(N, H, W, K, verts.device)
+    ws = workspace(verts.device, _lib.rast_workspace_size(N, H, W, faces.shape[0], bs, M))
+    gv = torch.empty_like(verts)
+    bws = torch.empty(_lib.rast_workspace_size(N, H, W, faces.shape[0], 0, 0), dtype=torch.uint8,
+                      device=verts.device)
+
+    def step():
+        forward_into(verts, faces, first_idx, num_faces, H, W, blur, K, bs, M, sched, out, ws)
+        if grads is not None:
+            _lib.rasterize_meshes_bwd(verts, faces, N, H, W, K, out.pix_to_face, grads[0], grads[1], grads[2], gv,
+                                      bws)
+
+    step()
+    st, _ = _lib.rast_query_status(ws)
+    if st != _lib.RAST_OK:
+        return float("inf")
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        step()
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    times.sort()
+    return times[len(times) // 2]
+
+
+def autotune(verts, faces, first_idx, num_faces, H, W, blur, K, bin_sizes: Iterable[int] = DEFAULT_BIN_SIZES,
+             scheds: Tuple[int, ...] = (_lib.RAST_SCHED_GRID, _lib.RAST_SCHED_PERSISTENT), backward: bool = True,
+             reps: int = 5, include_single_pass: Optional[bool] = None, max_list_bytes: int = 1 << 31,
+             force: bool = False) -> Choice:
+    """Pick (bin_size, max_faces_per_bin, sched) for this problem; cached."""
+    if not _cache:
+        _load_file()
+    key = signature(verts, faces, first_idx, num_faces, H, W, blur, K) + ("|bwd" if backward else "")
+    if not force and key in _cache:
+        return _cache[key]
+    N = first_idx.shape[0]
+    grads = None
+    if backward:
+        g = torch.Generator(device=verts.device)
+        g.manual_seed(0)
+        shp = (N, H, W, K)
+        grads = (torch.randn(shp, device=verts.device, generator=g),
+                 torch.randn(shp + (3,), device=verts.device, generator=g),
+                 torch.randn(shp, device=verts.device, generator=g))
+    if include_single_pass is None:
+        # every pixel against every face of its mesh: affordable only when small
+        work = float(H * W) * float(faces.shape[0])
+        include_single_pass = work <= 2e9
+    best = None
+    cands = []
+    if include_single_pass:
+        cands.append((0, 0, _lib.RAST_SCHED_GRID))
+    for bs in bin_sizes:
+        if bs > max(H, W) * 2 or bs % _lib.RAST_TILE:
+            continue
+        mx = count_max_faces_per_bin(verts, faces, first_idx, num_faces, H, W, blur, bs)
+        M = round_up(mx, 32)
+        nbins = N * ((H + bs - 1) // bs) * ((W + bs - 1) // bs)
+        if nbins * M * 4 > max_list_bytes:
+            continue
+        for sc in scheds:
+            cands.append((bs, M, sc))
+    for bs, M, sc in cands:
+        ms = _time_candidate(verts, faces, first_idx, num_faces, H, W, blur, K, bs, M, sc, grads, reps)
+        if best is None or ms < best.ms:
+            best = Choice(bs, M, sc, ms)
+    if best is None:
+        raise RuntimeError("autotune found no feasible configuration")
+    _cache[key] = best
+    _save_file()
+    return best

@@ -1,0 +1,250 @@
+// api.hip -- the library's C ABI (declared in include/rast.h): argument
+// validation on the host, workspace layout, and the launch sequence of each
+// entry point on the caller's stream.  No allocation, no synchronisation
+// (except rast_query_status).
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/rast.h"
+#include "device.hpp"
+#include "launch.hpp"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxDevices = 64;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t hdr, recs, counts, lists, order, hist, total;
+    int nby, nbx, tiles_x, tiles_y;
+    int64_t nbins;
+};
+
+// Workspace layout; returns false if a size does not fit in size_t.
+bool make_layout(int N, int H, int W, int64_t F, int bs, int M, Layout* L) {
+    const size_t big = (size_t)1 << 62;
+    size_t off = 0;
+    L->hdr = off;
+    off += kAlign;
+    L->recs = off;
+    if ((size_t)F > big / sizeof(rast::FaceRec)) return false;
+    off = align_up(off + (size_t)F * sizeof(rast::FaceRec));
+    L->tiles_x = (W + rast::kTile - 1) / rast::kTile;
+    L->tiles_y = (H + rast::kTile - 1) / rast::kTile;
+    L->nby = L->nbx = 0;
+    L->nbins = 0;
+    L->counts = L->lists = L->order = L->hist = off;
+    if (bs > 0) {
+        L->nby = (H + bs - 1) / bs;
+        L->nbx = (W + bs - 1) / bs;
+        L->nbins = (int64_t)N * L->nby * L->nbx;
+        L->counts = off;
+        off = align_up(off + (size_t)L->nbins * 4);
+        L->lists = off;
+        size_t ls = (size_t)L->nbins * (size_t)(M > 0 ? M : 0);
+        if (ls > big / 4) return false;
+        off = align_up(off + ls * 4);
+        L->order = off;
+        off = align_up(off + (size_t)N * L->tiles_x * L->tiles_y * 4);
+        L->hist = off;
+        off = align_up(off + 64 * 4);
+    }
+    L->total = off;
+    return true;
+}
+
+bool bad_dims(int N, int H, int W, int K) {
+    if (N < 1 || H < 1 || W < 1) return true;
+    if (K < 1 || K > RAST_KMAX) return true;
+    // keep N*H*W*K*3 well inside int64 and every per-image pixel index in int32
+    if ((int64_t)H * W > ((int64_t)1 << 30)) return true;
+    if ((int64_t)N * H * W * K > ((int64_t)1 << 40)) return true;
+    return false;
+}
+
+int n_workers_for_current_device() {
+    static int cached[kMaxDevices] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 1024;
+    if (cached[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cached[dev] = cus * 32;
+    }
+    return cached[dev];
+}
+
+inline int hip_rc(hipError_t e) { return e == hipSuccess ? RAST_OK : RAST_EHIP; }
+
+// Instrumentation events of the calling host thread (rast_set_kernel_events).
+struct KernelEvents {
+    hipEvent_t begin[2] = {nullptr, nullptr};
+    hipEvent_t end[2] = {nullptr, nullptr};
+};
+thread_local KernelEvents tl_events;
+
+}  // namespace
+
+extern "C" {
+
+int rast_workspace_size(int N, int H, int W, int64_t F, int bin_size, int max_faces_per_bin, size_t* bytes_out) {
+    if (bytes_out == nullptr) return RAST_EINVAL;
+    if (N < 1 || H < 1 || W < 1 || F < 0 || F > INT32_MAX) return RAST_EINVAL;
+    if (bin_size < 0 || bin_size > RAST_MAX_BIN || (bin_size % RAST_TILE) != 0) return RAST_EINVAL;
+    if (bin_size > 0 && max_faces_per_bin < 1) return RAST_EINVAL;
+    Layout L;
+    if (!make_layout(N, H, W, F, bin_size, max_faces_per_bin, &L)) return RAST_EINVAL;
+    *bytes_out = L.total;
+    return RAST_OK;
+}
+
+int rasterize_meshes_fwd(const float* verts_packed, int64_t V, const int32_t* faces_packed, int64_t F,
+                         const int64_t* mesh_to_face_first_idx, const int64_t* num_faces_per_mesh, int N, int H,
+                         int W, float blur_radius, int faces_per_pixel, int bin_size, int max_faces_per_bin,
+                         int sched, int32_t* pix_to_face, float* zbuf, float* bary, float* dists, void* workspace,
+                         size_t workspace_bytes, void* stream) {
+    if (bad_dims(N, H, W, faces_per_pixel)) return RAST_EINVAL;
+    if (V < 0 || V > INT32_MAX || F < 0 || F > INT32_MAX) return RAST_EINVAL;
+    if ((V > 0 && verts_packed == nullptr) || (F > 0 && faces_packed == nullptr)) return RAST_EINVAL;
+    if (mesh_to_face_first_idx == nullptr || num_faces_per_mesh == nullptr) return RAST_EINVAL;
+    if (pix_to_face == nullptr || zbuf == nullptr || bary == nullptr || dists == nullptr) return RAST_EINVAL;
+    if (!(blur_radius >= 0.0f) || !isfinite(blur_radius)) return RAST_EINVAL;
+    if (bin_size < 0 || bin_size > RAST_MAX_BIN || (bin_size % RAST_TILE) != 0) return RAST_EINVAL;
+    if (bin_size > 0 && max_faces_per_bin < 1) return RAST_EINVAL;
+    if (sched != RAST_SCHED_GRID && sched != RAST_SCHED_PERSISTENT) return RAST_EINVAL;
+    Layout L;
+    if (!make_layout(N, H, W, F, bin_size, max_faces_per_bin, &L)) return RAST_EINVAL;
+    if (workspace == nullptr || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < L.total)
+        return RAST_EWORKSPACE;
+
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    int* hdr = (int*)(ws + L.hdr);
+    rast::FaceRec* recs = (rast::FaceRec*)(ws + L.recs);
+    int n_workers = (sched == RAST_SCHED_PERSISTENT) ? n_workers_for_current_device() : 0;
+
+    hipError_t e = rast::launch_fill_i32(hdr, rast::kHdrWords, 0, s);
+    if (e != hipSuccess) return RAST_EHIP;
+    e = rast::launch_face_setup(verts_packed, V, faces_packed, F, mesh_to_face_first_idx, num_faces_per_mesh, N,
+                                sqrtf(blur_radius), recs, hdr, s);
+    if (e != hipSuccess) return RAST_EHIP;
+    int* counts = nullptr;
+    int* lists = nullptr;
+    if (bin_size > 0) {
+        counts = (int*)(ws + L.counts);
+        lists = (int*)(ws + L.lists);
+        e = rast::launch_binning(recs, F, N, H, W, bin_size, max_faces_per_bin, counts, lists, hdr, s);
+        if (e != hipSuccess) return RAST_EHIP;
+    }
+    e = rast::launch_fine(recs, mesh_to_face_first_idx, num_faces_per_mesh, counts, lists, F, N, H, W,
+                          faces_per_pixel, blur_radius, bin_size, max_faces_per_bin, sched, (int*)(ws + L.order),
+                          (int*)(ws + L.hist), hdr, n_workers, pix_to_face, zbuf, bary, dists, s,
+                          tl_events.begin[RAST_KERNEL_FINE], tl_events.end[RAST_KERNEL_FINE]);
+    return hip_rc(e);
+}
+
+int rasterize_meshes_bwd(const float* verts_packed, int64_t V, const int32_t* faces_packed, int64_t F, int N, int H,
+                         int W, int faces_per_pixel, const int32_t* pix_to_face, const float* grad_zbuf,
+                         const float* grad_bary, const float* grad_dists, float* grad_verts, void* workspace,
+                         size_t workspace_bytes, void* stream) {
+    if (bad_dims(N, H, W, faces_per_pixel)) return RAST_EINVAL;
+    if (V < 0 || V > INT32_MAX || F < 0 || F > INT32_MAX) return RAST_EINVAL;
+    if ((V > 0 && (verts_packed == nullptr || grad_verts == nullptr)) || (F > 0 && faces_packed == nullptr))
+        return RAST_EINVAL;
+    if (pix_to_face == nullptr) return RAST_EINVAL;
+    Layout L;
+    if (!make_layout(N, H, W, F, 0, 0, &L)) return RAST_EINVAL;
+    if (workspace == nullptr || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < L.total)
+        return RAST_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    if (V == 0) return RAST_OK;
+    return hip_rc(rast::launch_backward(verts_packed, V, faces_packed, F, N, H, W, faces_per_pixel, pix_to_face,
+                                        grad_zbuf, grad_bary, grad_dists, grad_verts, s,
+                                        tl_events.begin[RAST_KERNEL_BWD], tl_events.end[RAST_KERNEL_BWD]));
+}
+
+int rast_set_kernel_events(int kernel, void* begin, void* end) {
+    if (kernel != RAST_KERNEL_FINE && kernel != RAST_KERNEL_BWD) return RAST_EINVAL;
+    if ((begin == nullptr) != (end == nullptr)) return RAST_EINVAL;
+    tl_events.begin[kernel] = (hipEvent_t)begin;
+    tl_events.end[kernel] = (hipEvent_t)end;
+    return RAST_OK;
+}
+
+int rast_bin_count(const float* verts_packed, int64_t V, const int32_t* faces_packed, int64_t F,
+                   const int64_t* mesh_to_face_first_idx, const int64_t* num_faces_per_mesh, int N, int H, int W,
+                   float blur_radius, int bin_size, void* workspace, size_t workspace_bytes, void* stream) {
+    if (N < 1 || H < 1 || W < 1) return RAST_EINVAL;
+    if (V < 0 || V > INT32_MAX || F < 0 || F > INT32_MAX) return RAST_EINVAL;
+    if ((V > 0 && verts_packed == nullptr) || (F > 0 && faces_packed == nullptr)) return RAST_EINVAL;
+    if (mesh_to_face_first_idx == nullptr || num_faces_per_mesh == nullptr) return RAST_EINVAL;
+    if (!(blur_radius >= 0.0f) || !isfinite(blur_radius)) return RAST_EINVAL;
+    if (bin_size < RAST_TILE || bin_size > RAST_MAX_BIN || (bin_size % RAST_TILE) != 0) return RAST_EINVAL;
+    Layout L;
+    if (!make_layout(N, H, W, F, bin_size, 1, &L)) return RAST_EINVAL;
+    if (workspace == nullptr || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < L.total)
+        return RAST_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    int* hdr = (int*)(ws + L.hdr);
+    rast::FaceRec* recs = (rast::FaceRec*)(ws + L.recs);
+    hipError_t e = rast::launch_fill_i32(hdr, rast::kHdrWords, 0, s);
+    if (e != hipSuccess) return RAST_EHIP;
+    e = rast::launch_face_setup(verts_packed, V, faces_packed, F, mesh_to_face_first_idx, num_faces_per_mesh, N,
+                                sqrtf(blur_radius), recs, hdr, s);
+    if (e != hipSuccess) return RAST_EHIP;
+    // M = 0: count only, no list writes
+    return hip_rc(rast::launch_binning(recs, F, N, H, W, bin_size, 0, (int*)(ws + L.counts), nullptr, hdr, s));
+}
+
+int rast_query_status(const void* workspace, int* status, int* max_bin_count, void* stream) {
+    if (workspace == nullptr || status == nullptr) return RAST_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int h[2] = {0, 0};
+    if (hipMemcpyAsync(h, workspace, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess) return RAST_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return RAST_EHIP;
+    int st = RAST_OK;
+    if (h[0] & rast::kStatMesh)
+        st = RAST_EMESH;
+    else if (h[0] & rast::kStatOverflow)
+        st = RAST_EOVERFLOW;
+    *status = st;
+    if (max_bin_count) *max_bin_count = h[1];
+    return RAST_OK;
+}
+
+const char* rast_status_string(int status) {
+    switch (status) {
+        case RAST_OK: return "ok";
+        case RAST_EINVAL: return "invalid argument";
+        case RAST_EWORKSPACE: return "workspace missing, too small or misaligned";
+        case RAST_EHIP: return "HIP launch failed";
+        case RAST_EOVERFLOW: return "a bin received more faces than max_faces_per_bin";
+        case RAST_EMESH: return "mesh face ranges or vertex ids out of range";
+        default: return "unknown status";
+    }
+}
+
+int silhouette_blend_fwd(const int32_t* pix_to_face, const float* dists, int64_t P, int K, float sigma, float* alpha,
+                         void* stream) {
+    if (P < 0 || K < 1 || K > RAST_KMAX || !(sigma > 0.0f) || !isfinite(sigma)) return RAST_EINVAL;
+    if (P > 0 && (pix_to_face == nullptr || dists == nullptr || alpha == nullptr)) return RAST_EINVAL;
+    return hip_rc(rast::launch_blend_fwd(pix_to_face, dists, P, K, sigma, alpha, (hipStream_t)stream));
+}
+
+int silhouette_blend_bwd(const int32_t* pix_to_face, const float* dists, const float* grad_alpha, int64_t P, int K,
+                         float sigma, float* grad_dists, void* stream) {
+    if (P < 0 || K < 1 || K > RAST_KMAX || !(sigma > 0.0f) || !isfinite(sigma)) return RAST_EINVAL;
+    if (P > 0 && (pix_to_face == nullptr || dists == nullptr || grad_alpha == nullptr || grad_dists == nullptr))
+        return RAST_EINVAL;
+    return hip_rc(rast::launch_blend_bwd(pix_to_face, dists, grad_alpha, P, K, sigma, grad_dists,
+                                         (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,405 @@
+// kernels_fwd.hip -- forward rasterization kernels for gfx950.
+//
+//   face_setup      one thread per face: mesh id, 64-byte record, padded bbox
+//   bin_faces       one thread per face: append the face to every bin its bbox
+//                   touches (counting only when lists == nullptr)
+//   bin_max         largest bin count -> workspace header, overflow flag
+//   raster_tiles    one wave per 8x8 pixel tile: loop over candidate faces
+//                   (all faces of the tile's mesh, or the tile's bin list),
+//                   cull per tile, test per pixel, keep the K nearest in
+//                   registers, write the fragments
+//
+// The paper's rasterizer (Section 3.2) first works on image tiles to drop
+// faces and then on pixels, keeping per-pixel queues of the K nearest faces;
+// this is that scheme laid out for 64-wide waves.
+#include "device.hpp"
+#include "launch.hpp"
+
+namespace rast {
+
+__global__ void fill_i32_kernel(int* __restrict__ p, int64_t n, int v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void fill_f32_kernel(float* __restrict__ p, int64_t n, float v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+static int grid_for(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+hipError_t launch_fill_i32(int* p, int64_t n, int v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_f32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// Mesh of face f: the last n with first[n] <= f, if f lies in its range.
+__device__ __forceinline__ int find_mesh(const int64_t* __restrict__ first, const int64_t* __restrict__ nf, int N,
+                                         int64_t f) {
+    int lo = 0, hi = N - 1, ans = -1;
+    while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        if (first[mid] <= f) {
+            ans = mid;
+            lo = mid + 1;
+        } else {
+            hi = mid - 1;
+        }
+    }
+    if (ans >= 0 && f < first[ans] + nf[ans]) return ans;
+    return -1;
+}
+
+__global__ void face_setup_kernel(const float* __restrict__ verts, int64_t V, const int32_t* __restrict__ faces,
+                                  int64_t F, const int64_t* __restrict__ first, const int64_t* __restrict__ nf, int N,
+                                  float rb, FaceRec* __restrict__ recs, int* __restrict__ hdr) {
+    int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (first != nullptr && f < N) {
+        // mesh range check: inside [0, F] and ascending without overlap
+        int64_t a = first[f], c = nf[f];
+        bool bad = a < 0 || c < 0 || a + c > F;
+        if (f > 0) bad = bad || a < first[f - 1] + nf[f - 1];
+        if (bad) atomicOr(&hdr[kHdrStatus], kStatMesh);
+    }
+    if (f >= F) return;
+    int mesh = first != nullptr ? find_mesh(first, nf, N, f) : 0;
+    int i0 = faces[3 * f + 0], i1 = faces[3 * f + 1], i2 = faces[3 * f + 2];
+    bool idx_ok = i0 >= 0 && i0 < V && i1 >= 0 && i1 < V && i2 >= 0 && i2 < V;
+    if (!idx_ok) {
+        atomicOr(&hdr[kHdrStatus], kStatMesh);
+        mesh = -1;
+        i0 = i1 = i2 = 0;
+    }
+    if (V == 0) {
+        recs[f] = make_rec(0, 0, 0, 0, 0, 0, 0, 0, 0, rb, -1);
+        return;
+    }
+    const float* a = verts + 3 * (int64_t)i0;
+    const float* b = verts + 3 * (int64_t)i1;
+    const float* c = verts + 3 * (int64_t)i2;
+    recs[f] = make_rec(a[0], a[1], a[2], b[0], b[1], b[2], c[0], c[1], c[2], rb, mesh);
+}
+
+hipError_t launch_face_setup(const float* verts, int64_t V, const int32_t* faces, int64_t F, const int64_t* first,
+                             const int64_t* nf, int N, float rb, FaceRec* recs, int* hdr, hipStream_t s) {
+    int64_t n = F > N ? F : N;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(face_setup_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, verts, V, faces, F,
+                       first, nf, N, rb, recs, hdr);
+    return hipGetLastError();
+}
+
+// Inclusive pixel range [lo, hi] whose centres may fall in [vmin, vmax] along
+// one axis of `size` pixels (centre of pixel i at 1 - (2i+1)/size), grown by
+// one pixel each way to absorb rounding; empty when hi < lo.
+__device__ __forceinline__ void pix_range(float vmin, float vmax, int size, int& lo, int& hi) {
+    float a = ((float)size * (1.0f - vmax) - 1.0f) * 0.5f;
+    float b = ((float)size * (1.0f - vmin) - 1.0f) * 0.5f;
+    a = fminf(fmaxf(a, -2.0f), (float)size + 1.0f);
+    b = fminf(fmaxf(b, -2.0f), (float)size + 1.0f);
+    lo = (int)floorf(a) - 1;
+    hi = (int)ceilf(b) + 1;
+    if (lo < 0) lo = 0;
+    if (hi > size - 1) hi = size - 1;
+}
+
+__global__ void bin_faces_kernel(const FaceRec* __restrict__ recs, int64_t F, int H, int W, int bs, int nby, int nbx,
+                                 int M, int* __restrict__ counts, int* __restrict__ lists) {
+    int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    FaceRec R = recs[f];
+    if (!R.ok()) return;
+    int n = R.mesh();
+    int c0, c1, r0, r1;
+    pix_range(R.q4.x, R.q4.y, W, c0, c1);
+    pix_range(R.q4.z, R.q4.w, H, r0, r1);
+    if (c1 < c0 || r1 < r0) return;
+    int bx0 = c0 / bs, bx1 = c1 / bs, by0 = r0 / bs, by1 = r1 / bs;
+    for (int by = by0; by <= by1; ++by) {
+        for (int bx = bx0; bx <= bx1; ++bx) {
+            int64_t bin = ((int64_t)n * nby + by) * nbx + bx;
+            int pos = atomicAdd(&counts[bin], 1);
+            if (lists != nullptr && pos < M) lists[bin * M + pos] = (int)f;
+        }
+    }
+}
+
+__global__ void bin_max_kernel(const int* __restrict__ counts, int64_t nbins, int M, int* __restrict__ hdr) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int m = 0;
+    for (; i < nbins; i += stride) m = max(m, counts[i]);
+    // wave reduction, then one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&hdr[kHdrMaxCount], m);
+        if (M > 0 && m > M) atomicOr(&hdr[kHdrStatus], kStatOverflow);
+    }
+}
+
+hipError_t launch_binning(const FaceRec* recs, int64_t F, int N, int H, int W, int bs, int M, int* counts, int* lists,
+                          int* hdr, hipStream_t s) {
+    int nby = (H + bs - 1) / bs, nbx = (W + bs - 1) / bs;
+    int64_t nbins = (int64_t)N * nby * nbx;
+    hipError_t e = launch_fill_i32(counts, nbins, 0, s);
+    if (e != hipSuccess) return e;
+    if (F > 0) {
+        hipLaunchKernelGGL(bin_faces_kernel, dim3((unsigned)((F + 255) / 256)), dim3(256), 0, s, recs, F, H, W, bs, nby,
+                           nbx, M, counts, lists);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(bin_max_kernel, dim3(grid_for(nbins, 256)), dim3(256), 0, s, counts, nbins, M, hdr);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fine pass.  One 64-thread workgroup = one wave = one 8x8 tile of image n.
+// Faces come either from the whole mesh (BINNED = false) or from the list of
+// the bin that contains the tile.  Every face is first culled against the
+// tile's extent (a wave-uniform branch) and then tested by each lane for its
+// own pixel; winners go through the register top-K.
+// ---------------------------------------------------------------------------
+struct FineArgs {
+    const FaceRec* recs;
+    const int64_t* first;
+    const int64_t* nf;
+    const int* counts;
+    const int* lists;
+    int64_t F;
+    int N, H, W, K;
+    float blur;
+    int bs, nby, nbx, M;
+    int tiles_x, tiles_y;
+    int32_t* p2f;
+    float* zbuf;
+    float* bary;
+    float* dists;
+};
+
+template <int KB, bool BINNED>
+__device__ __forceinline__ void raster_tile(const FineArgs& a, int n, int tx, int ty) {
+    const int lane = threadIdx.x & 63;
+    const int r = ty * kTile + (lane >> 3);
+    const int c = tx * kTile + (lane & 7);
+    const bool live = (r < a.H) && (c < a.W);
+    const Pix p = make_pix(r, c, a.H, a.W);
+    // extent of the tile's pixel centres (x decreases with c, y with r)
+    const int c_last = min(tx * kTile + kTile - 1, a.W - 1);
+    const int r_last = min(ty * kTile + kTile - 1, a.H - 1);
+    const float tx_hi = pix_x(tx * kTile, a.W), tx_lo = pix_x(c_last, a.W);
+    const float ty_hi = pix_y(ty * kTile, a.H), ty_lo = pix_y(r_last, a.H);
+
+    TopK<KB> top;
+    top.init();
+
+    const int* list = nullptr;
+    int64_t base = 0, cnt = 0;
+    if (BINNED) {
+        int bx = (tx * kTile) / a.bs, by = (ty * kTile) / a.bs;
+        int64_t bin = ((int64_t)n * a.nby + by) * a.nbx + bx;
+        cnt = min(a.counts[bin], a.M);
+        list = a.lists + bin * a.M;
+    } else {
+        int64_t lo = a.first[n], hi = a.first[n] + a.nf[n];
+        lo = lo < 0 ? 0 : lo;
+        hi = hi > a.F ? a.F : hi;
+        base = lo;
+        cnt = hi > lo ? hi - lo : 0;
+    }
+    for (int64_t j = 0; j < cnt; ++j) {
+        const int fid = BINNED ? list[j] : (int)(base + j);
+        const FaceRec R = a.recs[fid];
+        if (R.q4.y < tx_lo || R.q4.x > tx_hi || R.q4.w < ty_lo || R.q4.z > ty_hi) continue;
+        float z;
+        if (live && face_counts(R, p, a.blur, z)) top.insert(make_key(z, fid));
+    }
+    if (!live) return;
+    const int64_t pix = ((int64_t)n * a.H + r) * a.W + c;
+    const int K = a.K;
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        if (k < K) {
+            const int64_t o = pix * K + k;
+            const uint64_t key = top.q[k];
+            if (key != kEmptyKey) {
+                const int fid = (int)(uint32_t)key;
+                const FaceRec R = a.recs[fid];
+                Eval ev;
+                eval_full(R, p, ev);
+                a.p2f[o] = fid;
+                a.zbuf[o] = ev.z;
+                a.bary[3 * o + 0] = ev.w0;
+                a.bary[3 * o + 1] = ev.w1;
+                a.bary[3 * o + 2] = ev.w2;
+                a.dists[o] = ev.inside ? -ev.d2 : ev.d2;
+            } else {
+                a.p2f[o] = -1;
+                a.zbuf[o] = -1.0f;
+                a.bary[3 * o + 0] = -1.0f;
+                a.bary[3 * o + 1] = -1.0f;
+                a.bary[3 * o + 2] = -1.0f;
+                a.dists[o] = -1.0f;
+            }
+        }
+    }
+}
+
+template <int KB, bool BINNED>
+__global__ __launch_bounds__(64) void raster_tiles_kernel(FineArgs a) {
+    raster_tile<KB, BINNED>(a, blockIdx.z, blockIdx.x, blockIdx.y);
+}
+
+// Persistent form: a device-sized grid; each wave pulls the next tile id from
+// a counter in the workspace header.  order[] lists tile ids (image-major
+// linear ids) most-loaded bins first.  Every wave leaves when the counter
+// passes the number of tiles.
+template <int KB>
+__global__ __launch_bounds__(64) void raster_persistent_kernel(FineArgs a, const int* __restrict__ order,
+                                                               int* __restrict__ hdr, int total) {
+    for (;;) {
+        int item = 0;
+        if ((threadIdx.x & 63) == 0) item = atomicAdd(&hdr[kHdrWorkNext], 1);
+        item = __shfl(item, 0);
+        if (item >= total) break;
+        int t = order[item];
+        int per_img = a.tiles_x * a.tiles_y;
+        int n = t / per_img;
+        int rem = t - n * per_img;
+        int ty = rem / a.tiles_x;
+        int tx = rem - ty * a.tiles_x;
+        raster_tile<KB, true>(a, n, tx, ty);
+    }
+}
+
+// order[]: tiles sorted by the count of their bin, descending, using a
+// counting sort over count buckets (64 buckets of width ceil((M+1)/64)).
+__global__ void order_hist_kernel(const int* __restrict__ counts, int N, int tiles_x, int tiles_y, int bs, int nby,
+                                  int nbx, int M, int* __restrict__ hist) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = (int64_t)N * tiles_x * tiles_y;
+    if (t >= total) return;
+    int per_img = tiles_x * tiles_y;
+    int n = (int)(t / per_img);
+    int rem = (int)(t - (int64_t)n * per_img);
+    int ty = rem / tiles_x, tx = rem - ty * tiles_x;
+    int64_t bin = ((int64_t)n * nby + (ty * kTile) / bs) * nbx + (tx * kTile) / bs;
+    int cnt = min(counts[bin], M);
+    int width = (M + 64) / 64;
+    int bucket = 63 - min(cnt / width, 63);  // bucket 0 = heaviest
+    atomicAdd(&hist[bucket], 1);
+}
+
+__global__ void order_scatter_kernel(const int* __restrict__ counts, int N, int tiles_x, int tiles_y, int bs, int nby,
+                                     int nbx, int M, int* __restrict__ hist_off, int* __restrict__ order) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = (int64_t)N * tiles_x * tiles_y;
+    if (t >= total) return;
+    int per_img = tiles_x * tiles_y;
+    int n = (int)(t / per_img);
+    int rem = (int)(t - (int64_t)n * per_img);
+    int ty = rem / tiles_x, tx = rem - ty * tiles_x;
+    int64_t bin = ((int64_t)n * nby + (ty * kTile) / bs) * nbx + (tx * kTile) / bs;
+    int cnt = min(counts[bin], M);
+    int width = (M + 64) / 64;
+    int bucket = 63 - min(cnt / width, 63);
+    int pos = atomicAdd(&hist_off[bucket], 1);
+    order[pos] = (int)t;
+}
+
+// exclusive scan of the 64 bucket sizes, in place; also arms the work counter
+__global__ void order_scan_kernel(int* __restrict__ hist, int* __restrict__ hdr, int total) {
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int i = 0; i < 64; ++i) {
+            int v = hist[i];
+            hist[i] = acc;
+            acc += v;
+        }
+        hdr[kHdrWorkNext] = 0;
+        hdr[kHdrWorkTotal] = total;
+    }
+}
+
+template <int KB>
+static hipError_t launch_fine_k(const FineArgs& a, bool binned, int sched, int* order, int* hist, int* hdr,
+                                int n_workers, hipStream_t s, hipEvent_t eb, hipEvent_t ee) {
+    if (binned && sched == 1) {
+        int total = a.N * a.tiles_x * a.tiles_y;
+        hipError_t e = launch_fill_i32(hist, 64, 0, s);
+        if (e != hipSuccess) return e;
+        unsigned g = (unsigned)((total + 255) / 256);
+        hipLaunchKernelGGL(order_hist_kernel, dim3(g), dim3(256), 0, s, a.counts, a.N, a.tiles_x, a.tiles_y, a.bs,
+                           a.nby, a.nbx, a.M, hist);
+        hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, s, hist, hdr, total);
+        hipLaunchKernelGGL(order_scatter_kernel, dim3(g), dim3(256), 0, s, a.counts, a.N, a.tiles_x, a.tiles_y, a.bs,
+                           a.nby, a.nbx, a.M, hist, order);
+        int workers = n_workers < total ? n_workers : total;
+        if (eb) hipEventRecord(eb, s);
+        hipLaunchKernelGGL(raster_persistent_kernel<KB>, dim3(workers), dim3(64), 0, s, a, order, hdr, total);
+        if (ee) hipEventRecord(ee, s);
+        return hipGetLastError();
+    }
+    dim3 grid(a.tiles_x, a.tiles_y, a.N);
+    if (eb) hipEventRecord(eb, s);
+    if (binned)
+        hipLaunchKernelGGL((raster_tiles_kernel<KB, true>), grid, dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL((raster_tiles_kernel<KB, false>), grid, dim3(64), 0, s, a);
+    if (ee) hipEventRecord(ee, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_fine(const FaceRec* recs, const int64_t* first, const int64_t* nf, const int* counts,
+                       const int* lists, int64_t F, int N, int H, int W, int K, float blur, int bs, int M, int sched,
+                       int* order, int* hist, int* hdr, int n_workers, int32_t* p2f, float* zbuf, float* bary,
+                       float* dists, hipStream_t s, hipEvent_t eb, hipEvent_t ee) {
+    FineArgs a;
+    a.recs = recs;
+    a.first = first;
+    a.nf = nf;
+    a.counts = counts;
+    a.lists = lists;
+    a.F = F;
+    a.N = N;
+    a.H = H;
+    a.W = W;
+    a.K = K;
+    a.blur = blur;
+    a.bs = bs > 0 ? bs : kTile;
+    a.nby = bs > 0 ? (H + bs - 1) / bs : 0;
+    a.nbx = bs > 0 ? (W + bs - 1) / bs : 0;
+    a.M = M;
+    a.tiles_x = (W + kTile - 1) / kTile;
+    a.tiles_y = (H + kTile - 1) / kTile;
+    a.p2f = p2f;
+    a.zbuf = zbuf;
+    a.bary = bary;
+    a.dists = dists;
+    bool binned = bs > 0;
+    if (K <= 1) return launch_fine_k<1>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
+    if (K <= 2) return launch_fine_k<2>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
+    if (K <= 4) return launch_fine_k<4>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
+    if (K <= 8) return launch_fine_k<8>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
+    if (K <= 16) return launch_fine_k<16>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
+    if (K <= 32) return launch_fine_k<32>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
+    if (K <= 50) return launch_fine_k<50>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
+    return launch_fine_k<64>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
+}
+
+}  // namespace rast

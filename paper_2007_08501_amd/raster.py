@@ -1,0 +1,191 @@
+"""PyTorch front end of the HIP rasterizer: autograd Functions over the C ABI.
+
+    frags = rasterize_meshes(verts, faces, first_idx, num_faces, settings)
+    alpha = silhouette_blend(frags.pix_to_face, frags.dists, sigma)
+
+PyTorch provides device memory and the stream; every computation runs in
+librast.so.  Differentiable in ``verts`` (rasterizer) and ``dists`` (blend).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import NamedTuple, Optional, Tuple, Union
+
+import torch
+
+from . import _lib
+
+
+@dataclass
+class RasterSettings:
+    """image_size: int or (H, W).  blur_radius: squared NDC distance.
+    bin_size: 0 = single pass over every face of the mesh; a multiple of 8 =
+    two passes with bins of that many pixels; None = pick with the autotuner.
+    max_faces_per_bin: None = exact value from a counting pass.
+    sched: 0 = grid launch, 1 = persistent most-loaded-first scheduler.
+    check: read the device status after the forward (synchronises) and
+    recover from a bin overflow by recounting when max_faces_per_bin is None.
+    """
+
+    image_size: Union[int, Tuple[int, int]]
+    blur_radius: float = 0.0
+    faces_per_pixel: int = 1
+    bin_size: Optional[int] = None
+    max_faces_per_bin: Optional[int] = None
+    sched: int = _lib.RAST_SCHED_GRID
+    check: bool = True
+
+    @property
+    def hw(self):
+        if isinstance(self.image_size, int):
+            return self.image_size, self.image_size
+        return tuple(self.image_size)
+
+
+class Fragments(NamedTuple):
+    pix_to_face: torch.Tensor  # (N,H,W,K) int32
+    zbuf: torch.Tensor         # (N,H,W,K) f32
+    bary: torch.Tensor         # (N,H,W,K,3) f32
+    dists: torch.Tensor        # (N,H,W,K) f32
+
+
+class BinOverflow(RuntimeError):
+    pass
+
+
+_ws = {}
+
+
+def workspace(device, nbytes: int) -> torch.Tensor:
+    """A per-device scratch buffer of at least nbytes (grown on demand)."""
+    key = torch.device(device).index
+    t = _ws.get(key)
+    if t is None or t.numel() < nbytes:
+        t = _lib.alloc_workspace(int(nbytes * 1.25) + 4096, device)
+        _ws[key] = t
+    return t
+
+
+def count_max_faces_per_bin(verts, faces, first_idx, num_faces, H, W, blur_radius, bin_size) -> int:
+    """Largest bin count for this bin size (runs the counting pass; synchronises)."""
+    N = first_idx.shape[0]
+    ws = workspace(verts.device, _lib.rast_workspace_size(N, H, W, faces.shape[0], bin_size, 1))
+    _lib.rast_bin_count(verts, faces, first_idx, num_faces, H, W, blur_radius, bin_size, ws)
+    st, mx = _lib.rast_query_status(ws)
+    if st != _lib.RAST_OK:
+        raise _lib.RastError("rast_bin_count", st, _lib.status_string(st))
+    return mx
+
+
+def round_up(x: int, m: int) -> int:
+    return max(m, (x + m - 1) // m * m)
+
+
+def forward_into(verts, faces, first_idx, num_faces, H, W, blur_radius, K, bin_size, M, sched, out, ws):
+    """Raw forward into preallocated outputs (no status read)."""
+    _lib.rasterize_meshes_fwd(verts, faces, first_idx, num_faces, H, W, blur_radius, K, bin_size, M, sched,
+                              out.pix_to_face, out.zbuf, out.bary, out.dists, ws)
+
+
+def empty_fragments(N, H, W, K, device) -> Fragments:
+    return Fragments(
+        torch.empty((N, H, W, K), dtype=torch.int32, device=device),
+        torch.empty((N, H, W, K), dtype=torch.float32, device=device),
+        torch.empty((N, H, W, K, 3), dtype=torch.float32, device=device),
+        torch.empty((N, H, W, K), dtype=torch.float32, device=device),
+    )
+
+
+class _RasterizeMeshes(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, verts, faces, first_idx, num_faces, H, W, blur, K, bs, M, sched, check):
+        N = first_idx.shape[0]
+        out = empty_fragments(N, H, W, K, verts.device)
+        vd = verts.detach().contiguous()
+        need = _lib.rast_workspace_size(N, H, W, faces.shape[0], bs, M)
+        ws = workspace(verts.device, need)
+        forward_into(vd, faces, first_idx, num_faces, H, W, blur, K, bs, M, sched, out, ws)
+        if check:
+            st, mx = _lib.rast_query_status(ws)
+            if st == _lib.RAST_EOVERFLOW:
+                raise BinOverflow(f"a bin received {mx} faces > max_faces_per_bin={M}")
+            if st != _lib.RAST_OK:
+                raise _lib.RastError("rasterize_meshes_fwd", st, _lib.status_string(st))
+        ctx.save_for_backward(vd, faces, out.pix_to_face)
+        ctx.mark_non_differentiable(out.pix_to_face)
+        ctx.dims = (N, H, W, K)
+        return out.pix_to_face, out.zbuf, out.bary, out.dists
+
+    @staticmethod
+    def backward(ctx, _g_p2f, g_zbuf, g_bary, g_dists):
+        verts, faces, p2f = ctx.saved_tensors
+        N, H, W, K = ctx.dims
+
+        def prep(g):
+            return None if g is None else g.contiguous().to(torch.float32)
+
+        grad_verts = torch.empty_like(verts)
+        ws = workspace(verts.device, _lib.rast_workspace_size(N, H, W, faces.shape[0], 0, 0))
+        _lib.rasterize_meshes_bwd(verts, faces, N, H, W, K, p2f, prep(g_zbuf), prep(g_bary), prep(g_dists),
+                                  grad_verts, ws)
+        return (grad_verts,) + (None,) * 11
+
+
+def rasterize_meshes(verts, faces, first_idx, num_faces, settings: RasterSettings) -> Fragments:
+    """Fragments of the K nearest faces per pixel for a packed mesh batch.
+
+    verts (V,3) f32 device tensor (may require grad); faces (F,3) int32;
+    first_idx/num_faces (N,) int64 on the same device.
+    """
+    H, W = settings.hw
+    K = int(settings.faces_per_pixel)
+    bs = settings.bin_size
+    M = settings.max_faces_per_bin
+    if faces.dtype != torch.int32:
+        faces = faces.to(torch.int32)
+    faces = faces.contiguous()
+    if bs is None:
+        from .autotune import autotune
+        choice = autotune(verts.detach(), faces, first_idx, num_faces, H, W, settings.blur_radius, K)
+        bs, M, sched = choice.bin_size, choice.max_faces_per_bin, choice.sched
+    else:
+        sched = settings.sched
+    auto_M = bs > 0 and M is None
+    if auto_M:
+        M = round_up(count_max_faces_per_bin(verts.detach(), faces, first_idx, num_faces, H, W,
+                                             settings.blur_radius, bs), 32)
+    try:
+        res = _RasterizeMeshes.apply(verts, faces, first_idx, num_faces, H, W, float(settings.blur_radius), K,
+                                     int(bs), int(M or 0), int(sched), bool(settings.check))
+    except BinOverflow:
+        if not auto_M:
+            raise
+        M = round_up(count_max_faces_per_bin(verts.detach(), faces, first_idx, num_faces, H, W,
+                                             settings.blur_radius, bs), 32)
+        res = _RasterizeMeshes.apply(verts, faces, first_idx, num_faces, H, W, float(settings.blur_radius), K,
+                                     int(bs), int(M), int(sched), bool(settings.check))
+    return Fragments(*res)
+
+
+class _SilhouetteBlend(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, pix_to_face, dists, sigma):
+        d = dists.detach().contiguous()
+        alpha = torch.empty(d.shape[:-1], dtype=torch.float32, device=d.device)
+        _lib.silhouette_blend_fwd(pix_to_face, d, sigma, alpha)
+        ctx.save_for_backward(pix_to_face, d)
+        ctx.sigma = sigma
+        return alpha
+
+    @staticmethod
+    def backward(ctx, grad_alpha):
+        p2f, d = ctx.saved_tensors
+        gd = torch.empty_like(d)
+        _lib.silhouette_blend_bwd(p2f, d, grad_alpha.contiguous().to(torch.float32), ctx.sigma, gd)
+        return None, gd, None
+
+
+def silhouette_blend(pix_to_face, dists, sigma: float):
+    """Algorithm 1 of the paper: alpha = 1 - prod_k (1 - sigmoid(-dists_k / sigma)),
+    with empty slots (pix_to_face == -1) left out.  Differentiable in dists."""
+    return _SilhouetteBlend.apply(pix_to_face.contiguous(), dists, float(sigma))

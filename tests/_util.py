@@ -1,0 +1,149 @@
+"""Helpers shared by the GPU parity tests: run the HIP path through the C ABI
+and compare it with the oracle under the stated tolerances.
+
+Tolerances (fixed by the workload contract and the FP32/FP64 arithmetic):
+  pix_to_face  exact on pixels the oracle does not flag as ambiguous
+  bary         abs(dw_i) <= 1e-5 * max(1, abs(w_i))
+  zbuf         abs(dz)   <= 1e-5 * max(1, sum_i abs(w_i z_i))
+  dists        abs(dd)   <= 1e-5
+  grad_verts   max abs error <= 1e-3 * max abs(reference) and
+               L2 error <= 1e-3 * L2 norm of the reference
+The relative branches exist because an FP32 barycentric of an outside pixel
+near a sliver can be far above 1, where FP32 storage alone rounds it by more
+than 1e-5.
+"""
+import sys
+
+import numpy as np
+import torch
+
+import oracle
+from paper_2007_08501_amd import _lib
+from paper_2007_08501_amd.raster import empty_fragments
+
+TOL_VAL = 1e-5
+TOL_GRAD = 1e-3
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def threads():
+    return min(16, oracle.default_threads())
+
+
+def to_dev(b, dev="cuda"):
+    return (torch.from_numpy(b.verts).to(dev), torch.from_numpy(b.faces).to(dev),
+            torch.from_numpy(b.first_idx).to(dev), torch.from_numpy(b.num_faces).to(dev))
+
+
+def run_fwd(b, bs, M=None, sched=0, K=None, dev_inputs=None, check=True):
+    v, f, fi, nf = dev_inputs or to_dev(b)
+    H, W = b.image_size
+    K = K or b.faces_per_pixel
+    N = fi.shape[0]
+    if bs > 0 and M is None:
+        wsc = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, f.shape[0], bs, 1), v.device)
+        _lib.rast_bin_count(v, f, fi, nf, H, W, b.blur_radius, bs, wsc)
+        st, mx = _lib.rast_query_status(wsc)
+        assert st == _lib.RAST_OK
+        M = max(1, mx)
+    out = empty_fragments(N, H, W, K, v.device)
+    ws = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, f.shape[0], bs, M or 0), v.device)
+    _lib.rasterize_meshes_fwd(v, f, fi, nf, H, W, b.blur_radius, K, bs, M or 0, sched, out.pix_to_face, out.zbuf,
+                              out.bary, out.dists, ws)
+    if check:
+        st, _ = _lib.rast_query_status(ws)
+        assert st == _lib.RAST_OK, _lib.status_string(st)
+    return out, ws
+
+
+def run_bwd(b, p2f, gz, gb, gd, dev_inputs=None):
+    v, f, fi, nf = dev_inputs or to_dev(b)
+    H, W = b.image_size
+    N, K = p2f.shape[0], p2f.shape[-1]
+    gv = torch.empty_like(v)
+    ws = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, f.shape[0], 0, 0), v.device)
+    t = lambda a: None if a is None else (a if isinstance(a, torch.Tensor) else torch.from_numpy(a).to(v.device))
+    _lib.rasterize_meshes_bwd(v, f, N, H, W, K, p2f, t(gz), t(gb), t(gd), gv, ws)
+    torch.cuda.synchronize()
+    return gv
+
+
+def frag_numpy(out, pix=None):
+    """Fragments as numpy; with pix (linear pixel ids) only those pixels."""
+    res = {}
+    for name, t in zip(("p2f", "zbuf", "bary", "dists"), out):
+        if pix is not None:
+            N, H, W = t.shape[:3]
+            flat = t.reshape((N * H * W,) + tuple(t.shape[3:]))
+            t = flat[torch.from_numpy(np.asarray(pix)).to(t.device)]
+        res[name] = t.cpu().numpy()
+    return res
+
+
+def compare_fwd(g, o, verts, faces, blur, where=""):
+    """g, o: dicts of arrays with matching leading shape.  Returns stats."""
+    amb = o["amb"] != 0
+    pg, po = g["p2f"].astype(np.int64), o["p2f"]
+    bad = (pg != po).any(-1) & ~amb
+    nbad = int(bad.sum())
+    assert nbad == 0, f"{where}: pix_to_face differs at {nbad} unambiguous pixels, e.g. {np.argwhere(bad)[:5]}"
+    same = (pg == po)
+    valid = same & (po >= 0)
+    # empty slots are exactly -1
+    emp = same & (po < 0)
+    assert (g["zbuf"][emp] == -1).all() and (g["dists"][emp] == -1).all() and (g["bary"][emp] == -1).all()
+    wv = o["bary"][valid]
+    dw = np.abs(g["bary"][valid] - wv)
+    assert (dw <= TOL_VAL * np.maximum(1.0, np.abs(wv))).all(), f"{where}: bary max err {dw.max()}"
+    fz = np.asarray(verts, np.float64)[np.asarray(faces)[po[valid]]][..., 2]  # (n,3) vertex z
+    zscale = np.maximum(1.0, np.abs(wv * fz).sum(-1))
+    dz = np.abs(g["zbuf"][valid] - o["zbuf"][valid])
+    assert (dz <= TOL_VAL * zscale).all(), f"{where}: zbuf max err {(dz / zscale).max()}"
+    dd = np.abs(g["dists"][valid] - o["dists"][valid])
+    assert (dd <= TOL_VAL).all(), f"{where}: dists max err {dd.max()}"
+    rel_branch = int((np.abs(wv) > 1).any(-1).sum())
+    return dict(amb_frac=float(amb.mean()), slots=int(valid.sum()), rel_branch=rel_branch,
+                bary_err=float(dw.max()) if dw.size else 0.0, z_err=float(dz.max()) if dz.size else 0.0,
+                d_err=float(dd.max()) if dd.size else 0.0)
+
+
+def compare_grad(g, ref, where=""):
+    g = np.asarray(g, np.float64)
+    ref = np.asarray(ref, np.float64)
+    d = np.abs(g - ref)
+    mx = np.abs(ref).max()
+    assert d.max() <= TOL_GRAD * mx, f"{where}: grad max err {d.max()} vs scale {mx}"
+    assert np.linalg.norm(g - ref) <= TOL_GRAD * np.linalg.norm(ref), f"{where}: grad L2 err"
+    return float(d.max() / mx) if mx > 0 else 0.0
+
+
+def invariants_torch(out, fi, nf, blur):
+    """Properties that hold at any size, checked on the device."""
+    p2f, z, b, d = out
+    valid = p2f >= 0
+    assert not (valid[..., 1:] & ~valid[..., :-1]).any(), "valid slots are not a prefix"
+    vv = valid[..., 1:] & valid[..., :-1]
+    assert ((z[..., 1:] - z[..., :-1])[vv] >= 0).all(), "zbuf decreases along k"
+    s = b.sum(-1)
+    sc = torch.clamp(b.abs().sum(-1), min=1.0)
+    assert ((s - 1).abs()[valid] <= 1e-5 * sc[valid]).all(), "bary does not sum to 1"
+    inside = (b > 0).all(-1)
+    assert (d[valid & inside] < 0).all()
+    out_ = valid & ~inside
+    assert ((d[out_] >= 0) & (d[out_] < blur)).all()
+    N = p2f.shape[0]
+    lo = fi.view(N, 1, 1, 1)
+    hi = (fi + nf).view(N, 1, 1, 1)
+    assert (((p2f >= lo) & (p2f < hi)) | ~valid).all(), "face of another mesh"
+    assert (z[~valid] == -1).all() and (d[~valid] == -1).all()
+    return int(valid.sum())
+
+
+def tie_masked_grads(b, p2f_np, gz, gb, gd):
+    """Zero grad_dists on slots whose nearest edge is (nearly) tied (M6)."""
+    _, _, _, tie = oracle.fragments_fixed(b.verts, b.faces, b.image_size, p2f_np, nthreads=threads())
+    return gz, gb, np.where(tie.astype(bool), np.float32(0), gd).astype(np.float32)

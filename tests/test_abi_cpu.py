@@ -1,0 +1,135 @@
+"""The C ABI without a GPU: the library loads, exports every entry point the
+header declares, and rejects bad arguments on the host before any launch."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2007_08501_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rast.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^(?:int|const char\*|void|size_t)\s+(\w+)\s*\(", text, flags=re.M)
+    return names
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("rast_workspace_size", "rasterize_meshes_fwd", "rasterize_meshes_bwd", "rast_bin_count",
+              "rast_query_status", "rast_status_string", "silhouette_blend_fwd", "silhouette_blend_bwd"):
+        assert n in names
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    for n in declared_functions():
+        assert hasattr(L, n), n
+
+
+def test_status_strings():
+    for code in (_lib.RAST_OK, _lib.RAST_EINVAL, _lib.RAST_EWORKSPACE, _lib.RAST_EHIP, _lib.RAST_EOVERFLOW,
+                 _lib.RAST_EMESH):
+        s = _lib.status_string(code)
+        assert s and s != "unknown status"
+    assert _lib.status_string(12345) == "unknown status"
+
+
+def ws_size(*args):
+    out = ctypes.c_size_t(0)
+    rc = _lib.lib().rast_workspace_size(*args, ctypes.byref(out))
+    return rc, out.value
+
+
+def test_workspace_size_validation_and_growth():
+    rc, a = ws_size(1, 64, 64, 320, 0, 0)
+    assert rc == 0 and a >= 256 + 320 * 64
+    rc, b = ws_size(1, 64, 64, 320, 8, 100)
+    assert rc == 0 and b >= a + 64 * 100 * 4
+    rc, c = ws_size(1, 64, 64, 320, 8, 200)
+    assert rc == 0 and c > b
+    assert ws_size(0, 64, 64, 320, 0, 0)[0] == _lib.RAST_EINVAL        # N
+    assert ws_size(1, 64, 64, -1, 0, 0)[0] == _lib.RAST_EINVAL         # F
+    assert ws_size(1, 64, 64, 320, 12, 10)[0] == _lib.RAST_EINVAL      # not a multiple of 8
+    assert ws_size(1, 64, 64, 320, 1024, 10)[0] == _lib.RAST_EINVAL    # > max bin
+    assert ws_size(1, 64, 64, 320, 8, 0)[0] == _lib.RAST_EINVAL        # M
+    assert _lib.lib().rast_workspace_size(1, 64, 64, 320, 0, 0, None) == _lib.RAST_EINVAL
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every case fails validation first
+
+
+def fwd(**kw):
+    a = dict(verts=FAKE, V=3, faces=FAKE, F=1, first=FAKE, nf=FAKE, N=1, H=8, W=8, blur=0.0, K=1, bs=0, M=0,
+             sched=0, p2f=FAKE, zbuf=FAKE, bary=FAKE, dists=FAKE, ws=None, wsb=0, stream=None)
+    a.update(kw)
+    return _lib.lib().rasterize_meshes_fwd(a["verts"], a["V"], a["faces"], a["F"], a["first"], a["nf"], a["N"],
+                                           a["H"], a["W"], a["blur"], a["K"], a["bs"], a["M"], a["sched"],
+                                           a["p2f"], a["zbuf"], a["bary"], a["dists"], a["ws"], a["wsb"],
+                                           a["stream"])
+
+
+@pytest.mark.parametrize("kw", [
+    dict(N=0), dict(H=0), dict(W=-3), dict(K=0), dict(K=65), dict(blur=-1.0), dict(blur=float("nan")),
+    dict(blur=float("inf")), dict(bs=4), dict(bs=8, M=0), dict(bs=520, M=4), dict(sched=2), dict(V=-1),
+    dict(F=-1), dict(F=1 << 31), dict(verts=None), dict(faces=None), dict(first=None), dict(nf=None),
+    dict(p2f=None), dict(zbuf=None), dict(bary=None), dict(dists=None),
+])
+def test_forward_rejects_bad_arguments(kw):
+    assert fwd(**kw) == _lib.RAST_EINVAL
+
+
+def test_forward_rejects_bad_workspace():
+    assert fwd(ws=None, wsb=1 << 20) == _lib.RAST_EWORKSPACE
+    assert fwd(ws=ctypes.c_void_p(0x1001), wsb=1 << 20) == _lib.RAST_EWORKSPACE  # misaligned
+    assert fwd(ws=ctypes.c_void_p(0x1000), wsb=16) == _lib.RAST_EWORKSPACE      # too small
+
+
+def test_backward_rejects_bad_arguments():
+    L = _lib.lib()
+    args = [FAKE, 3, FAKE, 1, 1, 8, 8, 1, FAKE, None, None, None, FAKE, None, 0, None]
+    assert L.rasterize_meshes_bwd(*args) == _lib.RAST_EWORKSPACE
+    bad = list(args)
+    bad[8] = None  # pix_to_face
+    assert L.rasterize_meshes_bwd(*bad) == _lib.RAST_EINVAL
+    bad = list(args)
+    bad[12] = None  # grad_verts
+    assert L.rasterize_meshes_bwd(*bad) == _lib.RAST_EINVAL
+    bad = list(args)
+    bad[7] = 100  # K
+    assert L.rasterize_meshes_bwd(*bad) == _lib.RAST_EINVAL
+
+
+def test_bin_count_and_blend_reject_bad_arguments():
+    L = _lib.lib()
+    assert L.rast_bin_count(FAKE, 3, FAKE, 1, FAKE, FAKE, 1, 8, 8, 0.0, 0, None, 0, None) == _lib.RAST_EINVAL
+    assert L.rast_bin_count(FAKE, 3, FAKE, 1, FAKE, FAKE, 1, 8, 8, 0.0, 8, None, 0, None) == _lib.RAST_EWORKSPACE
+    assert L.silhouette_blend_fwd(FAKE, FAKE, 10, 4, 0.0, FAKE, None) == _lib.RAST_EINVAL
+    assert L.silhouette_blend_fwd(FAKE, FAKE, 10, 0, 1e-4, FAKE, None) == _lib.RAST_EINVAL
+    assert L.silhouette_blend_fwd(None, FAKE, 10, 4, 1e-4, FAKE, None) == _lib.RAST_EINVAL
+    assert L.silhouette_blend_bwd(FAKE, FAKE, FAKE, 10, 4, -1.0, FAKE, None) == _lib.RAST_EINVAL
+    assert L.silhouette_blend_bwd(FAKE, FAKE, None, 10, 4, 1e-4, FAKE, None) == _lib.RAST_EINVAL
+    assert L.rast_query_status(None, None, None, None) == _lib.RAST_EINVAL
+
+
+def test_product_path_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        _lib.lib()
+
+
+def test_product_path_never_imports_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2007_08501_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in text and "from oracle" not in text, fn
+                assert "oracle_rast" not in text and "liboracle" not in text, fn

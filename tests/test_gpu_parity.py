@@ -1,0 +1,351 @@
+"""GPU parity: the HIP rasterizer (through the C ABI) against the FP64 oracle.
+
+Small cases are compared in full; the full-size workloads are compared on
+seeded pixel samples (forward) and in full (backward: the oracle's backward is
+linear in the number of slots), plus size-independent invariants.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2007_08501_amd import _lib, meshgen
+from paper_2007_08501_amd.raster import empty_fragments
+
+from _util import (compare_fwd, compare_grad, frag_numpy, invariants_torch, log, run_bwd, run_fwd,
+                   threads, tie_masked_grads, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_full(b, K=None):
+    return oracle.rasterize(b.verts, b.faces, b.first_idx, b.num_faces, b.image_size, b.blur_radius,
+                            K or b.faces_per_pixel, nthreads=threads())
+
+
+def small_cfg(i, **kw):
+    return meshgen.make_config(i, **kw)
+
+
+# ----------------------------------------------------------------- forward
+
+def test_cfg1_naive_vs_oracle():
+    b = meshgen.make_config(1)
+    log("cfg1 naive", b.image_size, b.faces.shape)
+    out, _ = run_fwd(b, 0)
+    o = oracle_full(b)
+    st = compare_fwd(frag_numpy(out), o, b.verts, b.faces, b.blur_radius, "cfg1")
+    log("cfg1", st)
+    assert st["slots"] > 1000
+
+
+@pytest.mark.parametrize("bs", [8, 16, 24, 32, 64])
+def test_binned_equals_naive_bitwise(bs):
+    b = meshgen.make_config(2, n_override=3, level_override=3, image_override=72)
+    log("binned==naive", bs)
+    d = to_dev(b)
+    naive, _ = run_fwd(b, 0, dev_inputs=d)
+    for sched in (0, 1):
+        binned, _ = run_fwd(b, bs, sched=sched, dev_inputs=d)
+        for x, y in zip(naive, binned):
+            assert torch.equal(x, y)
+
+
+def test_reduced_cfg2_vs_oracle_ragged():
+    # 3 meshes at level 3, a 72x88 image: ragged against 8-pixel tiles and 32-pixel bins
+    b = meshgen.make_config(2, n_override=3, level_override=3)
+    b.image_size = (72, 88)
+    log("cfg2 reduced ragged")
+    out, _ = run_fwd(b, 32)
+    o = oracle_full(b)
+    st = compare_fwd(frag_numpy(out), o, b.verts, b.faces, b.blur_radius, "cfg2-reduced")
+    log(st)
+
+
+def test_reduced_cfg3_heterogeneous_vs_oracle():
+    b = meshgen.make_config(3, n_override=6, level_override=4, image_override=96)
+    log("cfg3 reduced", b.levels)
+    for bs, sched in ((0, 0), (16, 1), (24, 0)):
+        out, _ = run_fwd(b, bs, sched=sched)
+        o = oracle_full(b)
+        st = compare_fwd(frag_numpy(out), o, b.verts, b.faces, b.blur_radius, f"cfg3-reduced bs{bs}")
+        log(bs, sched, st)
+
+
+def test_reduced_cfg5_K50_vs_oracle():
+    b = meshgen.make_config(5, n_override=3, level_override=3, image_override=48)
+    log("cfg5 reduced K=50")
+    out, _ = run_fwd(b, 16)
+    o = oracle_full(b)
+    st = compare_fwd(frag_numpy(out), o, b.verts, b.faces, b.blur_radius, "cfg5-reduced")
+    log(st)
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 5, 7, 12, 16, 20, 33, 64])
+def test_every_K_bucket(K):
+    b = meshgen.make_config(2, n_override=2, level_override=3, image_override=40)
+    b.blur_radius = float(np.float32(3e-3))
+    out, _ = run_fwd(b, 8, K=K)
+    o = oracle.rasterize(b.verts, b.faces, b.first_idx, b.num_faces, b.image_size, b.blur_radius, K,
+                         nthreads=threads())
+    compare_fwd(frag_numpy(out), o, b.verts, b.faces, b.blur_radius, f"K={K}")
+
+
+def test_batch_equals_per_mesh_bitwise():
+    b = meshgen.make_config(3, n_override=5, level_override=4, image_override=64)
+    out, _ = run_fwd(b, 16)
+    for n in range(b.N):
+        fs = b.faces[b.first_idx[n]:b.first_idx[n] + b.num_faces[n]]
+        one = meshgen.Batch(name="one", verts=b.verts, faces=np.ascontiguousarray(fs), first_idx=np.array([0]),
+                            num_faces=np.array([fs.shape[0]]), verts_first_idx=np.array([0]),
+                            num_verts=np.array([b.verts.shape[0]]), image_size=b.image_size,
+                            faces_per_pixel=b.faces_per_pixel, blur_radius=b.blur_radius, bin_size=16,
+                            max_faces_per_bin=None)
+        o1, _ = run_fwd(one, 16)
+        p = o1.pix_to_face[0]
+        exp = torch.where(p >= 0, p + int(b.first_idx[n]), p)
+        assert torch.equal(out.pix_to_face[n], exp)
+        for x, y in zip(out[1:], o1[1:]):
+            assert torch.equal(x[n], y[0])
+
+
+def test_forward_deterministic():
+    b = meshgen.make_config(2, n_override=4, level_override=4, image_override=128)
+    d = to_dev(b)
+    ref, _ = run_fwd(b, 16, sched=1, dev_inputs=d)
+    for _ in range(5):
+        again, _ = run_fwd(b, 16, sched=1, dev_inputs=d)
+        for x, y in zip(ref, again):
+            assert torch.equal(x, y)
+
+
+# ----------------------------------------------------------------- full-size samples
+
+def sampled_check(i, bs, n_pix=1500, seed=0):
+    b = meshgen.make_config(i)
+    log(f"cfg{i} full size", b.image_size, b.faces.shape, "bs", bs)
+    d = to_dev(b)
+    out, _ = run_fwd(b, bs, sched=1, dev_inputs=d)
+    torch.cuda.synchronize()
+    invariants_torch(out, d[2], d[3], b.blur_radius)
+    N, (H, W) = b.N, b.image_size
+    rng = np.random.default_rng(seed)
+    # half uniform, half from pixels the GPU says are covered (where the work is)
+    cov = torch.nonzero((out.pix_to_face[..., 0] >= 0).reshape(-1)).reshape(-1).cpu().numpy()
+    pix = np.unique(np.concatenate([rng.integers(0, N * H * W, n_pix // 2),
+                                    rng.choice(cov, size=min(n_pix // 2, cov.size), replace=False)]))
+    o = oracle.rasterize(b.verts, b.faces, b.first_idx, b.num_faces, b.image_size, b.blur_radius,
+                         b.faces_per_pixel, pixels=pix, nthreads=threads())
+    st = compare_fwd(frag_numpy(out, pix), o, b.verts, b.faces, b.blur_radius, f"cfg{i}-sampled")
+    log(st)
+    return b, d, out
+
+
+def test_cfg2_full_size_sampled_and_backward():
+    b, d, out = sampled_check(2, 32)
+    gz, gb, gd = meshgen.upstream_grads(b)
+    p2f = out.pix_to_face.cpu().numpy()
+    gz, gb, gd = tie_masked_grads(b, p2f, gz, gb, gd)
+    gv = run_bwd(b, out.pix_to_face, gz, gb, gd, dev_inputs=d).cpu().numpy()
+    ref = oracle.backward(b.verts, b.faces, b.image_size, p2f, gz, gb, gd, nthreads=threads())
+    log("cfg2 grad rel err", compare_grad(gv, ref, "cfg2"))
+
+
+def test_cfg3_full_size_sampled_and_backward():
+    b, d, out = sampled_check(3, 16)
+    gz, gb, gd = meshgen.upstream_grads(b)
+    p2f = out.pix_to_face.cpu().numpy()
+    gz, gb, gd = tie_masked_grads(b, p2f, gz, gb, gd)
+    gv = run_bwd(b, out.pix_to_face, gz, gb, gd, dev_inputs=d).cpu().numpy()
+    ref = oracle.backward(b.verts, b.faces, b.image_size, p2f, gz, gb, gd, nthreads=threads())
+    log("cfg3 grad rel err", compare_grad(gv, ref, "cfg3"))
+
+
+def test_cfg4_full_size_sampled_and_backward():
+    b, d, out = sampled_check(4, 16, n_pix=800)
+    gz, gb, gd = meshgen.upstream_grads(b)
+    p2f = out.pix_to_face.cpu().numpy()
+    gz, gb, gd = tie_masked_grads(b, p2f, gz, gb, gd)
+    gv = run_bwd(b, out.pix_to_face, gz, gb, gd, dev_inputs=d).cpu().numpy()
+    ref = oracle.backward(b.verts, b.faces, b.image_size, p2f, gz, gb, gd, nthreads=threads())
+    log("cfg4 grad rel err", compare_grad(gv, ref, "cfg4"))
+
+
+# ----------------------------------------------------------------- backward
+
+@pytest.mark.parametrize("which", ["zbuf", "bary", "dists", "all"])
+def test_backward_vs_oracle_small(which):
+    b = meshgen.make_config(2, n_override=3, level_override=3, image_override=64)
+    out, _ = run_fwd(b, 16)
+    p2f = out.pix_to_face.cpu().numpy()
+    gz, gb, gd = meshgen.upstream_grads(b)
+    gz, gb, gd = tie_masked_grads(b, p2f, gz, gb, gd)
+    sel = dict(zbuf=(gz, None, None), bary=(None, gb, None), dists=(None, None, gd), all=(gz, gb, gd))[which]
+    gv = run_bwd(b, out.pix_to_face, *sel).cpu().numpy()
+    ref = oracle.backward(b.verts, b.faces, b.image_size, p2f, *sel, nthreads=threads())
+    compare_grad(gv, ref, which)
+
+
+def test_backward_hand_case():
+    # triangle T, pixel (2,2) of a 4x4 image; hand-derived gradients
+    v = np.array([[-1.0, -1.0, 1.0], [1.0, -1.0, 2.0], [-1.0, 1.0, 3.0]], np.float32)
+    f = np.array([[0, 1, 2]], np.int32)
+    b = meshgen.Batch(name="T", verts=v, faces=f, first_idx=np.array([0]), num_faces=np.array([1]),
+                      verts_first_idx=np.array([0]), num_verts=np.array([3]), image_size=(4, 4), faces_per_pixel=1,
+                      blur_radius=0.0, bin_size=0, max_faces_per_bin=None)
+    out, _ = run_fwd(b, 0)
+    p2f = out.pix_to_face.clone()
+    p2f[:] = -1
+    p2f[0, 2, 2, 0] = 0
+    one = torch.zeros((1, 4, 4, 1), device="cuda")
+    one[0, 2, 2, 0] = 1
+    g = run_bwd(b, p2f, None, None, one).cpu().numpy()
+    np.testing.assert_allclose(g, [[0, 0, 0], [-0.25, -0.25, 0], [-0.25, -0.25, 0]], atol=1e-6)
+    g = run_bwd(b, p2f, one, None, None).cpu().numpy()
+    np.testing.assert_allclose(g, [[-0.125, -0.25, 0.25], [-0.1875, -0.375, 0.375], [-0.1875, -0.375, 0.375]],
+                               atol=1e-6)
+
+
+def test_autograd_matches_abi():
+    from paper_2007_08501_amd.raster import RasterSettings, rasterize_meshes
+    b = meshgen.make_config(2, n_override=2, level_override=3, image_override=48)
+    v, f, fi, nf = to_dev(b)
+    vv = v.clone().requires_grad_(True)
+    frags = rasterize_meshes(vv, f, fi, nf, RasterSettings(48, b.blur_radius, b.faces_per_pixel, bin_size=16))
+    gz, gb, gd = [torch.from_numpy(x).cuda() for x in meshgen.upstream_grads(b)]
+    loss = (frags.zbuf * gz).sum() + (frags.bary * gb).sum() + (frags.dists * gd).sum()
+    loss.backward()
+    direct = run_bwd(b, frags.pix_to_face, gz, gb, gd)
+    # float atomics accumulate in a different order on each call
+    scale = float(direct.abs().max())
+    torch.testing.assert_close(vv.grad, direct, rtol=0, atol=1e-5 * scale)
+
+
+# ----------------------------------------------------------------- edge cases
+
+def test_empty_and_offscreen_meshes():
+    b = meshgen.make_config(2, n_override=3, level_override=2, image_override=32)
+    v = b.verts.copy()
+    # mesh 1 moved far off screen; mesh 2 given zero faces
+    s1 = slice(int(b.verts_first_idx[1]), int(b.verts_first_idx[1] + b.num_verts[1]))
+    v[s1, 0] += 5.0
+    b.verts = v
+    b.num_faces = b.num_faces.copy()
+    b.num_faces[2] = 0
+    for bs in (0, 8, 32):
+        out, _ = run_fwd(b, bs)
+        assert (out.pix_to_face[1:] == -1).all()
+        assert (out.pix_to_face[0] >= 0).any()
+        o = oracle_full(b)
+        compare_fwd(frag_numpy(out), o, b.verts, b.faces, b.blur_radius, f"empty bs{bs}")
+
+
+def test_bin_larger_than_image_and_K_above_hits():
+    b = meshgen.make_config(1)
+    b.blur_radius = float(np.float32(1e-3))
+    out, _ = run_fwd(b, 128, K=12)   # one bin covers the whole 64x64 image
+    o = oracle_full(b, K=12)
+    compare_fwd(frag_numpy(out), o, b.verts, b.faces, b.blur_radius, "bin>image")
+    assert (out.pix_to_face[..., -1] == -1).any() and (out.pix_to_face[..., 0] >= 0).any()
+
+
+def test_degenerate_and_behind_camera_faces():
+    v = np.array([
+        [-0.5, -0.5, 1.0], [0.5, -0.5, 1.0], [0.0, 0.5, 1.0],
+        [-0.9, 0.0, 0.5], [0.9, 0.0, 0.5], [0.0, 0.0, 0.5],
+        [-0.5, -0.5, -1.0], [0.5, -0.5, -1.0], [0.0, 0.5, -1.0],
+        [-0.2, -0.2, -0.5], [0.6, -0.2, 0.5], [-0.2, 0.6, 0.5],   # crosses z = 0
+    ], np.float32)
+    f = np.array([[0, 1, 2], [3, 4, 5], [6, 7, 8], [9, 10, 11]], np.int32)
+    b = meshgen.Batch(name="deg", verts=v, faces=f, first_idx=np.array([0]), num_faces=np.array([4]),
+                      verts_first_idx=np.array([0]), num_verts=np.array([12]), image_size=(24, 24),
+                      faces_per_pixel=3, blur_radius=float(np.float32(1e-2)), bin_size=8, max_faces_per_bin=None)
+    for bs in (0, 8):
+        out, _ = run_fwd(b, bs)
+        o = oracle_full(b)
+        compare_fwd(frag_numpy(out), o, v, f, b.blur_radius, f"degenerate bs{bs}")
+        assert not (out.pix_to_face == 1).any() and not (out.pix_to_face == 2).any()
+
+
+def test_overflow_is_reported_not_truncated():
+    b = meshgen.make_config(2, n_override=2, level_override=3, image_override=64)
+    out, ws = run_fwd(b, 32, M=1, check=False)
+    st, mx = _lib.rast_query_status(ws)
+    assert st == _lib.RAST_EOVERFLOW and mx > 1
+
+
+def test_bad_mesh_ranges_reported():
+    b = meshgen.make_config(2, n_override=2, level_override=2, image_override=32)
+    b.first_idx = np.array([0, 100], np.int64)  # overlaps mesh 0's range
+    out, ws = run_fwd(b, 0, check=False)
+    st, _ = _lib.rast_query_status(ws)
+    assert st == _lib.RAST_EMESH
+
+
+def test_zero_faces_total():
+    v = np.zeros((3, 3), np.float32)
+    f = np.zeros((0, 3), np.int32)
+    b = meshgen.Batch(name="nil", verts=v, faces=f, first_idx=np.array([0, 0]), num_faces=np.array([0, 0]),
+                      verts_first_idx=np.array([0, 0]), num_verts=np.array([3, 0]), image_size=(16, 16),
+                      faces_per_pixel=2, blur_radius=0.0, bin_size=8, max_faces_per_bin=None)
+    for bs in (0, 8):
+        out, _ = run_fwd(b, bs, M=4)
+        assert (out.pix_to_face == -1).all() and (out.zbuf == -1).all()
+
+
+# ----------------------------------------------------------------- blend
+
+def test_silhouette_blend_vs_oracle():
+    b = meshgen.make_config(5, n_override=4, level_override=3, image_override=64)
+    out, _ = run_fwd(b, 16)
+    sig = meshgen.SIL_SIGMA
+    alpha = torch.empty(out.dists.shape[:-1], device="cuda")
+    _lib.silhouette_blend_fwd(out.pix_to_face, out.dists, sig, alpha)
+    p2f = out.pix_to_face.cpu().numpy()
+    dn = out.dists.cpu().numpy()
+    ref = oracle.silhouette_blend(p2f, dn, sig)
+    assert np.abs(alpha.cpu().numpy() - ref).max() < 1e-5
+    ga = torch.randn_like(alpha)
+    gd = torch.empty_like(out.dists)
+    _lib.silhouette_blend_bwd(out.pix_to_face, out.dists, ga, sig, gd)
+    refg = oracle.silhouette_blend_backward(p2f, dn, sig, ga.cpu().numpy())
+    compare_grad(gd.cpu().numpy(), refg, "blend")
+
+
+# ----------------------------------------------------------------- graphs
+
+def test_graph_replay_matches_eager():
+    from paper_2007_08501_amd.graph import GraphRunner
+    b = meshgen.make_config(3, n_override=6, level_override=4, image_override=128)
+    v, f, fi, nf = to_dev(b)
+    _, ws0 = run_fwd(b, 16, check=True, dev_inputs=(v, f, fi, nf))
+    st, mx = _lib.rast_query_status(ws0)
+    gr = GraphRunner(v, f, fi, nf, 128, 128, b.blur_radius, 8, 16, 2 * mx + 64, sched=1)
+    gz, gb, gd = [torch.from_numpy(x).cuda() for x in meshgen.upstream_grads(b)]
+    gr.set_grads(gz, gb, gd)
+    gr.step_eager()
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in gr.out]
+    ref_g = gr.grad_verts.clone()
+    gr.capture()
+    for it in range(4):
+        # unrelated eager work between replays
+        gr.out.pix_to_face.fill_(7)
+        gr.grad_verts.fill_(3.0)
+        torch.cuda.synchronize()
+        gr.replay()
+        torch.cuda.synchronize()
+        for x, y in zip(ref, gr.out):
+            assert torch.equal(x, y), f"replay {it}"
+        # float atomics: summation order differs between runs
+        torch.testing.assert_close(gr.grad_verts, ref_g, rtol=0, atol=1e-5 * float(ref_g.abs().max()))
+        assert gr.status()[0] == _lib.RAST_OK
+    # new vertex positions flow through the captured graph
+    gr.set_verts(v * 0.9)
+    gr.replay()
+    torch.cuda.synchronize()
+    b2 = meshgen.make_config(3, n_override=6, level_override=4, image_override=128)
+    b2.verts = (b.verts * np.float32(0.9)).astype(np.float32)
+    e, _ = run_fwd(b2, 16, M=2 * mx + 64, sched=1)
+    for x, y in zip(e, gr.out):
+        assert torch.equal(x, y)

@@ -148,3 +148,21 @@ def test_iou_loss_cases():
     T = np.zeros_like(S)
     T[:, 2:] = 1.0
     assert oracle.iou_loss(S[:1], T[:1]) == pytest.approx(1.0)
+
+
+def test_backward_pixel_list_matches_full():
+    v, f, fi, nf = sphere_batch([2, 3], seed=15)
+    H = W = 24
+    o = oracle.rasterize(v, f, fi, nf, (H, W), 1e-3, 3)
+    rng = np.random.default_rng(7)
+    gz = rng.standard_normal(o["p2f"].shape)
+    gb = rng.standard_normal(o["p2f"].shape + (3,))
+    gd = rng.standard_normal(o["p2f"].shape)
+    pix = np.sort(rng.choice(2 * H * W, 300, replace=False))
+    keep = np.zeros(2 * H * W, bool)
+    keep[pix] = True
+    keep = keep.reshape(2, H, W, 1)
+    full = oracle.backward(v, f, (H, W), np.where(keep, o["p2f"], -1), gz, gb, gd)
+    flat = lambda a: a.reshape((2 * H * W,) + a.shape[3:])[pix]
+    part = oracle.backward(v, f, (H, W), flat(o["p2f"]), flat(gz), flat(gb), flat(gd), pixels=pix, N=2)
+    np.testing.assert_allclose(part, full, rtol=1e-12, atol=1e-12)
