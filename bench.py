@@ -128,14 +128,15 @@ def main():
     M = M or 0
     out = empty_fragments(N, H, W, K, dev)
     ws = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, f.shape[0], bs, M), dev)
-    bws = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, f.shape[0], 0, 0), dev)
+    bws = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, f.shape[0], bs, M), dev)
     gv = torch.empty_like(v)
     stream = torch.cuda.current_stream(dev).cuda_stream
 
     def step():
         _lib.rasterize_meshes_fwd(v, f, fi, nf, H, W, b.blur_radius, K, bs, M, sched, out.pix_to_face, out.zbuf,
                                   out.bary, out.dists, ws)
-        _lib.rasterize_meshes_bwd(v, f, N, H, W, K, out.pix_to_face, gz, gb, gd, gv, bws)
+        _lib.rasterize_meshes_bwd(v, f, fi, nf, H, W, b.blur_radius, K, bs, M, out.pix_to_face, gz, gb, gd, gv,
+                                  bws)
 
     ev = HipEvents()
     for _ in range(args.warmup):
@@ -213,7 +214,7 @@ def main():
     keep[pix_t] = True
     p2f_s = torch.where(keep.view(N, H, W, 1), out.pix_to_face, torch.full_like(out.pix_to_face, -1))
     gv_s = torch.empty_like(v)
-    _lib.rasterize_meshes_bwd(v, f, N, H, W, K, p2f_s, gz, gb, gd, gv_s, bws)
+    _lib.rasterize_meshes_bwd(v, f, fi, nf, H, W, b.blur_radius, K, bs, M, p2f_s, gz, gb, gd, gv_s, bws)
     rows = lambda a: a.reshape((N * H * W,) + a.shape[3:])[pix]
     p2f_rows = rows(out.pix_to_face.cpu().numpy()).astype(np.int64)
     ref = oracle.backward(b.verts, b.faces, (H, W), p2f_rows, rows(gz_np), rows(gb_np), rows(gd_np), nthreads=nthr,
@@ -244,7 +245,8 @@ def main():
             for fm, o1, z0, c1 in calls:
                 _lib.rasterize_meshes_fwd(v, fm, z0, c1, H, W, b.blur_radius, K, 0, 0, 0, o1.pix_to_face, o1.zbuf,
                                           o1.bary, o1.dists, one_ws)
-                _lib.rasterize_meshes_bwd(v, fm, 1, H, W, K, o1.pix_to_face, gz[:1], gb[:1], gd[:1], gvm, one_ws)
+                _lib.rasterize_meshes_bwd(v, fm, z0, c1, H, W, b.blur_radius, K, 0, 0, o1.pix_to_face, gz[:1],
+                                          gb[:1], gd[:1], gvm, one_ws)
 
         per_mesh_step()
         torch.cuda.synchronize()

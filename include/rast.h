@@ -75,7 +75,7 @@ enum rast_status {
 
 /*
  * Bytes of workspace needed by rasterize_meshes_fwd / _bwd / rast_bin_count
- * for these sizes.  bin_size 0 selects the single-pass form (every pixel
+ * for these sizes (one size serves all three).  bin_size 0 selects the single-pass form (every pixel
  * against every face of its mesh).  bin_size > 0 must be a multiple of
  * RAST_TILE, at most RAST_MAX_BIN; max_faces_per_bin (M) > 0 then sizes the
  * per-bin face lists (N * ceil(H/bs) * ceil(W/bs) * M int32).
@@ -111,14 +111,23 @@ int rasterize_meshes_fwd(const float* verts_packed, int64_t V, const int32_t* fa
  * into grad_verts (V,3) f32, which is overwritten.  Each slot's barycentrics,
  * z and nearest edge are recomputed from the vertices; the choice of faces is
  * held fixed.  grad_zbuf (N,H,W,K), grad_bary (N,H,W,K,3) and grad_dists
- * (N,H,W,K) may each be NULL (= zero).  The result accumulates with float
- * atomics, so its last bits may differ between runs.
- * workspace: at least rast_workspace_size(N, H, W, F, 0, 0) bytes.
+ * (N,H,W,K) may each be NULL (= zero).
+ *   pix_to_face must come from rasterize_meshes_fwd with the same vertices,
+ *   faces, mesh ranges, image size and blur_radius; bin_size and
+ *   max_faces_per_bin are the forward's (bin_size 0: the backward walks each
+ *   face's pixel box; > 0: it re-bins the faces and streams each bin's slots).
+ *   A bin overflow sets RAST_EOVERFLOW in the workspace status and leaves
+ *   grad_verts incomplete.
+ * The result accumulates with float atomics, so its last bits may differ
+ * between runs.  workspace: at least rast_workspace_size(N, H, W, F,
+ * bin_size, max_faces_per_bin) bytes.
  */
 int rasterize_meshes_bwd(const float* verts_packed, int64_t V, const int32_t* faces_packed, int64_t F,
-                         int N, int H, int W, int faces_per_pixel, const int32_t* pix_to_face,
-                         const float* grad_zbuf, const float* grad_bary, const float* grad_dists,
-                         float* grad_verts, void* workspace, size_t workspace_bytes, void* stream);
+                         const int64_t* mesh_to_face_first_idx, const int64_t* num_faces_per_mesh,
+                         int N, int H, int W, float blur_radius, int faces_per_pixel, int bin_size,
+                         int max_faces_per_bin, const int32_t* pix_to_face, const float* grad_zbuf,
+                         const float* grad_bary, const float* grad_dists, float* grad_verts, void* workspace,
+                         size_t workspace_bytes, void* stream);
 
 /*
  * Coarse pass only, counting: fills the workspace status with the largest

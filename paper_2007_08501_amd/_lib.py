@@ -56,7 +56,7 @@ def lib() -> ctypes.CDLL:
         sz = ctypes.c_size_t
         L.rast_workspace_size.argtypes = [ci, ci, ci, i64, ci, ci, ctypes.POINTER(sz)]
         L.rasterize_meshes_fwd.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, cf, ci, ci, ci, ci, P, P, P, P, P, sz, P]
-        L.rasterize_meshes_bwd.argtypes = [P, i64, P, i64, ci, ci, ci, ci, P, P, P, P, P, P, sz, P]
+        L.rasterize_meshes_bwd.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, cf, ci, ci, ci, P, P, P, P, P, P, sz, P]
         L.rast_bin_count.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, cf, ci, P, sz, P]
         L.rast_query_status.argtypes = [P, ctypes.POINTER(ci), ctypes.POINTER(ci), P]
         L.rast_status_string.argtypes = [ci]
@@ -139,19 +139,23 @@ def rasterize_meshes_fwd(verts, faces, first_idx, num_faces, H, W, blur_radius, 
     _check("rasterize_meshes_fwd", rc)
 
 
-def rasterize_meshes_bwd(verts, faces, N, H, W, K, pix_to_face, grad_zbuf, grad_bary, grad_dists, grad_verts,
-                         workspace):
+def rasterize_meshes_bwd(verts, faces, first_idx, num_faces, H, W, blur_radius, K, bin_size, max_faces_per_bin,
+                         pix_to_face, grad_zbuf, grad_bary, grad_dists, grad_verts, workspace):
     dev = verts.device
     _require(verts, "verts", torch.float32, dev)
     _require(faces, "faces", torch.int32, dev)
+    _require(first_idx, "mesh_to_face_first_idx", torch.int64, dev)
+    _require(num_faces, "num_faces_per_mesh", torch.int64, dev)
     _require(pix_to_face, "pix_to_face", torch.int32, dev)
     for t, n in ((grad_zbuf, "grad_zbuf"), (grad_bary, "grad_bary"), (grad_dists, "grad_dists"),
                  (grad_verts, "grad_verts")):
         _require(t, n, torch.float32, dev)
     _require(workspace, "workspace", torch.uint8, dev)
-    rc = lib().rasterize_meshes_bwd(_p(verts), verts.shape[0], _p(faces), faces.shape[0], int(N), int(H), int(W),
-                                    int(K), _p(pix_to_face), _p(grad_zbuf), _p(grad_bary), _p(grad_dists),
-                                    _p(grad_verts), _p(workspace), workspace.numel(), _stream(dev))
+    N = first_idx.shape[0]
+    rc = lib().rasterize_meshes_bwd(_p(verts), verts.shape[0], _p(faces), faces.shape[0], _p(first_idx),
+                                    _p(num_faces), int(N), int(H), int(W), float(blur_radius), int(K),
+                                    int(bin_size), int(max_faces_per_bin or 0), _p(pix_to_face), _p(grad_zbuf), _p(grad_bary), _p(grad_dists), _p(grad_verts),
+                                    _p(workspace), workspace.numel(), _stream(dev))
     _check("rasterize_meshes_bwd", rc)
 
 

@@ -20,7 +20,7 @@ constexpr int kMaxDevices = 64;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t hdr, recs, counts, lists, order, hist, total;
+    size_t hdr, recs, counts, lists, order, hist, partial, fpos, big, total;
     int nby, nbx, tiles_x, tiles_y;
     int64_t nbins;
 };
@@ -54,6 +54,16 @@ bool make_layout(int N, int H, int W, int64_t F, int bs, int M, Layout* L) {
         L->hist = off;
         off = align_up(off + 64 * 4);
     }
+    // backward only: per-entry partial sums (bins x M x 9 floats), each face's
+    // position in its bins (F x 4 ints) and the list of large faces (F ints)
+    L->partial = off;
+    size_t ps = (size_t)L->nbins * (size_t)(M > 0 ? M : 0);
+    if (ps > big / 36) return false;
+    off = align_up(off + ps * 36);
+    L->fpos = off;
+    off = align_up(off + (size_t)F * 16);
+    L->big = off;
+    off = align_up(off + (size_t)F * 4);
     L->total = off;
     return true;
 }
@@ -149,24 +159,34 @@ int rasterize_meshes_fwd(const float* verts_packed, int64_t V, const int32_t* fa
     return hip_rc(e);
 }
 
-int rasterize_meshes_bwd(const float* verts_packed, int64_t V, const int32_t* faces_packed, int64_t F, int N, int H,
-                         int W, int faces_per_pixel, const int32_t* pix_to_face, const float* grad_zbuf,
-                         const float* grad_bary, const float* grad_dists, float* grad_verts, void* workspace,
-                         size_t workspace_bytes, void* stream) {
+int rasterize_meshes_bwd(const float* verts_packed, int64_t V, const int32_t* faces_packed, int64_t F,
+                         const int64_t* mesh_to_face_first_idx, const int64_t* num_faces_per_mesh, int N, int H,
+                         int W, float blur_radius, int faces_per_pixel, int bin_size, int max_faces_per_bin,
+                         const int32_t* pix_to_face, const float* grad_zbuf, const float* grad_bary,
+                         const float* grad_dists, float* grad_verts, void* workspace, size_t workspace_bytes,
+                         void* stream) {
     if (bad_dims(N, H, W, faces_per_pixel)) return RAST_EINVAL;
     if (V < 0 || V > INT32_MAX || F < 0 || F > INT32_MAX) return RAST_EINVAL;
     if ((V > 0 && (verts_packed == nullptr || grad_verts == nullptr)) || (F > 0 && faces_packed == nullptr))
         return RAST_EINVAL;
+    if (mesh_to_face_first_idx == nullptr || num_faces_per_mesh == nullptr) return RAST_EINVAL;
     if (pix_to_face == nullptr) return RAST_EINVAL;
+    if (!(blur_radius >= 0.0f) || !isfinite(blur_radius)) return RAST_EINVAL;
+    if (bin_size < 0 || bin_size > RAST_MAX_BIN || (bin_size % RAST_TILE) != 0) return RAST_EINVAL;
+    if (bin_size > 0 && max_faces_per_bin < 1) return RAST_EINVAL;
     Layout L;
-    if (!make_layout(N, H, W, F, 0, 0, &L)) return RAST_EINVAL;
+    if (!make_layout(N, H, W, F, bin_size, max_faces_per_bin, &L)) return RAST_EINVAL;
     if (workspace == nullptr || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < L.total)
         return RAST_EWORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     if (V == 0) return RAST_OK;
-    return hip_rc(rast::launch_backward(verts_packed, V, faces_packed, F, N, H, W, faces_per_pixel, pix_to_face,
-                                        grad_zbuf, grad_bary, grad_dists, grad_verts, s,
-                                        tl_events.begin[RAST_KERNEL_BWD], tl_events.end[RAST_KERNEL_BWD]));
+    char* ws = (char*)workspace;
+    return hip_rc(rast::launch_backward(
+        verts_packed, V, faces_packed, F, mesh_to_face_first_idx, num_faces_per_mesh, N, H, W, faces_per_pixel,
+        blur_radius, bin_size, max_faces_per_bin, pix_to_face, grad_zbuf, grad_bary, grad_dists, grad_verts,
+        (int*)(ws + L.hdr), (rast::FaceRec*)(ws + L.recs), (int*)(ws + L.counts), (int*)(ws + L.lists),
+        (float*)(ws + L.partial), (int*)(ws + L.fpos), (int*)(ws + L.big), s, tl_events.begin[RAST_KERNEL_BWD],
+        tl_events.end[RAST_KERNEL_BWD]));
 }
 
 int rast_set_kernel_events(int kernel, void* begin, void* end) {

@@ -31,6 +31,8 @@ enum : int {
     kHdrMaxCount = 1,   // largest bin count seen
     kHdrWorkNext = 2,   // persistent scheduler: next work item
     kHdrWorkTotal = 3,  // persistent scheduler: number of work items
+    kHdrBigCount = 8,   // backward: number of faces with large pixel boxes
+    kHdrBigNext = 9,    // backward: next large face to scan
     kHdrWords = 64,
 };
 enum : int { kStatOverflow = 1, kStatMesh = 2 };
@@ -226,6 +228,57 @@ __device__ __forceinline__ bool face_counts(const FaceRec& R, const Pix& p, floa
     float u;
     float d2 = eval_dist(R, sx, sy, e, u);
     return d2 < blur;
+}
+
+// Mesh of face f: the last n with first[n] <= f, if f lies in its range.
+__device__ __forceinline__ int find_mesh(const int64_t* __restrict__ first, const int64_t* __restrict__ nf, int N,
+                                         int64_t f) {
+    int lo = 0, hi = N - 1, ans = -1;
+    while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        if (first[mid] <= f) {
+            ans = mid;
+            lo = mid + 1;
+        } else {
+            hi = mid - 1;
+        }
+    }
+    if (ans >= 0 && f < first[ans] + nf[ans]) return ans;
+    return -1;
+}
+
+// Inclusive pixel range [lo, hi] whose centres may fall in [vmin, vmax] along
+// one axis of `size` pixels (centre of pixel i at 1 - (2i+1)/size); empty when
+// hi < lo.  The FP32 evaluation of the bounds is off by less than 1e-3 pixel
+// (and a rounded pixel centre by less than 1e-4), so widening each bound by
+// 0.01 pixel keeps every pixel whose centre passes the bbox test.
+__device__ __forceinline__ void pix_range(float vmin, float vmax, int size, int& lo, int& hi) {
+    float a = ((float)size * (1.0f - vmax) - 1.0f) * 0.5f;
+    float b = ((float)size * (1.0f - vmin) - 1.0f) * 0.5f;
+    a = fminf(fmaxf(a, -2.0f), (float)size + 1.0f);
+    b = fminf(fmaxf(b, -2.0f), (float)size + 1.0f);
+    lo = (int)ceilf(a - 0.01f);
+    hi = (int)floorf(b + 0.01f);
+    if (lo < 0) lo = 0;
+    if (hi > size - 1) hi = size - 1;
+}
+
+// Bins [bx0, bx1] x [by0, by1] (bin_size bs) whose pixels may count face R;
+// false when the face counts nowhere on the H x W image.  The binning pass
+// and the backward use this same function, so they agree on every face's
+// bins.
+__device__ __forceinline__ bool face_bins(const FaceRec& R, int H, int W, int bs, int& bx0, int& bx1, int& by0,
+                                          int& by1) {
+    if (!R.ok()) return false;
+    int c0, c1, r0, r1;
+    pix_range(R.q4.x, R.q4.y, W, c0, c1);
+    pix_range(R.q4.z, R.q4.w, H, r0, r1);
+    if (c1 < c0 || r1 < r0) return false;
+    bx0 = c0 / bs;
+    bx1 = c1 / bs;
+    by0 = r0 / bs;
+    by1 = r1 / bs;
+    return true;
 }
 
 // Sort key: ascending z, then ascending face id, as one unsigned 64-bit

@@ -1,9 +1,16 @@
-// kernels_bwd.hip -- backward of the rasterizer for gfx950.
+// kernels_bwd.hip -- backward of the rasterizer for gfx950, organised by face.
 //
-// For every slot with a face, the barycentrics, z and the nearest edge are
-// recomputed from the vertices (only the face ids are kept from the forward),
-// the fragment gradients are chained to the nine coordinates of the face's
-// vertices, and the result is added into grad_verts with float atomics.
+// The forward stores only the face ids (paper, Section 3.2: the cached
+// Fragment data avoid recomputing face-pixel intersections).  Here every face
+// gathers its own gradient: the thread that owns face f scans the pixels of
+// f's blur-grown bounding box (the only pixels whose slots the forward can
+// fill with f), finds the slot holding f in each, recomputes barycentrics, z
+// and the nearest edge for that pixel, and sums the chain rule for its nine
+// vertex coordinates in registers -- no atomics per slot.  A workgroup then
+// merges its 256 faces' contributions per vertex in an LDS hash table and
+// issues one float atomic per (vertex, coordinate).  Faces whose box exceeds
+// kBigArea pixels are handed to a second kernel in which a whole workgroup
+// scans one face's box.
 //
 // Derivatives (pixel p fixed, R_j = v_j - p, cross(u,v) = u.x v.y - u.y v.x):
 //   e0 = cross(R1,R2), e1 = cross(R2,R0), e2 = cross(R0,R1), E = e0+e1+e2,
@@ -18,39 +25,42 @@
 
 namespace rast {
 
+constexpr int kBwdBlock = 256;
+constexpr int kHash = 1024;     // LDS hash entries per workgroup (>= 3 * kBwdBlock)
+constexpr int kBigArea = 256;   // faces with larger pixel boxes go to the cooperative kernel
+
 struct BwdArgs {
     const float* verts;
     const int32_t* faces;
+    const int64_t* first;
+    const int64_t* nf;
     const int32_t* p2f;
     const float* gz;
     const float* gb;
     const float* gd;
     float* grad;
-    int64_t S;
+    int* hdr;
+    int* big;      // list of faces with large boxes
     int64_t V, F;
-    int H, W, K;
+    int N, H, W, K;
+    float rb;      // sqrt(blur_radius)
+    // binned form
+    const FaceRec* recs;
+    const int* counts;
+    const int* lists;
+    float* partial;    // (bins, M, 9): nine coordinate sums per bin-list entry
+    float fix_limit;   // contributions below this magnitude use the fixed-point sums
+    const int* fpos;   // (F, 4): position of a face in each bin of its range (ranges of <= 4 bins)
+    int bs, nby, nbx, M;
 };
 
-__global__ __launch_bounds__(256) void raster_bwd_kernel(BwdArgs a) {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= a.S) return;
-    int f = a.p2f[s];
-    if (f < 0 || f >= a.F) return;  // an id outside [0, F) cannot come from the forward; ignore it
-    int64_t pix = s / a.K;
-    int64_t hw = (int64_t)a.H * a.W;
-    int rem = (int)(pix % hw);
-    int r = rem / a.W, c = rem - r * a.W;
-    const Pix p = make_pix(r, c, a.H, a.W);
-    int vi[3] = {a.faces[3 * (int64_t)f], a.faces[3 * (int64_t)f + 1], a.faces[3 * (int64_t)f + 2]};
-    if (vi[0] < 0 || vi[0] >= a.V || vi[1] < 0 || vi[1] >= a.V || vi[2] < 0 || vi[2] >= a.V) return;
-    float P[3][3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-#pragma unroll
-        for (int x = 0; x < 3; ++x) P[j][x] = a.verts[3 * (int64_t)vi[j] + x];
-    }
-    FaceRec R = make_rec(P[0][0], P[0][1], P[0][2], P[1][0], P[1][1], P[1][2], P[2][0], P[2][1], P[2][2], 0.0f, 0);
-    if (!R.ok()) return;
+struct FaceGrad {
+    float gx[3], gy[3], gzv[3];
+};
+
+// Adds the contribution of slot s (pixel p) of face R to g.
+__device__ __forceinline__ void slot_grad(const BwdArgs& a, const FaceRec& R, const float (&vz)[3], const Pix& p,
+                                          int64_t s, FaceGrad& g) {
     Eval ev;
     eval_full(R, p, ev);
     float gzs = a.gz ? a.gz[s] : 0.0f;
@@ -61,14 +71,13 @@ __global__ __launch_bounds__(256) void raster_bwd_kernel(BwdArgs a) {
         gb2 = a.gb[3 * s + 2];
     }
     float gds = a.gd ? a.gd[s] : 0.0f;
-    float w[3] = {ev.w0, ev.w1, ev.w2};
-    float G0 = gb0 + gzs * P[0][2];
-    float G1 = gb1 + gzs * P[1][2];
-    float G2 = gb2 + gzs * P[2][2];
-    float Gw = G0 * w[0] + G1 * w[1] + G2 * w[2];
+    float G0 = gb0 + gzs * vz[0];
+    float G1 = gb1 + gzs * vz[1];
+    float G2 = gb2 + gzs * vz[2];
+    float Gw = G0 * ev.w0 + G1 * ev.w1 + G2 * ev.w2;
     float invE = R.invE();
     float H0 = (G0 - Gw) * invE, H1 = (G1 - Gw) * invE, H2 = (G2 - Gw) * invE;
-    // vertex positions relative to the pixel, from the record's exact pieces
+    // vertex positions relative to the pixel
     float Rx[3], Ry[3];
     Rx[0] = -ev.sx;
     Ry[0] = -ev.sy;
@@ -79,61 +88,485 @@ __global__ __launch_bounds__(256) void raster_bwd_kernel(BwdArgs a) {
     // de0/dR1 = (R2.y, -R2.x), de0/dR2 = (-R1.y, R1.x)
     // de1/dR2 = (R0.y, -R0.x), de1/dR0 = (-R2.y, R2.x)
     // de2/dR0 = (R1.y, -R1.x), de2/dR1 = (-R0.y, R0.x)
-    float gx[3], gy[3];
-    gx[0] = H1 * (-Ry[2]) + H2 * Ry[1];
-    gy[0] = H1 * Rx[2] + H2 * (-Rx[1]);
-    gx[1] = H0 * Ry[2] + H2 * (-Ry[0]);
-    gy[1] = H0 * (-Rx[2]) + H2 * Rx[0];
-    gx[2] = H0 * (-Ry[1]) + H1 * Ry[0];
-    gy[2] = H0 * Rx[1] + H1 * (-Rx[0]);
+    g.gx[0] += H1 * (-Ry[2]) + H2 * Ry[1];
+    g.gy[0] += H1 * Rx[2] + H2 * (-Rx[1]);
+    g.gx[1] += H0 * Ry[2] + H2 * (-Ry[0]);
+    g.gy[1] += H0 * (-Rx[2]) + H2 * Rx[0];
+    g.gx[2] += H0 * (-Ry[1]) + H1 * Ry[0];
+    g.gy[2] += H0 * Rx[1] + H1 * (-Rx[0]);
+    g.gzv[0] += gzs * ev.w0;
+    g.gzv[1] += gzs * ev.w1;
+    g.gzv[2] += gzs * ev.w2;
     if (gds != 0.0f) {
         int e = ev.edge;
         int js = e, jt = e == 2 ? 0 : e + 1;
         float u = ev.u;
-        float Qx = Rx[js] + u * (Rx[jt] - Rx[js]);
-        float Qy = Ry[js] + u * (Ry[jt] - Ry[js]);
+        float Rsx = js == 0 ? Rx[0] : (js == 1 ? Rx[1] : Rx[2]);
+        float Rsy = js == 0 ? Ry[0] : (js == 1 ? Ry[1] : Ry[2]);
+        float Rtx = jt == 0 ? Rx[0] : (jt == 1 ? Rx[1] : Rx[2]);
+        float Rty = jt == 0 ? Ry[0] : (jt == 1 ? Ry[1] : Ry[2]);
+        float Qx = Rsx + u * (Rtx - Rsx);
+        float Qy = Rsy + u * (Rty - Rsy);
         float sg = ev.inside ? -gds : gds;
         float cs = 2.0f * (1.0f - u) * sg, ct = 2.0f * u * sg;
-        // only the two endpoints of the nearest edge move d2
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             float k = (j == js) ? cs : ((j == jt) ? ct : 0.0f);
-            gx[j] += k * Qx;
-            gy[j] += k * Qy;
+            g.gx[j] += k * Qx;
+            g.gy[j] += k * Qy;
         }
-    }
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        float* g = a.grad + 3 * (int64_t)vi[j];
-        atomicAdd(g + 0, gx[j]);
-        atomicAdd(g + 1, gy[j]);
-        atomicAdd(g + 2, gzs * w[j]);
     }
 }
 
-hipError_t launch_backward(const float* verts, int64_t V, const int32_t* faces, int64_t F, int N, int H, int W, int K,
+// Scans the K slots of pixel (n, r, c) for face f and accumulates every match.
+__device__ __forceinline__ void scan_pixel(const BwdArgs& a, const FaceRec& R, const float (&vz)[3], int f, int n,
+                                           int r, int c, FaceGrad& g) {
+    const int64_t pix = ((int64_t)n * a.H + r) * a.W + c;
+    const int32_t* row = a.p2f + pix * a.K;
+    int first_k = -1;
+    bool more = false;
+    if ((a.K & 3) == 0) {
+        const int4* row4 = reinterpret_cast<const int4*>(row);
+        for (int k = 0; k < a.K; k += 4) {
+            int4 v = row4[k >> 2];
+            int h = (int)(v.x == f) + (int)(v.y == f) + (int)(v.z == f) + (int)(v.w == f);
+            if (h > 0) {
+                int hit = v.x == f ? 0 : (v.y == f ? 1 : (v.z == f ? 2 : 3));
+                more = more || first_k >= 0 || h > 1;
+                if (first_k < 0) first_k = k + hit;
+            }
+        }
+    } else {
+        for (int k = 0; k < a.K; ++k) {
+            if (row[k] == f) {
+                more = more || first_k >= 0;
+                if (first_k < 0) first_k = k;
+            }
+        }
+    }
+    if (first_k < 0) return;
+    Pix p = make_pix(r, c, a.H, a.W);
+    slot_grad(a, R, vz, p, pix * a.K + first_k, g);
+    if (more) {
+        // the same face in several slots of one pixel cannot come from the
+        // forward, but every slot is still honoured
+        for (int kk = first_k + 1; kk < a.K; ++kk)
+            if (row[kk] == f) slot_grad(a, R, vz, p, pix * a.K + kk, g);
+    }
+}
+
+// Face f's record (with the blur-grown box), its vertex ids and depths.
+__device__ __forceinline__ bool load_face(const BwdArgs& a, int64_t f, FaceRec& R, int (&vi)[3], float (&vz)[3],
+                                          int& n) {
+    vi[0] = a.faces[3 * f];
+    vi[1] = a.faces[3 * f + 1];
+    vi[2] = a.faces[3 * f + 2];
+    if (vi[0] < 0 || vi[0] >= a.V || vi[1] < 0 || vi[1] >= a.V || vi[2] < 0 || vi[2] >= a.V) {
+        vi[0] = vi[1] = vi[2] = -1;
+        return false;
+    }
+    n = find_mesh(a.first, a.nf, a.N, f);
+    if (n < 0) return false;
+    const float* P0 = a.verts + 3 * (int64_t)vi[0];
+    const float* P1 = a.verts + 3 * (int64_t)vi[1];
+    const float* P2 = a.verts + 3 * (int64_t)vi[2];
+    R = make_rec(P0[0], P0[1], P0[2], P1[0], P1[1], P1[2], P2[0], P2[1], P2[2], a.rb, n);
+    vz[0] = P0[2];
+    vz[1] = P1[2];
+    vz[2] = P2[2];
+    return R.ok();
+}
+
+__device__ __forceinline__ uint32_t vhash(int v) { return ((uint32_t)v * 2654435761u) >> (32 - 10); }
+
+// Merges (vertex, grad3) into the workgroup's LDS table; falls back to a global
+// atomic when the table is full.
+__device__ __forceinline__ void lds_add(int* keys, float* vals, float* grad, int v, float x, float y, float z) {
+    uint32_t h = vhash(v);
+    for (int probe = 0; probe < kHash; ++probe) {
+        int prev = atomicCAS(&keys[h], -1, v);
+        if (prev == -1 || prev == v) {
+            atomicAdd(&vals[3 * h + 0], x);
+            atomicAdd(&vals[3 * h + 1], y);
+            atomicAdd(&vals[3 * h + 2], z);
+            return;
+        }
+        h = (h + 1) & (kHash - 1);
+    }
+    atomicAdd(grad + 3 * (int64_t)v + 0, x);
+    atomicAdd(grad + 3 * (int64_t)v + 1, y);
+    atomicAdd(grad + 3 * (int64_t)v + 2, z);
+}
+
+__global__ __launch_bounds__(kBwdBlock) void bwd_faces_kernel(BwdArgs a) {
+    __shared__ int keys[kHash];
+    __shared__ float vals[3 * kHash];
+    for (int i = threadIdx.x; i < kHash; i += kBwdBlock) {
+        keys[i] = -1;
+        vals[3 * i] = vals[3 * i + 1] = vals[3 * i + 2] = 0.0f;
+    }
+    __syncthreads();
+    const int64_t f = (int64_t)blockIdx.x * kBwdBlock + threadIdx.x;
+    FaceGrad g;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) g.gx[j] = g.gy[j] = g.gzv[j] = 0.0f;
+    int vi[3] = {-1, -1, -1};
+    bool have = false;
+    if (f < a.F) {
+        FaceRec R;
+        float vz[3];
+        int n;
+        if (load_face(a, f, R, vi, vz, n)) {
+            int c0, c1, r0, r1;
+            pix_range(R.q4.x, R.q4.y, a.W, c0, c1);
+            pix_range(R.q4.z, R.q4.w, a.H, r0, r1);
+            if (c1 >= c0 && r1 >= r0) {
+                int area = (c1 - c0 + 1) * (r1 - r0 + 1);
+                if (area > kBigArea) {
+                    int pos = atomicAdd(&a.hdr[kHdrBigCount], 1);
+                    a.big[pos] = (int)f;
+                } else {
+                    for (int r = r0; r <= r1; ++r)
+                        for (int c = c0; c <= c1; ++c) scan_pixel(a, R, vz, (int)f, n, r, c, g);
+                    have = true;
+                }
+            }
+        }
+    }
+    if (have) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) lds_add(keys, vals, a.grad, vi[j], g.gx[j], g.gy[j], g.gzv[j]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kHash; i += kBwdBlock) {
+        int v = keys[i];
+        if (v >= 0) {
+            atomicAdd(a.grad + 3 * (int64_t)v + 0, vals[3 * i + 0]);
+            atomicAdd(a.grad + 3 * (int64_t)v + 1, vals[3 * i + 1]);
+            atomicAdd(a.grad + 3 * (int64_t)v + 2, vals[3 * i + 2]);
+        }
+    }
+}
+
+// Faces with large boxes: each workgroup takes the next listed face and its
+// 256 threads share the pixel scan; the nine sums are reduced in LDS.  Every
+// workgroup leaves once the list is exhausted.
+__global__ __launch_bounds__(kBwdBlock) void bwd_big_faces_kernel(BwdArgs a) {
+    __shared__ float red[9][kBwdBlock / 64];
+    __shared__ int item_s;
+    const int count = a.hdr[kHdrBigCount];
+    for (;;) {
+        if (threadIdx.x == 0) item_s = atomicAdd(&a.hdr[kHdrBigNext], 1);
+        __syncthreads();
+        const int item = item_s;
+        __syncthreads();
+        if (item >= count) break;
+        const int f = a.big[item];
+        FaceRec R;
+        int vi[3] = {-1, -1, -1};
+        float vz[3];
+        int n;
+        FaceGrad g;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) g.gx[j] = g.gy[j] = g.gzv[j] = 0.0f;
+        bool ok = load_face(a, f, R, vi, vz, n);
+        if (ok) {
+            int c0, c1, r0, r1;
+            pix_range(R.q4.x, R.q4.y, a.W, c0, c1);
+            pix_range(R.q4.z, R.q4.w, a.H, r0, r1);
+            const int w = c1 - c0 + 1;
+            const int64_t area = (c1 >= c0 && r1 >= r0) ? (int64_t)w * (r1 - r0 + 1) : 0;
+            for (int64_t q = threadIdx.x; q < area; q += kBwdBlock) {
+                int r = r0 + (int)(q / w), c = c0 + (int)(q % w);
+                scan_pixel(a, R, vz, f, n, r, c, g);
+            }
+        }
+        float t[9] = {g.gx[0], g.gy[0], g.gzv[0], g.gx[1], g.gy[1], g.gzv[1], g.gx[2], g.gy[2], g.gzv[2]};
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            float v = t[j];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if ((threadIdx.x & 63) == 0) red[j][threadIdx.x >> 6] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < 9 && ok) {
+            float s = 0.0f;
+            for (int w4 = 0; w4 < kBwdBlock / 64; ++w4) s += red[threadIdx.x][w4];
+            int j = threadIdx.x / 3, x = threadIdx.x % 3;
+            atomicAdd(a.grad + 3 * (int64_t)vi[j] + x, s);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Binned form.  Pass 1: one workgroup per bin streams the slots of the bin's
+// pixels once (coalesced reads of pix_to_face and the gradients), maps each
+// slot's face to its index in the bin's face list through an LDS hash table,
+// and accumulates the nine coordinate sums per listed face in LDS as 64-bit
+// fixed-point integers (scale 2^32): integer LDS atomics are far cheaper than
+// float ones on this hardware, and the per-bin sums become exact and
+// independent of the order of the additions.  A contribution too large for
+// the fixed-point headroom goes to a float accumulator instead.  Each list
+// entry's nine sums are then written next to the entry (partial[bin][j],
+// coalesced, no global atomic).  Pass 2: one thread per face reads its (at
+// most four) partials through the positions the binning pass recorded,
+// merges per vertex in LDS and issues one atomic per (vertex, coordinate).
+// Faces spanning more than four bins take global atomics directly.
+// ---------------------------------------------------------------------------
+constexpr int kP1Threads = 256;
+constexpr int kP1Chunk = 160;    // faces staged in LDS per pass over a bin's slots
+constexpr int kP1Table = 512;    // LDS hash entries (>= 2 * kP1Chunk)
+constexpr int kP1Unroll = 4;     // slots per thread whose loads are issued together
+constexpr int kMaxPartials = 4;
+
+__device__ __forceinline__ uint32_t fhash(int f) { return ((uint32_t)f * 2654435761u) >> (32 - 9); }
+
+__device__ __forceinline__ void atomic_face(const BwdArgs& a, int f, const float* g9) {
+    const int32_t* fv = a.faces + 3 * (int64_t)f;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        int v = fv[j];
+        if (v < 0 || v >= a.V) continue;
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+            if (g9[3 * j + x] != 0.0f) atomicAdd(a.grad + 3 * (int64_t)v + x, g9[3 * j + x]);
+    }
+}
+
+// One 1024-thread workgroup per bin.  The bin's face list is taken in chunks
+// of kP1Chunk faces: the chunk's records go to LDS (one coalesced gather) with
+// a hash table from face id to chunk index, then every thread streams its
+// slots of the bin (kP1Unroll at a time, loads issued together), and the slots
+// whose face is in the chunk add their nine coordinate sums into the chunk's
+// LDS accumulators.  A bin of up to kP1Chunk faces -- most of them --
+// is one chunk and reads its slots once.
+constexpr double kFixScale = 4294967296.0;  // 2^32
+
+__global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a) {
+    __shared__ FaceRec srec[kP1Chunk];
+    __shared__ unsigned long long acci[kP1Chunk * 9];
+    __shared__ float acc[kP1Chunk * 9];
+    __shared__ int tkey[kP1Table];
+    __shared__ int tval[kP1Table];
+    const int64_t bin = blockIdx.x;
+    const int per_img = a.nby * a.nbx;
+    const int n = (int)(bin / per_img);
+    const int rem = (int)(bin - (int64_t)n * per_img);
+    const int by = rem / a.nbx, bx = rem - (rem / a.nbx) * a.nbx;
+    const int cnt = min(a.counts[bin], a.M);
+    const int* list = a.lists + bin * a.M;
+    const int r0 = by * a.bs, c0 = bx * a.bs;
+    const int rows = min(a.bs, a.H - r0), cols = min(a.bs, a.W - c0);
+    const int nslots = rows * cols * a.K;
+    for (int base = 0; base < cnt; base += kP1Chunk) {
+        const int m = min(kP1Chunk, cnt - base);
+        for (int i = threadIdx.x; i < kP1Table; i += kP1Threads) tkey[i] = -1;
+        for (int i = threadIdx.x; i < m * 9; i += kP1Threads) {
+            acc[i] = 0.0f;
+            acci[i] = 0ull;
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < m; j += kP1Threads) {
+            const int f = list[base + j];
+            srec[j] = a.recs[f];
+            uint32_t h = fhash(f);
+            for (int probe = 0; probe < kP1Table; ++probe) {
+                if (atomicCAS(&tkey[h], -1, f) == -1) {
+                    tval[h] = j;
+                    break;
+                }
+                h = (h + 1) & (kP1Table - 1);
+            }
+        }
+        __syncthreads();
+        for (int q0 = 0; q0 < nslots; q0 += kP1Unroll * kP1Threads) {
+            int fq[kP1Unroll];
+            int64_t sq[kP1Unroll];
+            int rq[kP1Unroll], cq[kP1Unroll];
+#pragma unroll
+            for (int u = 0; u < kP1Unroll; ++u) {
+                const int q = q0 + u * kP1Threads + threadIdx.x;
+                fq[u] = -1;
+                if (q < nslots) {
+                    const int pl = q / a.K, k = q - pl * a.K;
+                    const int pr = pl / cols;
+                    rq[u] = r0 + pr;
+                    cq[u] = c0 + (pl - pr * cols);
+                    sq[u] = (((int64_t)n * a.H + rq[u]) * a.W + cq[u]) * a.K + k;
+                    fq[u] = a.p2f[sq[u]];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kP1Unroll; ++u) {
+                const int f = fq[u];
+                if (f < 0) continue;
+                int j = -1;
+                uint32_t h = fhash(f);
+                for (int probe = 0; probe < kP1Table; ++probe) {
+                    const int key = tkey[h];
+                    if (key == f) {
+                        j = tval[h];
+                        break;
+                    }
+                    if (key == -1) break;
+                    h = (h + 1) & (kP1Table - 1);
+                }
+                if (j < 0) continue;
+                const FaceRec R = srec[j];
+                const float vz[3] = {R.q3.x, R.q3.x + R.q3.y, R.q3.x + R.q3.z};
+                FaceGrad g;
+#pragma unroll
+                for (int jj = 0; jj < 3; ++jj) g.gx[jj] = g.gy[jj] = g.gzv[jj] = 0.0f;
+                slot_grad(a, R, vz, make_pix(rq[u], cq[u], a.H, a.W), sq[u], g);
+                const float g9[9] = {g.gx[0], g.gy[0], g.gzv[0], g.gx[1], g.gy[1], g.gzv[1], g.gx[2], g.gy[2],
+                                     g.gzv[2]};
+#pragma unroll
+                for (int x = 0; x < 9; ++x) {
+                    const float v = g9[x];
+                    if (fabsf(v) < a.fix_limit) {
+                        atomicAdd(&acci[9 * j + x], (unsigned long long)__double2ll_rn((double)v * kFixScale));
+                    } else {
+                        atomicAdd(&acc[9 * j + x], v);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // flush: one partial per listed face; every listed face writes one, so
+        // the face pass never reads an unwritten partial (unless the bin
+        // overflowed, which the status word reports)
+        for (int j = threadIdx.x; j < m; j += kP1Threads) {
+            const int f = list[base + j];
+            int bx0, bx1, by0, by1;
+            if (!face_bins(srec[j], a.H, a.W, a.bs, bx0, bx1, by0, by1)) continue;
+            const int nb = (bx1 - bx0 + 1) * (by1 - by0 + 1);
+            float g9[9];
+#pragma unroll
+            for (int x = 0; x < 9; ++x)
+                g9[x] = (float)((double)(long long)acci[9 * j + x] * (1.0 / kFixScale)) + acc[9 * j + x];
+            if (nb <= kMaxPartials) {
+                float* dst = a.partial + (bin * a.M + base + j) * 9;
+#pragma unroll
+                for (int x = 0; x < 9; ++x) dst[x] = g9[x];
+            } else {
+                atomic_face(a, f, g9);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBwdBlock) void bwd_face_sum_kernel(BwdArgs a) {
+    __shared__ int keys[kHash];
+    __shared__ float vals[3 * kHash];
+    for (int i = threadIdx.x; i < kHash; i += kBwdBlock) {
+        keys[i] = -1;
+        vals[3 * i] = vals[3 * i + 1] = vals[3 * i + 2] = 0.0f;
+    }
+    __syncthreads();
+    const int64_t f = (int64_t)blockIdx.x * kBwdBlock + threadIdx.x;
+    const bool overflowed = (a.hdr[kHdrStatus] & kStatOverflow) != 0;
+    if (f < a.F && !overflowed) {
+        const FaceRec R = a.recs[f];
+        int bx0, bx1, by0, by1;
+        if (face_bins(R, a.H, a.W, a.bs, bx0, bx1, by0, by1)) {
+            const int nbw = bx1 - bx0 + 1;
+            const int nb = nbw * (by1 - by0 + 1);
+            if (nb <= kMaxPartials) {
+                const int n = R.mesh();
+                float g9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                for (int i = 0; i < nb; ++i) {
+                    const int64_t bin = ((int64_t)n * a.nby + by0 + i / nbw) * a.nbx + bx0 + i % nbw;
+                    const int pos = a.fpos[4 * f + i];
+                    if (pos < 0 || pos >= a.M) continue;  // cannot happen without an overflow
+                    const float* src = a.partial + (bin * a.M + pos) * 9;
+#pragma unroll
+                    for (int x = 0; x < 9; ++x) g9[x] += src[x];
+                }
+                const int32_t* fv = a.faces + 3 * f;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    int v = fv[j];
+                    if (v >= 0 && v < a.V) lds_add(keys, vals, a.grad, v, g9[3 * j], g9[3 * j + 1], g9[3 * j + 2]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kHash; i += kBwdBlock) {
+        int v = keys[i];
+        if (v >= 0) {
+            atomicAdd(a.grad + 3 * (int64_t)v + 0, vals[3 * i + 0]);
+            atomicAdd(a.grad + 3 * (int64_t)v + 1, vals[3 * i + 1]);
+            atomicAdd(a.grad + 3 * (int64_t)v + 2, vals[3 * i + 2]);
+        }
+    }
+}
+
+hipError_t launch_backward(const float* verts, int64_t V, const int32_t* faces, int64_t F, const int64_t* first,
+                           const int64_t* nf, int N, int H, int W, int K, float blur, int bs, int M,
                            const int32_t* p2f, const float* gz, const float* gb, const float* gd, float* grad,
+                           int* hdr, FaceRec* recs, int* counts, int* lists, float* partial, int* fpos, int* big,
                            hipStream_t s, hipEvent_t eb, hipEvent_t ee) {
     hipError_t e = launch_fill_f32(grad, V * 3, 0.0f, s);
     if (e != hipSuccess) return e;
+    e = launch_fill_i32(hdr, kHdrWords, 0, s);
+    if (e != hipSuccess) return e;
+    if (F == 0) return hipSuccess;
     BwdArgs a;
     a.verts = verts;
     a.faces = faces;
+    a.first = first;
+    a.nf = nf;
     a.p2f = p2f;
     a.gz = gz;
     a.gb = gb;
     a.gd = gd;
     a.grad = grad;
-    a.S = (int64_t)N * H * W * K;
+    a.hdr = hdr;
+    a.big = big;
     a.V = V;
     a.F = F;
+    a.N = N;
     a.H = H;
     a.W = W;
     a.K = K;
-    if (a.S == 0) return hipSuccess;
-    if (eb) hipEventRecord(eb, s);
-    hipLaunchKernelGGL(raster_bwd_kernel, dim3((unsigned)((a.S + 255) / 256)), dim3(256), 0, s, a);
-    if (ee) hipEventRecord(ee, s);
+    a.rb = sqrtf(blur);
+    a.recs = recs;
+    a.counts = counts;
+    a.lists = lists;
+    a.partial = partial;
+    a.fpos = fpos;
+    a.bs = bs;
+    // a face appears in at most bs*bs slots of a bin, each below fix_limit, so
+    // a 64-bit sum of fixed-point values (scale 2^32) stays below 2^62
+    {
+        int lg = 0;
+        while ((1 << lg) < bs) ++lg;
+        a.fix_limit = ldexpf(1.0f, 30 - 2 * lg);
+    }
+    a.nby = bs > 0 ? (H + bs - 1) / bs : 0;
+    a.nbx = bs > 0 ? (W + bs - 1) / bs : 0;
+    a.M = M;
+    if (bs > 0) {
+        // the same face setup and binning as the forward, then the two passes
+        e = launch_face_setup(verts, V, faces, F, first, nf, N, a.rb, recs, hdr, s);
+        if (e != hipSuccess) return e;
+        e = launch_binning(recs, F, N, H, W, bs, M, counts, lists, hdr, s, fpos);
+        if (e != hipSuccess) return e;
+        const int64_t nbins = (int64_t)N * a.nby * a.nbx;
+        if (eb) (void)hipEventRecord(eb, s);
+        hipLaunchKernelGGL(bwd_bins_kernel, dim3((unsigned)nbins), dim3(kP1Threads), 0, s, a);
+        hipLaunchKernelGGL(bwd_face_sum_kernel, dim3((unsigned)((F + kBwdBlock - 1) / kBwdBlock)), dim3(kBwdBlock), 0,
+                           s, a);
+        if (ee) (void)hipEventRecord(ee, s);
+        return hipGetLastError();
+    }
+    if (eb) (void)hipEventRecord(eb, s);
+    hipLaunchKernelGGL(bwd_faces_kernel, dim3((unsigned)((F + kBwdBlock - 1) / kBwdBlock)), dim3(kBwdBlock), 0, s, a);
+    hipLaunchKernelGGL(bwd_big_faces_kernel, dim3(512), dim3(kBwdBlock), 0, s, a);
+    if (ee) (void)hipEventRecord(ee, s);
     return hipGetLastError();
 }
 

@@ -48,23 +48,6 @@ hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Mesh of face f: the last n with first[n] <= f, if f lies in its range.
-__device__ __forceinline__ int find_mesh(const int64_t* __restrict__ first, const int64_t* __restrict__ nf, int N,
-                                         int64_t f) {
-    int lo = 0, hi = N - 1, ans = -1;
-    while (lo <= hi) {
-        int mid = (lo + hi) >> 1;
-        if (first[mid] <= f) {
-            ans = mid;
-            lo = mid + 1;
-        } else {
-            hi = mid - 1;
-        }
-    }
-    if (ans >= 0 && f < first[ans] + nf[ans]) return ans;
-    return -1;
-}
-
 __global__ void face_setup_kernel(const float* __restrict__ verts, int64_t V, const int32_t* __restrict__ faces,
                                   int64_t F, const int64_t* __restrict__ first, const int64_t* __restrict__ nf, int N,
                                   float rb, FaceRec* __restrict__ recs, int* __restrict__ hdr) {
@@ -104,37 +87,49 @@ hipError_t launch_face_setup(const float* verts, int64_t V, const int32_t* faces
     return hipGetLastError();
 }
 
-// Inclusive pixel range [lo, hi] whose centres may fall in [vmin, vmax] along
-// one axis of `size` pixels (centre of pixel i at 1 - (2i+1)/size), grown by
-// one pixel each way to absorb rounding; empty when hi < lo.
-__device__ __forceinline__ void pix_range(float vmin, float vmax, int size, int& lo, int& hi) {
-    float a = ((float)size * (1.0f - vmax) - 1.0f) * 0.5f;
-    float b = ((float)size * (1.0f - vmin) - 1.0f) * 0.5f;
-    a = fminf(fmaxf(a, -2.0f), (float)size + 1.0f);
-    b = fminf(fmaxf(b, -2.0f), (float)size + 1.0f);
-    lo = (int)floorf(a) - 1;
-    hi = (int)ceilf(b) + 1;
-    if (lo < 0) lo = 0;
-    if (hi > size - 1) hi = size - 1;
-}
-
-__global__ void bin_faces_kernel(const FaceRec* __restrict__ recs, int64_t F, int H, int W, int bs, int nby, int nbx,
-                                 int M, int* __restrict__ counts, int* __restrict__ lists) {
-    int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= F) return;
-    FaceRec R = recs[f];
-    if (!R.ok()) return;
-    int n = R.mesh();
-    int c0, c1, r0, r1;
-    pix_range(R.q4.x, R.q4.y, W, c0, c1);
-    pix_range(R.q4.z, R.q4.w, H, r0, r1);
-    if (c1 < c0 || r1 < r0) return;
-    int bx0 = c0 / bs, bx1 = c1 / bs, by0 = r0 / bs, by1 = r1 / bs;
-    for (int by = by0; by <= by1; ++by) {
-        for (int bx = bx0; bx <= bx1; ++bx) {
-            int64_t bin = ((int64_t)n * nby + by) * nbx + bx;
-            int pos = atomicAdd(&counts[bin], 1);
-            if (lists != nullptr && pos < M) lists[bin * M + pos] = (int)f;
+// One thread per face appends the face to every bin of its range.  Lanes of a
+// wave hold consecutive faces, which are usually neighbours on the mesh and
+// share bins, so the appends are aggregated per wave: for each distinct bin
+// among the active lanes one lane reserves room for all of them with a single
+// atomic and each lane takes its rank among them.  With fpos, a face whose
+// range has at most four bins also records its position in each of them
+// (fpos[4f + i] for the i-th bin of its range, row-major), which the
+// backward uses to find the face's per-bin partial sums.
+__global__ __launch_bounds__(256) void bin_faces_kernel(const FaceRec* __restrict__ recs, int64_t F, int H, int W,
+                                                        int bs, int nby, int nbx, int M, int* __restrict__ counts,
+                                                        int* __restrict__ lists, int* __restrict__ fpos) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int n = 0, bx0 = 0, by0 = 0, nbw = 1, nb = 0;
+    if (f < F) {
+        FaceRec R = recs[f];
+        int bx1, by1;
+        if (face_bins(R, H, W, bs, bx0, bx1, by0, by1)) {
+            n = R.mesh();
+            nbw = bx1 - bx0 + 1;
+            nb = nbw * (by1 - by0 + 1);
+        }
+    }
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int i = 0;; ++i) {
+        const bool act = i < nb;
+        uint64_t pending = __ballot(act);
+        if (pending == 0) break;
+        int64_t bin = -1;
+        if (act) bin = ((int64_t)n * nby + by0 + i / nbw) * nbx + bx0 + i % nbw;
+        while (pending) {
+            const int leader = __ffsll((unsigned long long)pending) - 1;
+            const int64_t lb = __shfl(bin, leader);
+            const uint64_t same = __ballot(act && bin == lb);
+            int base = 0;
+            if (lane == leader) base = atomicAdd(&counts[lb], __popcll(same));
+            base = __shfl(base, leader);
+            if (act && bin == lb) {
+                const int pos = base + __popcll(same & lt_mask);
+                if (lists != nullptr && pos < M) lists[lb * M + pos] = (int)f;
+                if (fpos != nullptr && nb <= 4) fpos[4 * f + i] = pos;
+            }
+            pending &= ~same;
         }
     }
 }
@@ -153,14 +148,14 @@ __global__ void bin_max_kernel(const int* __restrict__ counts, int64_t nbins, in
 }
 
 hipError_t launch_binning(const FaceRec* recs, int64_t F, int N, int H, int W, int bs, int M, int* counts, int* lists,
-                          int* hdr, hipStream_t s) {
+                          int* hdr, hipStream_t s, int* fpos) {
     int nby = (H + bs - 1) / bs, nbx = (W + bs - 1) / bs;
     int64_t nbins = (int64_t)N * nby * nbx;
     hipError_t e = launch_fill_i32(counts, nbins, 0, s);
     if (e != hipSuccess) return e;
     if (F > 0) {
         hipLaunchKernelGGL(bin_faces_kernel, dim3((unsigned)((F + 255) / 256)), dim3(256), 0, s, recs, F, H, W, bs, nby,
-                           nbx, M, counts, lists);
+                           nbx, M, counts, lists, fpos);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -192,8 +187,27 @@ struct FineArgs {
     float* dists;
 };
 
+// LDS of one tile's wave: a chunk of up to 64 candidate faces that overlap the
+// tile, and per lane the indices (within the chunk) of the faces whose boxes
+// contain the lane's pixel.
+constexpr int kChunk = 64;
+struct TileLds {
+    FaceRec rec[kChunk];
+    int id[kChunk];
+    unsigned char lst[64 * kChunk];
+};
+
+// One wave rasterizes one 8x8 tile in three steps per chunk of 64 faces:
+//  1. gather the chunk's face records, keep those whose box overlaps the tile
+//     (wave ballot + prefix count compacts them into LDS);
+//  2. every lane tests its pixel against each kept face's box (a broadcast
+//     LDS read) and appends the hits to its own list;
+//  3. every lane walks only its own list, runs the full test and inserts the
+//     faces that count into its register top-K.
+// Step 3 is where the arithmetic is; compacting the (pixel, face) pairs first
+// keeps lanes from idling on faces that miss their pixel.
 template <int KB, bool BINNED>
-__device__ __forceinline__ void raster_tile(const FineArgs& a, int n, int tx, int ty) {
+__device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n, int tx, int ty) {
     const int lane = threadIdx.x & 63;
     const int r = ty * kTile + (lane >> 3);
     const int c = tx * kTile + (lane & 7);
@@ -204,6 +218,7 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, int n, int tx, in
     const int r_last = min(ty * kTile + kTile - 1, a.H - 1);
     const float tx_hi = pix_x(tx * kTile, a.W), tx_lo = pix_x(c_last, a.W);
     const float ty_hi = pix_y(ty * kTile, a.H), ty_lo = pix_y(r_last, a.H);
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     TopK<KB> top;
     top.init();
@@ -222,12 +237,39 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, int n, int tx, in
         base = lo;
         cnt = hi > lo ? hi - lo : 0;
     }
-    for (int64_t j = 0; j < cnt; ++j) {
-        const int fid = BINNED ? list[j] : (int)(base + j);
-        const FaceRec R = a.recs[fid];
-        if (R.q4.y < tx_lo || R.q4.x > tx_hi || R.q4.w < ty_lo || R.q4.z > ty_hi) continue;
-        float z;
-        if (live && face_counts(R, p, a.blur, z)) top.insert(make_key(z, fid));
+    unsigned char* mylst = L.lst + lane * kChunk;
+    for (int64_t c0 = 0; c0 < cnt; c0 += kChunk) {
+        // 1. gather and compact the chunk's faces that overlap the tile
+        const int64_t e = c0 + lane;
+        const bool in_list = e < cnt;
+        const int fid = in_list ? (BINNED ? list[e] : (int)(base + e)) : 0;
+        const FaceRec R = a.recs[in_list ? fid : (BINNED ? list[0] : (int)base)];
+        const bool keep =
+            in_list && !(R.q4.y < tx_lo || R.q4.x > tx_hi || R.q4.w < ty_lo || R.q4.z > ty_hi);
+        const uint64_t kept = __ballot(keep);
+        const int m = __popcll(kept);
+        if (keep) {
+            const int dst = __popcll(kept & lt_mask);
+            L.rec[dst] = R;
+            L.id[dst] = fid;
+        }
+        __syncthreads();
+        // 2. per-lane lists of the faces whose boxes contain the lane's pixel
+        int nl = 0;
+        for (int j = 0; j < m; ++j) {
+            const float4 bb = L.rec[j].q4;
+            if (live && p.x >= bb.x && p.x <= bb.y && p.y >= bb.z && p.y <= bb.w) mylst[nl++] = (unsigned char)j;
+        }
+        // 3. full test of the lane's own candidates
+        for (int i = 0; __any(i < nl); ++i) {
+            if (i < nl) {
+                const int j = mylst[i];
+                const FaceRec Rj = L.rec[j];
+                float z;
+                if (face_counts(Rj, p, a.blur, z)) top.insert(make_key(z, L.id[j]));
+            }
+        }
+        __syncthreads();
     }
     if (!live) return;
     const int64_t pix = ((int64_t)n * a.H + r) * a.W + c;
@@ -262,7 +304,8 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, int n, int tx, in
 
 template <int KB, bool BINNED>
 __global__ __launch_bounds__(64) void raster_tiles_kernel(FineArgs a) {
-    raster_tile<KB, BINNED>(a, blockIdx.z, blockIdx.x, blockIdx.y);
+    __shared__ TileLds L;
+    raster_tile<KB, BINNED>(a, L, blockIdx.z, blockIdx.x, blockIdx.y);
 }
 
 // Persistent form: a device-sized grid; each wave pulls the next tile id from
@@ -272,6 +315,7 @@ __global__ __launch_bounds__(64) void raster_tiles_kernel(FineArgs a) {
 template <int KB>
 __global__ __launch_bounds__(64) void raster_persistent_kernel(FineArgs a, const int* __restrict__ order,
                                                                int* __restrict__ hdr, int total) {
+    __shared__ TileLds L;
     for (;;) {
         int item = 0;
         if ((threadIdx.x & 63) == 0) item = atomicAdd(&hdr[kHdrWorkNext], 1);
@@ -283,7 +327,7 @@ __global__ __launch_bounds__(64) void raster_persistent_kernel(FineArgs a, const
         int rem = t - n * per_img;
         int ty = rem / a.tiles_x;
         int tx = rem - ty * a.tiles_x;
-        raster_tile<KB, true>(a, n, tx, ty);
+        raster_tile<KB, true>(a, L, n, tx, ty);
     }
 }
 
@@ -350,18 +394,18 @@ static hipError_t launch_fine_k(const FineArgs& a, bool binned, int sched, int* 
         hipLaunchKernelGGL(order_scatter_kernel, dim3(g), dim3(256), 0, s, a.counts, a.N, a.tiles_x, a.tiles_y, a.bs,
                            a.nby, a.nbx, a.M, hist, order);
         int workers = n_workers < total ? n_workers : total;
-        if (eb) hipEventRecord(eb, s);
+        if (eb) (void)hipEventRecord(eb, s);
         hipLaunchKernelGGL(raster_persistent_kernel<KB>, dim3(workers), dim3(64), 0, s, a, order, hdr, total);
-        if (ee) hipEventRecord(ee, s);
+        if (ee) (void)hipEventRecord(ee, s);
         return hipGetLastError();
     }
     dim3 grid(a.tiles_x, a.tiles_y, a.N);
-    if (eb) hipEventRecord(eb, s);
+    if (eb) (void)hipEventRecord(eb, s);
     if (binned)
         hipLaunchKernelGGL((raster_tiles_kernel<KB, true>), grid, dim3(64), 0, s, a);
     else
         hipLaunchKernelGGL((raster_tiles_kernel<KB, false>), grid, dim3(64), 0, s, a);
-    if (ee) hipEventRecord(ee, s);
+    if (ee) (void)hipEventRecord(ee, s);
     return hipGetLastError();
 }
 

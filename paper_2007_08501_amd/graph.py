@@ -37,8 +37,8 @@ class GraphRunner:
             self.grad_bary = torch.zeros((N, H, W, K, 3), device=dev)
             self.grad_dists = torch.zeros((N, H, W, K), device=dev)
             self.grad_verts = torch.empty_like(self.verts)
-            self.bws = torch.empty(_lib.rast_workspace_size(N, H, W, self.faces.shape[0], 0, 0), dtype=torch.uint8,
-                                   device=dev)
+            self.bws = torch.empty(_lib.rast_workspace_size(N, H, W, self.faces.shape[0], bin_size,
+                                                            max_faces_per_bin), dtype=torch.uint8, device=dev)
         self.graph = None
 
     def set_verts(self, verts):
@@ -55,8 +55,9 @@ class GraphRunner:
         _lib.rasterize_meshes_fwd(self.verts, self.faces, self.first_idx, self.num_faces, H, W, blur, K, bs, M, sched,
                                   self.out.pix_to_face, self.out.zbuf, self.out.bary, self.out.dists, self.ws)
         if self.backward:
-            _lib.rasterize_meshes_bwd(self.verts, self.faces, N, H, W, K, self.out.pix_to_face, self.grad_zbuf,
-                                      self.grad_bary, self.grad_dists, self.grad_verts, self.bws)
+            _lib.rasterize_meshes_bwd(self.verts, self.faces, self.first_idx, self.num_faces, H, W, blur, K, bs, M,
+                                      self.out.pix_to_face, self.grad_zbuf, self.grad_bary, self.grad_dists,
+                                      self.grad_verts, self.bws)
 
     def capture(self, warmup: int = 2):
         s = torch.cuda.Stream(device=self.device)

@@ -111,23 +111,26 @@ class _RasterizeMeshes(torch.autograd.Function):
                 raise BinOverflow(f"a bin received {mx} faces > max_faces_per_bin={M}")
             if st != _lib.RAST_OK:
                 raise _lib.RastError("rasterize_meshes_fwd", st, _lib.status_string(st))
-        ctx.save_for_backward(vd, faces, out.pix_to_face)
+        ctx.save_for_backward(vd, faces, first_idx, num_faces, out.pix_to_face)
         ctx.mark_non_differentiable(out.pix_to_face)
         ctx.dims = (N, H, W, K)
+        ctx.blur = blur
+        ctx.bins = (bs, M)
         return out.pix_to_face, out.zbuf, out.bary, out.dists
 
     @staticmethod
     def backward(ctx, _g_p2f, g_zbuf, g_bary, g_dists):
-        verts, faces, p2f = ctx.saved_tensors
+        verts, faces, first_idx, num_faces, p2f = ctx.saved_tensors
         N, H, W, K = ctx.dims
 
         def prep(g):
             return None if g is None else g.contiguous().to(torch.float32)
 
         grad_verts = torch.empty_like(verts)
-        ws = workspace(verts.device, _lib.rast_workspace_size(N, H, W, faces.shape[0], 0, 0))
-        _lib.rasterize_meshes_bwd(verts, faces, N, H, W, K, p2f, prep(g_zbuf), prep(g_bary), prep(g_dists),
-                                  grad_verts, ws)
+        bs, M = ctx.bins
+        ws = workspace(verts.device, _lib.rast_workspace_size(N, H, W, faces.shape[0], bs, M))
+        _lib.rasterize_meshes_bwd(verts, faces, first_idx, num_faces, H, W, ctx.blur, K, bs, M, p2f, prep(g_zbuf),
+                                  prep(g_bary), prep(g_dists), grad_verts, ws)
         return (grad_verts,) + (None,) * 11
 
 

@@ -45,11 +45,7 @@ def run_fwd(b, bs, M=None, sched=0, K=None, dev_inputs=None, check=True):
     K = K or b.faces_per_pixel
     N = fi.shape[0]
     if bs > 0 and M is None:
-        wsc = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, f.shape[0], bs, 1), v.device)
-        _lib.rast_bin_count(v, f, fi, nf, H, W, b.blur_radius, bs, wsc)
-        st, mx = _lib.rast_query_status(wsc)
-        assert st == _lib.RAST_OK
-        M = max(1, mx)
+        M = bin_capacity(b, bs, (v, f, fi, nf))
     out = empty_fragments(N, H, W, K, v.device)
     ws = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, f.shape[0], bs, M or 0), v.device)
     _lib.rasterize_meshes_fwd(v, f, fi, nf, H, W, b.blur_radius, K, bs, M or 0, sched, out.pix_to_face, out.zbuf,
@@ -60,14 +56,32 @@ def run_fwd(b, bs, M=None, sched=0, K=None, dev_inputs=None, check=True):
     return out, ws
 
 
-def run_bwd(b, p2f, gz, gb, gd, dev_inputs=None):
+def bin_capacity(b, bs, dev_inputs=None):
+    """Exact largest bin count for bin size bs (counting pass)."""
+    v, f, fi, nf = dev_inputs or to_dev(b)
+    H, W = b.image_size
+    wsc = _lib.alloc_workspace(_lib.rast_workspace_size(fi.shape[0], H, W, f.shape[0], bs, 1), v.device)
+    _lib.rast_bin_count(v, f, fi, nf, H, W, b.blur_radius, bs, wsc)
+    st, mx = _lib.rast_query_status(wsc)
+    assert st == _lib.RAST_OK
+    return max(1, mx)
+
+
+def run_bwd(b, p2f, gz, gb, gd, dev_inputs=None, bs=0, M=None, check=True):
+    """Backward through the C ABI; bs/M are the binning of the forward
+    (bs 0 = per-face form)."""
     v, f, fi, nf = dev_inputs or to_dev(b)
     H, W = b.image_size
     N, K = p2f.shape[0], p2f.shape[-1]
+    if bs > 0 and M is None:
+        M = bin_capacity(b, bs, (v, f, fi, nf))
     gv = torch.empty_like(v)
-    ws = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, f.shape[0], 0, 0), v.device)
+    ws = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, f.shape[0], bs, M or 0), v.device)
     t = lambda a: None if a is None else (a if isinstance(a, torch.Tensor) else torch.from_numpy(a).to(v.device))
-    _lib.rasterize_meshes_bwd(v, f, N, H, W, K, p2f, t(gz), t(gb), t(gd), gv, ws)
+    _lib.rasterize_meshes_bwd(v, f, fi, nf, H, W, b.blur_radius, K, bs, M or 0, p2f, t(gz), t(gb), t(gd), gv, ws)
+    if check:
+        st, _ = _lib.rast_query_status(ws)
+        assert st == _lib.RAST_OK, _lib.status_string(st)
     torch.cuda.synchronize()
     return gv
 

@@ -141,47 +141,43 @@ def sampled_check(i, bs, n_pix=1500, seed=0):
     return b, d, out
 
 
-def test_cfg2_full_size_sampled_and_backward():
-    b, d, out = sampled_check(2, 32)
+def full_backward_check(b, d, out, bins):
     gz, gb, gd = meshgen.upstream_grads(b)
     p2f = out.pix_to_face.cpu().numpy()
     gz, gb, gd = tie_masked_grads(b, p2f, gz, gb, gd)
-    gv = run_bwd(b, out.pix_to_face, gz, gb, gd, dev_inputs=d).cpu().numpy()
     ref = oracle.backward(b.verts, b.faces, b.image_size, p2f, gz, gb, gd, nthreads=threads())
-    log("cfg2 grad rel err", compare_grad(gv, ref, "cfg2"))
+    for bs in bins:
+        gv = run_bwd(b, out.pix_to_face, gz, gb, gd, dev_inputs=d, bs=bs).cpu().numpy()
+        log(f"{b.name} bs{bs} grad rel err", compare_grad(gv, ref, f"{b.name} bs{bs}"))
+
+
+def test_cfg2_full_size_sampled_and_backward():
+    b, d, out = sampled_check(2, 32)
+    full_backward_check(b, d, out, (0, 8, 16))
 
 
 def test_cfg3_full_size_sampled_and_backward():
     b, d, out = sampled_check(3, 16)
-    gz, gb, gd = meshgen.upstream_grads(b)
-    p2f = out.pix_to_face.cpu().numpy()
-    gz, gb, gd = tie_masked_grads(b, p2f, gz, gb, gd)
-    gv = run_bwd(b, out.pix_to_face, gz, gb, gd, dev_inputs=d).cpu().numpy()
-    ref = oracle.backward(b.verts, b.faces, b.image_size, p2f, gz, gb, gd, nthreads=threads())
-    log("cfg3 grad rel err", compare_grad(gv, ref, "cfg3"))
+    full_backward_check(b, d, out, (0, 8, 16))
 
 
 def test_cfg4_full_size_sampled_and_backward():
     b, d, out = sampled_check(4, 16, n_pix=800)
-    gz, gb, gd = meshgen.upstream_grads(b)
-    p2f = out.pix_to_face.cpu().numpy()
-    gz, gb, gd = tie_masked_grads(b, p2f, gz, gb, gd)
-    gv = run_bwd(b, out.pix_to_face, gz, gb, gd, dev_inputs=d).cpu().numpy()
-    ref = oracle.backward(b.verts, b.faces, b.image_size, p2f, gz, gb, gd, nthreads=threads())
-    log("cfg4 grad rel err", compare_grad(gv, ref, "cfg4"))
+    full_backward_check(b, d, out, (0, 8, 16))
 
 
 # ----------------------------------------------------------------- backward
 
+@pytest.mark.parametrize("bs", [0, 8, 16, 32])
 @pytest.mark.parametrize("which", ["zbuf", "bary", "dists", "all"])
-def test_backward_vs_oracle_small(which):
+def test_backward_vs_oracle_small(which, bs):
     b = meshgen.make_config(2, n_override=3, level_override=3, image_override=64)
     out, _ = run_fwd(b, 16)
     p2f = out.pix_to_face.cpu().numpy()
     gz, gb, gd = meshgen.upstream_grads(b)
     gz, gb, gd = tie_masked_grads(b, p2f, gz, gb, gd)
     sel = dict(zbuf=(gz, None, None), bary=(None, gb, None), dists=(None, None, gd), all=(gz, gb, gd))[which]
-    gv = run_bwd(b, out.pix_to_face, *sel).cpu().numpy()
+    gv = run_bwd(b, out.pix_to_face, *sel, bs=bs).cpu().numpy()
     ref = oracle.backward(b.verts, b.faces, b.image_size, p2f, *sel, nthreads=threads())
     compare_grad(gv, ref, which)
 
@@ -199,11 +195,12 @@ def test_backward_hand_case():
     p2f[0, 2, 2, 0] = 0
     one = torch.zeros((1, 4, 4, 1), device="cuda")
     one[0, 2, 2, 0] = 1
-    g = run_bwd(b, p2f, None, None, one).cpu().numpy()
-    np.testing.assert_allclose(g, [[0, 0, 0], [-0.25, -0.25, 0], [-0.25, -0.25, 0]], atol=1e-6)
-    g = run_bwd(b, p2f, one, None, None).cpu().numpy()
-    np.testing.assert_allclose(g, [[-0.125, -0.25, 0.25], [-0.1875, -0.375, 0.375], [-0.1875, -0.375, 0.375]],
-                               atol=1e-6)
+    for bs in (0, 8):
+        g = run_bwd(b, p2f, None, None, one, bs=bs).cpu().numpy()
+        np.testing.assert_allclose(g, [[0, 0, 0], [-0.25, -0.25, 0], [-0.25, -0.25, 0]], atol=1e-6)
+        g = run_bwd(b, p2f, one, None, None, bs=bs).cpu().numpy()
+        np.testing.assert_allclose(g, [[-0.125, -0.25, 0.25], [-0.1875, -0.375, 0.375], [-0.1875, -0.375, 0.375]],
+                                   atol=1e-6)
 
 
 def test_autograd_matches_abi():
@@ -215,7 +212,7 @@ def test_autograd_matches_abi():
     gz, gb, gd = [torch.from_numpy(x).cuda() for x in meshgen.upstream_grads(b)]
     loss = (frags.zbuf * gz).sum() + (frags.bary * gb).sum() + (frags.dists * gd).sum()
     loss.backward()
-    direct = run_bwd(b, frags.pix_to_face, gz, gb, gd)
+    direct = run_bwd(b, frags.pix_to_face, gz, gb, gd, bs=16)
     # float atomics accumulate in a different order on each call
     scale = float(direct.abs().max())
     torch.testing.assert_close(vv.grad, direct, rtol=0, atol=1e-5 * scale)
