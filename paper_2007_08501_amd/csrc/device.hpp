@@ -1,4 +1,4 @@
-// device.hpp -- per-face and per-pixel arithmetic of the rasterizer, FP32, gfx950.
+// device.hpp -- per-face and per-pixel arithmetic of the rasterizer for gfx950.
 //
 // Everything that decides whether a face counts for a pixel, and the values
 // written for it, lives here so that the single-pass and the binned forward
@@ -8,13 +8,13 @@
 //
 // Accuracy.  Faces seen edge-on (near a silhouette) project to slivers whose
 // doubled area E is tiny, and a barycentric w_i = e_i / E amplifies any error
-// of the edge function e_i by 1/E.  FP32 rounding of a pixel-to-vertex offset
-// or of an edge vector is then far above the 1e-5 target, so both are carried
-// exactly as unevaluated sums hi + lo (Knuth's two-sum), the edge functions
-// are formed as Kahan FMA differences of products of the hi parts plus
-// first-order corrections from the lo parts, and the third barycentric comes
-// from E - e1 - e2.  Each w_i is then accurate to a few units in the last
-// place of max(1, abs(w_i)), whatever the shape of the face.
+// of the edge function e_i by 1/E.  The edge functions are therefore formed
+// in FP64 from exact operands: the vertex offsets b - a, c - a of FP32
+// vertices and the pixel offset p - a are exact in FP64, leaving one rounding
+// of 2^-53 per product, far below what an FP32 barycentric can show.  On
+// CDNA vector FP64 issues at the same rate as non-packed FP32, so this costs
+// fewer instructions than compensated FP32 arithmetic.  Everything else
+// (depth, distances, the backward's chain rule) is FP32.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,7 +22,7 @@
 
 namespace rast {
 
-constexpr float kEpsArea = 1e-8f;  // faces with abs(2 * signed area) below this never count
+constexpr double kEpsArea = 1e-8;  // faces with abs(2 * signed area) below this never count
 constexpr int kTile = 8;           // forward work unit: 8x8 pixels = one wave64
 
 // Workspace header (int32 words); the header occupies the first 256 bytes.
@@ -37,101 +37,71 @@ enum : int {
 };
 enum : int { kStatOverflow = 1, kStatMesh = 2 };
 
-// x = hi + lo exactly, hi = fl(a - b) (Knuth's two-sum applied to a + (-b)).
-__device__ __forceinline__ void two_diff(float a, float b, float& hi, float& lo) {
-    float s = a - b;
-    float bb = s - a;
-    lo = (a - (s - bb)) - (b + bb);
-    hi = s;
-}
-
-// Pixel centre in NDC as an unevaluated sum hi + lo:
-// x = 1 - (2c+1)/W, y = 1 - (2r+1)/H.  lo is 0 for power-of-two sizes.
-__device__ __forceinline__ void pix_center(int c, int W, float& hi, float& lo) {
-    float num = (float)(2 * c + 1);
-    float q = num / (float)W;                // correctly rounded quotient
-    float rem = fmaf(-q, (float)W, num);     // exact remainder num - q*W
-    float h, l;
-    two_diff(1.0f, q, h, l);
-    hi = h;
-    lo = l - rem / (float)W;
-}
-// Rounded pixel centre (equal to hi above); used for tile extents and culls.
+// Pixel centre in NDC: x = 1 - (2c+1)/W, y = 1 - (2r+1)/H.  The FP32 value
+// (exact for power-of-two sizes) is used for box tests and tile extents, the
+// FP64 value for edge functions.
 __device__ __forceinline__ float pix_x(int c, int W) { return 1.0f - (float)(2 * c + 1) / (float)W; }
 __device__ __forceinline__ float pix_y(int r, int H) { return 1.0f - (float)(2 * r + 1) / (float)H; }
 
 struct Pix {
-    float x, y, xl, yl;  // centre hi parts and lo parts
+    float xf, yf;  // FP32 centre
+    double x, y;   // FP64 centre
 };
 __device__ __forceinline__ Pix make_pix(int r, int c, int H, int W) {
     Pix p;
-    pix_center(c, W, p.x, p.xl);
-    pix_center(r, H, p.y, p.yl);
+    p.xf = pix_x(c, W);
+    p.yf = pix_y(r, H);
+    p.x = 1.0 - (double)(2 * c + 1) / (double)W;
+    p.y = 1.0 - (double)(2 * r + 1) / (double)H;
     return p;
 }
 
-// a*b - c*d with one rounding error's worth of accuracy (Kahan's FMA
-// difference of products).
-__device__ __forceinline__ float dop(float a, float b, float c, float d) {
-    float w = c * d;
-    float e = fmaf(-c, d, w);
-    float f = fmaf(a, b, -w);
-    return f + e;
-}
-
-// Per-face record, 80 bytes, built once per call by the setup kernel.
-//   q0  ax, ay, E, 1/E                 (E = doubled signed area = cross(b-a, c-a))
-//   q1  (b-a).x, (b-a).y, (c-a).x, (c-a).y    rounded edge vectors
-//   q2  their rounding residuals (exact: edge = q1 + q2)
-//   q3  az, bz - az, cz - az, mesh id (int bits; -1 = never counts)
-//   q4  xmin, xmax, ymin, ymax: xy bbox grown by sqrt(blur) plus a pad;
-//       empty (+inf, -inf) for faces that never count
+// Per-face record, 96 bytes, built once per call by the setup kernel.
 struct FaceRec {
-    float4 q0, q1, q2, q3, q4;
-    __device__ __forceinline__ int mesh() const { return __float_as_int(q3.w); }
-    __device__ __forceinline__ bool ok() const { return __float_as_int(q3.w) >= 0; }
-    __device__ __forceinline__ float invE() const { return q0.w; }
+    double2 pa;  // vertex a (x, y)
+    double2 ab;  // b - a (exact)
+    double2 ac;  // c - a (exact)
+    double E;    // doubled signed area cross(b - a, c - a)
+    float az;    // depth of a
+    int mesh_;   // mesh (image) id; -1 = the face never counts
+    float dz1, dz2;  // bz - az, cz - az
+    float invE;      // 1 / E rounded to FP32
+    float pad_;
+    float4 bb;   // xmin, xmax, ymin, ymax: xy box grown by sqrt(blur) plus a pad;
+                 // empty (+inf, -inf) for faces that never count
+    __device__ __forceinline__ int mesh() const { return mesh_; }
+    __device__ __forceinline__ bool ok() const { return mesh_ >= 0; }
 };
 
 __device__ __forceinline__ bool finite3(float a, float b, float c) {
     return isfinite(a) && isfinite(b) && isfinite(c);
 }
 
-// cross(u, v) for u = uh + ul, v = vh + vl: Kahan product of the hi parts
-// plus the first-order terms of the residuals (the lo*lo term is below the
-// rounding of the result).
-__device__ __forceinline__ float cross_acc(float uhx, float uhy, float ulx, float uly, float vhx, float vhy, float vlx,
-                                           float vly) {
-    float main = dop(uhx, vhy, uhy, vhx);
-    float corr = fmaf(uhx, vly, fmaf(ulx, vhy, -fmaf(uhy, vlx, uly * vhx)));
-    return main + corr;
-}
-
 // Builds the record of face (a, b, c).  rb = sqrt(blur_radius) in NDC units.
 __device__ __forceinline__ FaceRec make_rec(float ax, float ay, float az, float bx, float by, float bz, float cx,
                                             float cy, float cz, float rb, int mesh) {
     FaceRec R;
-    float abx, abxl, aby, abyl, acx, acxl, acy, acyl;
-    two_diff(bx, ax, abx, abxl);
-    two_diff(by, ay, aby, abyl);
-    two_diff(cx, ax, acx, acxl);
-    two_diff(cy, ay, acy, acyl);
-    float E = cross_acc(abx, aby, abxl, abyl, acx, acy, acxl, acyl);
-    bool ok = mesh >= 0 && fabsf(E) >= kEpsArea && finite3(ax, ay, az) && finite3(bx, by, bz) &&
+    R.pa = make_double2(ax, ay);
+    R.ab = make_double2((double)bx - (double)ax, (double)by - (double)ay);
+    R.ac = make_double2((double)cx - (double)ax, (double)cy - (double)ay);
+    R.E = R.ab.x * R.ac.y - R.ab.y * R.ac.x;
+    bool ok = mesh >= 0 && fabs(R.E) >= kEpsArea && finite3(ax, ay, az) && finite3(bx, by, bz) &&
               finite3(cx, cy, cz);
-    R.q0 = make_float4(ax, ay, E, ok ? 1.0f / E : 0.0f);
-    R.q1 = make_float4(abx, aby, acx, acy);
-    R.q2 = make_float4(abxl, abyl, acxl, acyl);
-    R.q3 = make_float4(az, bz - az, cz - az, __int_as_float(ok ? mesh : -1));
+    R.az = az;
+    R.mesh_ = ok ? mesh : -1;
+    R.dz1 = bz - az;
+    R.dz2 = cz - az;
+    R.invE = ok ? (float)(1.0 / R.E) : 0.0f;
+    R.pad_ = 0.0f;
     if (ok) {
         // The pad covers the FP32 error of the distance test: a pixel whose
         // FP32 squared distance is < blur is never farther than rb*(1+1e-6)+1e-7.
         float pad = rb * 1e-4f + 1e-6f;
         float g = rb + pad;
-        R.q4 = make_float4(fminf(ax, fminf(bx, cx)) - g, fmaxf(ax, fmaxf(bx, cx)) + g,
+        R.bb = make_float4(fminf(ax, fminf(bx, cx)) - g, fmaxf(ax, fmaxf(bx, cx)) + g,
                            fminf(ay, fminf(by, cy)) - g, fmaxf(ay, fmaxf(by, cy)) + g);
     } else {
-        R.q4 = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+        R.bb = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
     }
     return R;
 }
@@ -156,47 +126,43 @@ __device__ __forceinline__ float seg_d2(float sx, float sy, float vx, float vy, 
 struct Eval {
     float w0, w1, w2;  // barycentrics
     float z;
-    float d2;     // squared distance to the nearest boundary point
-    float u;      // parameter of the nearest point on the nearest edge
-    int edge;     // nearest edge: 0 = (a,b), 1 = (b,c), 2 = (c,a); lowest index on ties
-    bool inside;  // all three barycentrics > 0
-    float sx, sy; // p - a (rounded): the pixel relative to vertex a
+    float d2;      // squared distance to the nearest boundary point
+    float u;       // parameter of the nearest point on the nearest edge
+    int edge;      // nearest edge: 0 = (a,b), 1 = (b,c), 2 = (c,a); lowest index on ties
+    bool inside;   // all three barycentrics > 0
+    float sx, sy;  // p - a (rounded): the pixel relative to vertex a
 };
 
 // Barycentrics, z and inside-ness of pixel p in face R.
+//   e1 = cross(p - a, c - a), e2 = cross(b - a, p - a), e0 = E - e1 - e2
+// (the same three sub-triangle areas as cross(b-p, c-p), cross(c-p, a-p) and
+// cross(a-p, b-p)), each FP64; w_i = e_i / E.
 __device__ __forceinline__ void eval_bary(const FaceRec& R, const Pix& p, float& w0, float& w1, float& w2, float& z,
                                           bool& inside, float& sx, float& sy) {
-    // s = p - a exactly as sh + sl
-    float shx, slx, shy, sly;
-    two_diff(p.x, R.q0.x, shx, slx);
-    two_diff(p.y, R.q0.y, shy, sly);
-    slx += p.xl;
-    sly += p.yl;
-    // e1 = cross(p - a, c - a), e2 = cross(b - a, p - a), e0 = E - e1 - e2
-    float e1 = cross_acc(shx, shy, slx, sly, R.q1.z, R.q1.w, R.q2.z, R.q2.w);
-    float e2 = cross_acc(R.q1.x, R.q1.y, R.q2.x, R.q2.y, shx, shy, slx, sly);
-    float e0 = (R.q0.z - e1) - e2;
-    float invE = R.q0.w;
-    w0 = e0 * invE;
-    w1 = e1 * invE;
-    w2 = e2 * invE;
+    const double dx = p.x - R.pa.x, dy = p.y - R.pa.y;
+    const double e1 = fma(dx, R.ac.y, -(dy * R.ac.x));
+    const double e2 = fma(R.ab.x, dy, -(R.ab.y * dx));
+    const double e0 = (R.E - e1) - e2;
+    w0 = (float)e0 * R.invE;
+    w1 = (float)e1 * R.invE;
+    w2 = (float)e2 * R.invE;
     // z = w0 az + w1 bz + w2 cz, rearranged with w0 = 1 - w1 - w2 so that the
     // large common depth az is added last
-    z = fmaf(w2, R.q3.z, w1 * R.q3.y) + R.q3.x;
-    inside = (w0 > 0.0f) && (w1 > 0.0f) && (w2 > 0.0f);
-    sx = shx;
-    sy = shy;
+    z = fmaf(w2, R.dz2, w1 * R.dz1) + R.az;
+    inside = (R.E > 0.0) ? (e0 > 0.0 && e1 > 0.0 && e2 > 0.0) : (e0 < 0.0 && e1 < 0.0 && e2 < 0.0);
+    sx = (float)dx;
+    sy = (float)dy;
 }
 
 // Squared distance to the triangle boundary and its nearest edge, from the
 // pixel offset s = p - a.
 __device__ __forceinline__ float eval_dist(const FaceRec& R, float sx, float sy, int& edge, float& u) {
-    float Ax = -sx, Ay = -sy;                         // a - p
-    float Bx = Ax + R.q1.x, By = Ay + R.q1.y;         // b - p
+    const float abx = (float)R.ab.x, aby = (float)R.ab.y, acx = (float)R.ac.x, acy = (float)R.ac.y;
+    const float Ax = -sx, Ay = -sy;  // a - p
     float u0, u1, u2;
-    float d0 = seg_d2(Ax, Ay, R.q1.x, R.q1.y, u0);
-    float d1 = seg_d2(Bx, By, R.q1.z - R.q1.x, R.q1.w - R.q1.y, u1);
-    float d2 = seg_d2(Ax + R.q1.z, Ay + R.q1.w, -R.q1.z, -R.q1.w, u2);
+    float d0 = seg_d2(Ax, Ay, abx, aby, u0);
+    float d1 = seg_d2(Ax + abx, Ay + aby, acx - abx, acy - aby, u1);
+    float d2 = seg_d2(Ax + acx, Ay + acy, -acx, -acy, u2);
     float d = d0;
     int e = 0;
     float uu = u0;
@@ -213,7 +179,7 @@ __device__ __forceinline__ void eval_full(const FaceRec& R, const Pix& p, Eval& 
 }
 
 __device__ __forceinline__ bool in_bbox(const FaceRec& R, const Pix& p) {
-    return p.x >= R.q4.x && p.x <= R.q4.y && p.y >= R.q4.z && p.y <= R.q4.w;
+    return p.xf >= R.bb.x && p.xf <= R.bb.y && p.yf >= R.bb.z && p.yf <= R.bb.w;
 }
 
 // Does face R count for pixel p?  On success z is its depth.
@@ -271,8 +237,8 @@ __device__ __forceinline__ bool face_bins(const FaceRec& R, int H, int W, int bs
                                           int& by1) {
     if (!R.ok()) return false;
     int c0, c1, r0, r1;
-    pix_range(R.q4.x, R.q4.y, W, c0, c1);
-    pix_range(R.q4.z, R.q4.w, H, r0, r1);
+    pix_range(R.bb.x, R.bb.y, W, c0, c1);
+    pix_range(R.bb.z, R.bb.w, H, r0, r1);
     if (c1 < c0 || r1 < r0) return false;
     bx0 = c0 / bs;
     bx1 = c1 / bs;
@@ -299,14 +265,17 @@ struct TopK {
 #pragma unroll
         for (int i = 0; i < KB; ++i) q[i] = kEmptyKey;
     }
-    __device__ __forceinline__ void insert(uint64_t key) {
-        if (key >= q[KB - 1]) return;
+    // Branch-free insertion: every slot is a compare-exchange with the
+    // travelling key, so the array is only indexed with compile-time
+    // constants; `want` masks lanes with nothing to insert.
+    __device__ __forceinline__ void insert(uint64_t key, bool want = true) {
+        if (!want) key = kEmptyKey;
 #pragma unroll
         for (int i = 0; i < KB; ++i) {
-            uint64_t lo = key < q[i] ? key : q[i];
-            uint64_t hi = key < q[i] ? q[i] : key;
+            const bool lt = key < q[i];
+            const uint64_t lo = lt ? key : q[i];
+            key = lt ? q[i] : key;
             q[i] = lo;
-            key = hi;
         }
     }
 };

@@ -75,16 +75,16 @@ __device__ __forceinline__ void slot_grad(const BwdArgs& a, const FaceRec& R, co
     float G1 = gb1 + gzs * vz[1];
     float G2 = gb2 + gzs * vz[2];
     float Gw = G0 * ev.w0 + G1 * ev.w1 + G2 * ev.w2;
-    float invE = R.invE();
+    float invE = R.invE;
     float H0 = (G0 - Gw) * invE, H1 = (G1 - Gw) * invE, H2 = (G2 - Gw) * invE;
     // vertex positions relative to the pixel
     float Rx[3], Ry[3];
     Rx[0] = -ev.sx;
     Ry[0] = -ev.sy;
-    Rx[1] = Rx[0] + R.q1.x;
-    Ry[1] = Ry[0] + R.q1.y;
-    Rx[2] = Rx[0] + R.q1.z;
-    Ry[2] = Ry[0] + R.q1.w;
+    Rx[1] = Rx[0] + (float)R.ab.x;
+    Ry[1] = Ry[0] + (float)R.ab.y;
+    Rx[2] = Rx[0] + (float)R.ac.x;
+    Ry[2] = Ry[0] + (float)R.ac.y;
     // de0/dR1 = (R2.y, -R2.x), de0/dR2 = (-R1.y, R1.x)
     // de1/dR2 = (R0.y, -R0.x), de1/dR0 = (-R2.y, R2.x)
     // de2/dR0 = (R1.y, -R1.x), de2/dR1 = (-R0.y, R0.x)
@@ -218,8 +218,8 @@ __global__ __launch_bounds__(kBwdBlock) void bwd_faces_kernel(BwdArgs a) {
         int n;
         if (load_face(a, f, R, vi, vz, n)) {
             int c0, c1, r0, r1;
-            pix_range(R.q4.x, R.q4.y, a.W, c0, c1);
-            pix_range(R.q4.z, R.q4.w, a.H, r0, r1);
+            pix_range(R.bb.x, R.bb.y, a.W, c0, c1);
+            pix_range(R.bb.z, R.bb.w, a.H, r0, r1);
             if (c1 >= c0 && r1 >= r0) {
                 int area = (c1 - c0 + 1) * (r1 - r0 + 1);
                 if (area > kBigArea) {
@@ -272,8 +272,8 @@ __global__ __launch_bounds__(kBwdBlock) void bwd_big_faces_kernel(BwdArgs a) {
         bool ok = load_face(a, f, R, vi, vz, n);
         if (ok) {
             int c0, c1, r0, r1;
-            pix_range(R.q4.x, R.q4.y, a.W, c0, c1);
-            pix_range(R.q4.z, R.q4.w, a.H, r0, r1);
+            pix_range(R.bb.x, R.bb.y, a.W, c0, c1);
+            pix_range(R.bb.z, R.bb.w, a.H, r0, r1);
             const int w = c1 - c0 + 1;
             const int64_t area = (c1 >= c0 && r1 >= r0) ? (int64_t)w * (r1 - r0 + 1) : 0;
             for (int64_t q = threadIdx.x; q < area; q += kBwdBlock) {
@@ -414,7 +414,7 @@ __global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a) {
                 }
                 if (j < 0) continue;
                 const FaceRec R = srec[j];
-                const float vz[3] = {R.q3.x, R.q3.x + R.q3.y, R.q3.x + R.q3.z};
+                const float vz[3] = {R.az, R.az + R.dz1, R.az + R.dz2};
                 FaceGrad g;
 #pragma unroll
                 for (int jj = 0; jj < 3; ++jj) g.gx[jj] = g.gy[jj] = g.gzv[jj] = 0.0f;

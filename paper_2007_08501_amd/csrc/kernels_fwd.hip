@@ -194,7 +194,7 @@ constexpr int kChunk = 64;
 struct TileLds {
     FaceRec rec[kChunk];
     int id[kChunk];
-    unsigned char lst[64 * kChunk];
+    unsigned short lst[kChunk * 64];  // entry i of lane l at [i * 64 + l]: conflict-free
 };
 
 // One wave rasterizes one 8x8 tile in three steps per chunk of 64 faces:
@@ -237,37 +237,52 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
         base = lo;
         cnt = hi > lo ? hi - lo : 0;
     }
-    unsigned char* mylst = L.lst + lane * kChunk;
+    unsigned short* mylst = L.lst + lane;
     for (int64_t c0 = 0; c0 < cnt; c0 += kChunk) {
         // 1. gather and compact the chunk's faces that overlap the tile
         const int64_t e = c0 + lane;
         const bool in_list = e < cnt;
         const int fid = in_list ? (BINNED ? list[e] : (int)(base + e)) : 0;
-        const FaceRec R = a.recs[in_list ? fid : (BINNED ? list[0] : (int)base)];
-        const bool keep =
-            in_list && !(R.q4.y < tx_lo || R.q4.x > tx_hi || R.q4.w < ty_lo || R.q4.z > ty_hi);
+        // the record as six 16-byte words (see FaceRec): [3].z = a.z,
+        // [4].x/.y = b.z - a.z / c.z - a.z, [5] = grown box
+        const float4* rsrc = reinterpret_cast<const float4*>(a.recs + (in_list ? fid : (BINNED ? list[0] : (int)base)));
+        const float4 rv0 = rsrc[0], rv1 = rsrc[1], rv2 = rsrc[2], rv3 = rsrc[3], rv4 = rsrc[4], rv5 = rsrc[5];
+        const float4 bb = rv5;
+        const bool keep = in_list && !(bb.y < tx_lo || bb.x > tx_hi || bb.w < ty_lo || bb.z > ty_hi);
         const uint64_t kept = __ballot(keep);
         const int m = __popcll(kept);
         if (keep) {
             const int dst = __popcll(kept & lt_mask);
-            L.rec[dst] = R;
+            float4* rdst = reinterpret_cast<float4*>(&L.rec[dst]);
+            rdst[0] = rv0;
+            rdst[1] = rv1;
+            rdst[2] = rv2;
+            rdst[3] = rv3;
+            rdst[4] = rv4;
+            rdst[5] = rv5;
             L.id[dst] = fid;
         }
         __syncthreads();
         // 2. per-lane lists of the faces whose boxes contain the lane's pixel
         int nl = 0;
         for (int j = 0; j < m; ++j) {
-            const float4 bb = L.rec[j].q4;
-            if (live && p.x >= bb.x && p.x <= bb.y && p.y >= bb.z && p.y <= bb.w) mylst[nl++] = (unsigned char)j;
+            const float4 bb = L.rec[j].bb;
+            if (live && p.xf >= bb.x && p.xf <= bb.y && p.yf >= bb.z && p.yf <= bb.w) mylst[64 * nl++] = (unsigned short)j;
         }
         // 3. full test of the lane's own candidates
         for (int i = 0; __any(i < nl); ++i) {
+            bool want = false;
+            uint64_t key = kEmptyKey;
             if (i < nl) {
-                const int j = mylst[i];
+                const int j = mylst[64 * i];
                 const FaceRec Rj = L.rec[j];
                 float z;
-                if (face_counts(Rj, p, a.blur, z)) top.insert(make_key(z, L.id[j]));
+                if (face_counts(Rj, p, a.blur, z)) {
+                    want = true;
+                    key = make_key(z, L.id[j]);
+                }
             }
+            top.insert(key, want);  // every lane calls it: the insertion votes across the wave
         }
         __syncthreads();
     }
