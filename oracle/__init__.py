@@ -48,7 +48,7 @@ def _load():
     lib.oracle_rasterize.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, ctypes.c_double, ci, P, i64,
                                      P, P, P, P, P, P, ci]
     lib.oracle_rasterize.restype = ci
-    lib.oracle_fragments_fixed.argtypes = [P, P, ci, ci, ci, ci, P, P, P, P, P, ci]
+    lib.oracle_fragments_fixed.argtypes = [P, P, ci, ci, ci, ci, P, ctypes.c_int64, P, P, P, P, P, ci]
     lib.oracle_fragments_fixed.restype = ci
     lib.oracle_backward.argtypes = [P, i64, P, ci, ci, ci, ci, P, i64, P, P, P, P, P, ci]
     lib.oracle_backward.restype = ci
@@ -114,21 +114,25 @@ def rasterize(verts, faces, first_idx, num_faces, image_size, blur_radius, faces
     return out
 
 
-def fragments_fixed(verts, faces, image_size, p2f, nthreads: Optional[int] = None):
+def fragments_fixed(verts, faces, image_size, p2f, nthreads: Optional[int] = None, pixels=None):
     """zbuf, bary, dists (float64) and the per-slot edge-tie mask for a given
-    face choice p2f (N,H,W,K); the forward map with the selection frozen."""
+    face choice p2f (N,H,W,K); the forward map with the selection frozen.
+    With ``pixels`` (linear pixel ids), p2f is (npix,K) rows of those pixels."""
     lib = _load()
     H, W = image_size
     p = _i64(p2f)
     N, K = p.shape[0], p.shape[-1]
+    pix = None if pixels is None else _i64(pixels)
+    if pix is not None and pix.shape[0] != N:
+        raise ValueError("one p2f row per listed pixel")
     v = _f64(verts)
     f = _i64(faces)
     zbuf = np.empty(p.shape, np.float64)
     bary = np.empty(p.shape + (3,), np.float64)
     dists = np.empty(p.shape, np.float64)
     tie = np.empty(p.shape, np.uint8)
-    lib.oracle_fragments_fixed(_ptr(v), _ptr(f), N, H, W, K, _ptr(p), _ptr(zbuf), _ptr(bary), _ptr(dists),
-                               _ptr(tie), nthreads or default_threads())
+    lib.oracle_fragments_fixed(_ptr(v), _ptr(f), N, H, W, K, _ptr(pix), 0 if pix is None else pix.shape[0],
+                               _ptr(p), _ptr(zbuf), _ptr(bary), _ptr(dists), _ptr(tie), nthreads or default_threads())
     return zbuf, bary, dists, tie
 
 

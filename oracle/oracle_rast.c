@@ -259,11 +259,12 @@ int oracle_rasterize(const double* verts, int64_t V, const int64_t* faces, int64
  * frozen, used for finite-difference checks of the backward.
  * Also writes tie (per slot, may be NULL): 1 where the two smallest edge
  * distances differ by less than tau in linear units (M6).
+ * With pix (npix linear pixel ids) the slots are the rows of those pixels.
  */
 int oracle_fragments_fixed(const double* verts, const int64_t* faces, int N, int H, int W, int K,
-                           const int64_t* p2f, double* zbuf, double* bary, double* dists,
-                           uint8_t* tie, int nthreads) {
-    int64_t S = (int64_t)N * H * W * K;
+                           const int64_t* pix, int64_t npix, const int64_t* p2f, double* zbuf, double* bary,
+                           double* dists, uint8_t* tie, int nthreads) {
+    int64_t S = pix ? npix * K : (int64_t)N * H * W * K;
 #pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
     for (int64_t s = 0; s < S; ++s) {
         int64_t f = p2f[s];
@@ -274,7 +275,7 @@ int oracle_fragments_fixed(const double* verts, const int64_t* faces, int N, int
             dists[s] = -1.0;
             continue;
         }
-        int64_t lin = s / K;
+        int64_t lin = pix ? pix[s / K] : s / K;
         int64_t rem = lin % ((int64_t)H * W);
         double px, py;
         pixel_center(rem / W, rem % W, H, W, &px, &py);

@@ -182,6 +182,20 @@ __device__ __forceinline__ bool in_bbox(const FaceRec& R, const Pix& p) {
     return p.xf >= R.bb.x && p.xf <= R.bb.y && p.yf >= R.bb.z && p.yf <= R.bb.w;
 }
 
+// Does face R count for pixel p, given that p lies in R's grown box?  On
+// success z is its depth.
+__device__ __forceinline__ bool face_counts_in_box(const FaceRec& R, const Pix& p, float blur, float& z) {
+    float w0, w1, w2, sx, sy;
+    bool inside;
+    eval_bary(R, p, w0, w1, w2, z, inside, sx, sy);
+    if (!(z >= 0.0f)) return false;
+    if (inside) return true;
+    int e;
+    float u;
+    float d2 = eval_dist(R, sx, sy, e, u);
+    return d2 < blur;
+}
+
 // Does face R count for pixel p?  On success z is its depth.
 __device__ __forceinline__ bool face_counts(const FaceRec& R, const Pix& p, float blur, float& z) {
     if (!in_bbox(R, p)) return false;
@@ -258,12 +272,62 @@ constexpr uint64_t kEmptyKey = ~0ull;
 // Register-resident sorted list of the KB smallest keys; every slot is a
 // compare-exchange with the travelling key, so the array is only ever
 // indexed with compile-time constants.
+// Compare-exchange: a <- min, b <- max.
+__device__ __forceinline__ void cex(uint64_t& a, uint64_t& b) {
+    const bool lt = b < a;
+    const uint64_t lo = lt ? b : a;
+    const uint64_t hi = lt ? a : b;
+    a = lo;
+    b = hi;
+}
+
+// Sorts eight keys ascending with a 19-comparator network.
+__device__ __forceinline__ void sort8(uint64_t (&b)[8]) {
+    cex(b[0], b[2]); cex(b[1], b[3]); cex(b[4], b[6]); cex(b[5], b[7]);
+    cex(b[0], b[4]); cex(b[1], b[5]); cex(b[2], b[6]); cex(b[3], b[7]);
+    cex(b[0], b[1]); cex(b[2], b[3]); cex(b[4], b[5]); cex(b[6], b[7]);
+    cex(b[2], b[4]); cex(b[3], b[5]);
+    cex(b[1], b[4]); cex(b[3], b[6]);
+    cex(b[1], b[2]); cex(b[3], b[4]); cex(b[5], b[6]);
+}
+
+constexpr bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
 template <int KB>
 struct TopK {
     uint64_t q[KB];
     __device__ __forceinline__ void init() {
 #pragma unroll
         for (int i = 0; i < KB; ++i) q[i] = kEmptyKey;
+    }
+    // Keeps the KB smallest of the queue and eight new keys (absent keys are
+    // kEmptyKey).  The batch is sorted, then one half-cleaner step
+    // q[i] = min(q[i], b[KB-1-i]) leaves the KB smallest of both as a bitonic
+    // sequence, and a bitonic merge sorts it: about four compare-exchanges
+    // per key for KB = 16, against KB for one insertion at a time.
+    __device__ __forceinline__ void merge8(uint64_t (&b)[8]) {
+        sort8(b);
+        constexpr int M = KB < 8 ? KB : 8;
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            const int qi = KB - M + i;
+            q[qi] = b[M - 1 - i] < q[qi] ? b[M - 1 - i] : q[qi];
+        }
+#pragma unroll
+        for (int d = KB / 2; d >= 1; d /= 2) {
+#pragma unroll
+            for (int i = 0; i < KB; ++i)
+                if (!(i & d)) cex(q[i], q[i + d]);
+        }
+    }
+    // Adds eight keys: batched merge for power-of-two queues, else one at a time.
+    __device__ __forceinline__ void push8(uint64_t (&b)[8]) {
+        if constexpr (is_pow2(KB)) {
+            merge8(b);
+        } else {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) insert(b[u]);
+        }
     }
     // Branch-free insertion: every slot is a compare-exchange with the
     // travelling key, so the array is only indexed with compile-time

@@ -1,6 +1,6 @@
 // kernels_fwd.hip -- forward rasterization kernels for gfx950.
 //
-//   face_setup      one thread per face: mesh id, 64-byte record, padded bbox
+//   face_setup      one thread per face: mesh id, 96-byte record, padded bbox
 //   bin_faces       one thread per face: append the face to every bin its bbox
 //                   touches (counting only when lists == nullptr)
 //   bin_max         largest bin count -> workspace header, overflow flag
@@ -197,6 +197,116 @@ struct TileLds {
     unsigned short lst[kChunk * 64];  // entry i of lane l at [i * 64 + l]: conflict-free
 };
 
+// Largest value of v over the wave.
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Writes the tile's fragments from the per-lane queues.  Values are staged in
+// LDS per pixel and then stored by consecutive lanes to consecutive
+// addresses, so every store instruction writes whole contiguous runs (one
+// tile row of pix_to_face is 8*K contiguous words) instead of 64 scattered
+// words; written slot by slot, each cache line would be completed by K
+// separate instructions with loads in between and could be evicted half
+// written.  Ids and depths come straight from the keys; barycentrics and
+// distances are recomputed from the face records.
+constexpr int kStageG1 = 16;  // slots per pass for ids and depths
+constexpr int kStageG2 = 8;   // slots per pass for barycentrics and distances
+
+// element e of a pass that stages `per` values per pixel: pixel e / per
+__device__ __forceinline__ int stage_pixel(int e, float inv_per) { return (int)(((float)e + 0.5f) * inv_per); }
+
+template <int KB>
+__device__ __forceinline__ void write_fragments(const FineArgs& a, TileLds& L, const TopK<KB>& top, const Pix& p,
+                                                int n, int tx, int ty) {
+    const int lane = threadIdx.x & 63;
+    const int K = a.K;
+    const int rows = min(kTile, a.H - ty * kTile), cols = min(kTile, a.W - tx * kTile);
+    const int64_t pix0 = ((int64_t)n * a.H + ty * kTile) * a.W + tx * kTile;
+    static_assert(sizeof(TileLds) >= sizeof(float) * 64 * 2 * (kStageG1 + 1), "id/depth staging exceeds the tile LDS");
+    static_assert(sizeof(TileLds) >= sizeof(float) * 64 * (4 * kStageG2 + 2), "bary/dist staging exceeds the tile LDS");
+    float* stage = reinterpret_cast<float*>(&L);
+    // ids and depths
+    {
+        constexpr int G = KB < kStageG1 ? KB : kStageG1;
+        constexpr int S = G + 1;  // odd stride: lane-major writes hit distinct banks
+        int* sid = reinterpret_cast<int*>(stage);
+        float* sz = stage + 64 * S;
+#pragma unroll
+        for (int g0 = 0; g0 < KB; g0 += G) {
+            if (g0 >= K) continue;  // K is uniform: the whole wave skips
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const uint64_t key = top.q[g0 + k];
+                const bool empty = key == kEmptyKey;
+                sid[lane * S + k] = empty ? -1 : (int)(uint32_t)key;
+                sz[lane * S + k] = empty ? -1.0f : __uint_as_float((uint32_t)(key >> 32));
+            }
+            __syncthreads();
+            const int gw = min(G, K - g0);
+            const float inv = 1.0f / (float)gw;
+            for (int e = lane; e < 64 * gw; e += 64) {
+                const int px = stage_pixel(e, inv);
+                const int k = e - px * gw;
+                const int r = px >> 3, c = px & 7;
+                if (r < rows && c < cols) {
+                    const int64_t o = (pix0 + (int64_t)r * a.W + c) * K + g0 + k;
+                    a.p2f[o] = sid[px * S + k];
+                    a.zbuf[o] = sz[px * S + k];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // barycentrics and signed distances
+    {
+        constexpr int G = KB < kStageG2 ? KB : kStageG2;
+        constexpr int SB = 3 * G + 1, SD = G + 1;
+        float* sb = stage;
+        float* sd = stage + 64 * SB;
+#pragma unroll
+        for (int g0 = 0; g0 < KB; g0 += G) {
+            if (g0 >= K) continue;  // K is uniform: the whole wave skips
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const uint64_t key = top.q[g0 + k];
+                float w0 = -1.0f, w1 = -1.0f, w2 = -1.0f, d = -1.0f;
+                if (key != kEmptyKey) {
+                    const FaceRec R = a.recs[(uint32_t)key];
+                    Eval ev;
+                    eval_full(R, p, ev);
+                    w0 = ev.w0;
+                    w1 = ev.w1;
+                    w2 = ev.w2;
+                    d = ev.inside ? -ev.d2 : ev.d2;
+                }
+                sb[lane * SB + 3 * k + 0] = w0;
+                sb[lane * SB + 3 * k + 1] = w1;
+                sb[lane * SB + 3 * k + 2] = w2;
+                sd[lane * SD + k] = d;
+            }
+            __syncthreads();
+            const int gw = min(G, K - g0);
+            const float inv3 = 1.0f / (float)(3 * gw), inv1 = 1.0f / (float)gw;
+            for (int e = lane; e < 64 * 3 * gw; e += 64) {
+                const int px = stage_pixel(e, inv3);
+                const int m = e - px * 3 * gw;
+                const int r = px >> 3, c = px & 7;
+                if (r < rows && c < cols) a.bary[((pix0 + (int64_t)r * a.W + c) * K + g0) * 3 + m] = sb[px * SB + m];
+            }
+            for (int e = lane; e < 64 * gw; e += 64) {
+                const int px = stage_pixel(e, inv1);
+                const int k = e - px * gw;
+                const int r = px >> 3, c = px & 7;
+                if (r < rows && c < cols) a.dists[(pix0 + (int64_t)r * a.W + c) * K + g0 + k] = sd[px * SD + k];
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // One wave rasterizes one 8x8 tile in three steps per chunk of 64 faces:
 //  1. gather the chunk's face records, keep those whose box overlaps the tile
 //     (wave ballot + prefix count compacts them into LDS);
@@ -269,52 +379,27 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
             const float4 bb = L.rec[j].bb;
             if (live && p.xf >= bb.x && p.xf <= bb.y && p.yf >= bb.z && p.yf <= bb.w) mylst[64 * nl++] = (unsigned short)j;
         }
-        // 3. full test of the lane's own candidates
-        for (int i = 0; __any(i < nl); ++i) {
-            bool want = false;
-            uint64_t key = kEmptyKey;
-            if (i < nl) {
-                const int j = mylst[64 * i];
-                const FaceRec Rj = L.rec[j];
-                float z;
-                if (face_counts(Rj, p, a.blur, z)) {
-                    want = true;
-                    key = make_key(z, L.id[j]);
+        // 3. full test of the lane's own candidates, eight per round; the
+        //    round count is the wave's longest list, so the loop is uniform
+        //    and the queue stays in place across rounds
+        const int nmax = wave_max(nl);
+        for (int i0 = 0; i0 < nmax; i0 += 8) {
+            uint64_t b[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                uint64_t key = kEmptyKey;
+                if (i0 + u < nl) {
+                    const int j = mylst[64 * (i0 + u)];
+                    float z;
+                    if (face_counts_in_box(L.rec[j], p, a.blur, z)) key = make_key(z, L.id[j]);
                 }
+                b[u] = key;
             }
-            top.insert(key, want);  // every lane calls it: the insertion votes across the wave
+            top.push8(b);
         }
         __syncthreads();
     }
-    if (!live) return;
-    const int64_t pix = ((int64_t)n * a.H + r) * a.W + c;
-    const int K = a.K;
-#pragma unroll
-    for (int k = 0; k < KB; ++k) {
-        if (k < K) {
-            const int64_t o = pix * K + k;
-            const uint64_t key = top.q[k];
-            if (key != kEmptyKey) {
-                const int fid = (int)(uint32_t)key;
-                const FaceRec R = a.recs[fid];
-                Eval ev;
-                eval_full(R, p, ev);
-                a.p2f[o] = fid;
-                a.zbuf[o] = ev.z;
-                a.bary[3 * o + 0] = ev.w0;
-                a.bary[3 * o + 1] = ev.w1;
-                a.bary[3 * o + 2] = ev.w2;
-                a.dists[o] = ev.inside ? -ev.d2 : ev.d2;
-            } else {
-                a.p2f[o] = -1;
-                a.zbuf[o] = -1.0f;
-                a.bary[3 * o + 0] = -1.0f;
-                a.bary[3 * o + 1] = -1.0f;
-                a.bary[3 * o + 2] = -1.0f;
-                a.dists[o] = -1.0f;
-            }
-        }
-    }
+    write_fragments<KB>(a, L, top, p, n, tx, ty);
 }
 
 template <int KB, bool BINNED>
@@ -457,7 +542,6 @@ hipError_t launch_fine(const FaceRec* recs, const int64_t* first, const int64_t*
     if (K <= 8) return launch_fine_k<8>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
     if (K <= 16) return launch_fine_k<16>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
     if (K <= 32) return launch_fine_k<32>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
-    if (K <= 50) return launch_fine_k<50>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
     return launch_fine_k<64>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
 }
 

@@ -157,7 +157,16 @@ def invariants_torch(out, fi, nf, blur):
     return int(valid.sum())
 
 
-def tie_masked_grads(b, p2f_np, gz, gb, gd):
-    """Zero grad_dists on slots whose nearest edge is (nearly) tied (M6)."""
-    _, _, _, tie = oracle.fragments_fixed(b.verts, b.faces, b.image_size, p2f_np, nthreads=threads())
-    return gz, gb, np.where(tie.astype(bool), np.float32(0), gd).astype(np.float32)
+def tie_masked_grads(b, p2f_np, gz, gb, gd, pixels=None):
+    """Zero grad_dists on slots whose nearest edge is (nearly) tied (M6).
+    With pixels, p2f_np holds the rows of those pixels and only their rows
+    of gd (full (N,H,W,K)) are examined."""
+    if pixels is None:
+        _, _, _, tie = oracle.fragments_fixed(b.verts, b.faces, b.image_size, p2f_np, nthreads=threads())
+        return gz, gb, np.where(tie.astype(bool), np.float32(0), gd).astype(np.float32)
+    _, _, _, tie = oracle.fragments_fixed(b.verts, b.faces, b.image_size, p2f_np, nthreads=threads(),
+                                          pixels=pixels)
+    gd = gd.copy()
+    flat = gd.reshape(-1, gd.shape[-1])
+    flat[pixels] = np.where(tie.astype(bool), np.float32(0), flat[pixels])
+    return gz, gb, gd

@@ -1,8 +1,9 @@
 """GPU parity: the HIP rasterizer (through the C ABI) against the FP64 oracle.
 
 Small cases are compared in full; the full-size workloads are compared on
-seeded pixel samples (forward) and in full (backward: the oracle's backward is
-linear in the number of slots), plus size-independent invariants.
+seeded pixel samples (forward, and backward over the oracle's selection on
+those pixels), plus size-independent invariants.  The oracle never takes an
+input produced by the GPU.
 """
 import numpy as np
 import pytest
@@ -129,41 +130,57 @@ def sampled_check(i, bs, n_pix=1500, seed=0):
     torch.cuda.synchronize()
     invariants_torch(out, d[2], d[3], b.blur_radius)
     N, (H, W) = b.N, b.image_size
-    rng = np.random.default_rng(seed)
-    # half uniform, half from pixels the GPU says are covered (where the work is)
-    cov = torch.nonzero((out.pix_to_face[..., 0] >= 0).reshape(-1)).reshape(-1).cpu().numpy()
-    pix = np.unique(np.concatenate([rng.integers(0, N * H * W, n_pix // 2),
-                                    rng.choice(cov, size=min(n_pix // 2, cov.size), replace=False)]))
+    # seeded uniform pixel sample (the meshes cover most of every image)
+    pix = np.unique(np.random.default_rng(seed).integers(0, N * H * W, n_pix))
     o = oracle.rasterize(b.verts, b.faces, b.first_idx, b.num_faces, b.image_size, b.blur_radius,
                          b.faces_per_pixel, pixels=pix, nthreads=threads())
     st = compare_fwd(frag_numpy(out, pix), o, b.verts, b.faces, b.blur_radius, f"cfg{i}-sampled")
     log(st)
-    return b, d, out
+    return b, d, out, pix, o
 
 
-def full_backward_check(b, d, out, bins):
+def full_backward_check(b, d, out, pix, o, bins):
+    """Backward at full size in the launch configuration.  Parity: both sides
+    take the oracle's selection on the sampled pixels (every other pixel
+    empty).  At full density: the bin-major passes against the per-face pass
+    on the GPU's own selection, and additivity over a split of the pixels."""
+    N, (H, W), K = b.N, b.image_size, b.faces_per_pixel
     gz, gb, gd = meshgen.upstream_grads(b)
-    p2f = out.pix_to_face.cpu().numpy()
-    gz, gb, gd = tie_masked_grads(b, p2f, gz, gb, gd)
-    ref = oracle.backward(b.verts, b.faces, b.image_size, p2f, gz, gb, gd, nthreads=threads())
+    rows = lambda a: a.reshape((N * H * W,) + a.shape[3:])[pix]
+    gz, gb, gd = tie_masked_grads(b, o["p2f"], gz, gb, gd, pixels=pix)
+    p2f = np.full((N * H * W, K), -1, np.int32)
+    p2f[pix] = o["p2f"]
+    p2f = p2f.reshape(N, H, W, K)
+    ref = oracle.backward(b.verts, b.faces, b.image_size, o["p2f"], rows(gz), rows(gb), rows(gd),
+                          nthreads=threads(), pixels=pix, N=N)
+    p2f_dev = torch.from_numpy(p2f).cuda()
     for bs in bins:
-        gv = run_bwd(b, out.pix_to_face, gz, gb, gd, dev_inputs=d, bs=bs).cpu().numpy()
-        log(f"{b.name} bs{bs} grad rel err", compare_grad(gv, ref, f"{b.name} bs{bs}"))
+        gv = run_bwd(b, p2f_dev, gz, gb, gd, dev_inputs=d, bs=bs).cpu().numpy()
+        log(f"{b.name} bs{bs} sampled grad rel err", compare_grad(gv, ref, f"{b.name} bs{bs}"))
+    # dense selection: every slot of the forward, all passes must agree
+    gz_t, gb_t, gd_t = [torch.from_numpy(x).cuda() for x in meshgen.upstream_grads(b)]
+    dense = [run_bwd(b, out.pix_to_face, gz_t, gb_t, gd_t, dev_inputs=d, bs=bs) for bs in bins]
+    scale = float(dense[0].abs().max())
+    for bs, g in zip(bins[1:], dense[1:]):
+        torch.testing.assert_close(g, dense[0], rtol=0, atol=2e-5 * scale, msg=f"dense bs{bs} vs bs{bins[0]}")
+    half = torch.zeros(N, H, W, 1, dtype=torch.bool, device="cuda")
+    half[:, ::2] = True
+    empty = torch.full_like(out.pix_to_face, -1)
+    a = run_bwd(b, torch.where(half, out.pix_to_face, empty), gz_t, gb_t, gd_t, dev_inputs=d, bs=bins[-1])
+    c = run_bwd(b, torch.where(half, empty, out.pix_to_face), gz_t, gb_t, gd_t, dev_inputs=d, bs=bins[-1])
+    torch.testing.assert_close(a + c, dense[-1], rtol=0, atol=2e-5 * scale, msg="additivity over pixel halves")
 
 
 def test_cfg2_full_size_sampled_and_backward():
-    b, d, out = sampled_check(2, 32)
-    full_backward_check(b, d, out, (0, 8, 16))
+    full_backward_check(*sampled_check(2, 32), bins=(0, 8, 16))
 
 
 def test_cfg3_full_size_sampled_and_backward():
-    b, d, out = sampled_check(3, 16)
-    full_backward_check(b, d, out, (0, 8, 16))
+    full_backward_check(*sampled_check(3, 16), bins=(0, 8, 16))
 
 
 def test_cfg4_full_size_sampled_and_backward():
-    b, d, out = sampled_check(4, 16, n_pix=800)
-    full_backward_check(b, d, out, (0, 8, 16))
+    full_backward_check(*sampled_check(4, 16, n_pix=800), bins=(0, 8, 16))
 
 
 # ----------------------------------------------------------------- backward
@@ -172,12 +189,12 @@ def test_cfg4_full_size_sampled_and_backward():
 @pytest.mark.parametrize("which", ["zbuf", "bary", "dists", "all"])
 def test_backward_vs_oracle_small(which, bs):
     b = meshgen.make_config(2, n_override=3, level_override=3, image_override=64)
-    out, _ = run_fwd(b, 16)
-    p2f = out.pix_to_face.cpu().numpy()
+    # both sides take the oracle's selection
+    p2f = oracle_full(b)["p2f"]
     gz, gb, gd = meshgen.upstream_grads(b)
     gz, gb, gd = tie_masked_grads(b, p2f, gz, gb, gd)
     sel = dict(zbuf=(gz, None, None), bary=(None, gb, None), dists=(None, None, gd), all=(gz, gb, gd))[which]
-    gv = run_bwd(b, out.pix_to_face, *sel, bs=bs).cpu().numpy()
+    gv = run_bwd(b, torch.from_numpy(p2f.astype(np.int32)).cuda(), *sel, bs=bs).cpu().numpy()
     ref = oracle.backward(b.verts, b.faces, b.image_size, p2f, *sel, nthreads=threads())
     compare_grad(gv, ref, which)
 
@@ -293,19 +310,21 @@ def test_zero_faces_total():
 # ----------------------------------------------------------------- blend
 
 def test_silhouette_blend_vs_oracle():
+    # both sides blend the oracle's fragments (dists rounded to f32 once)
     b = meshgen.make_config(5, n_override=4, level_override=3, image_override=64)
-    out, _ = run_fwd(b, 16)
+    o = oracle_full(b)
+    p2f, dn = o["p2f"], o["dists"].astype(np.float32)
+    p2f_t, dn_t = torch.from_numpy(p2f.astype(np.int32)).cuda(), torch.from_numpy(dn).cuda()
     sig = meshgen.SIL_SIGMA
-    alpha = torch.empty(out.dists.shape[:-1], device="cuda")
-    _lib.silhouette_blend_fwd(out.pix_to_face, out.dists, sig, alpha)
-    p2f = out.pix_to_face.cpu().numpy()
-    dn = out.dists.cpu().numpy()
-    ref = oracle.silhouette_blend(p2f, dn, sig)
+    alpha = torch.empty(dn_t.shape[:-1], device="cuda")
+    _lib.silhouette_blend_fwd(p2f_t, dn_t, sig, alpha)
+    ref = oracle.silhouette_blend(p2f, dn.astype(np.float64), sig)
     assert np.abs(alpha.cpu().numpy() - ref).max() < 1e-5
-    ga = torch.randn_like(alpha)
-    gd = torch.empty_like(out.dists)
-    _lib.silhouette_blend_bwd(out.pix_to_face, out.dists, ga, sig, gd)
-    refg = oracle.silhouette_blend_backward(p2f, dn, sig, ga.cpu().numpy())
+    ga_np = np.random.default_rng(7).standard_normal(alpha.shape).astype(np.float32)
+    ga = torch.from_numpy(ga_np).cuda()
+    gd = torch.empty_like(dn_t)
+    _lib.silhouette_blend_bwd(p2f_t, dn_t, ga, sig, gd)
+    refg = oracle.silhouette_blend_backward(p2f, dn.astype(np.float64), sig, ga_np)
     compare_grad(gd.cpu().numpy(), refg, "blend")
 
 

@@ -166,3 +166,17 @@ def test_backward_pixel_list_matches_full():
     flat = lambda a: a.reshape((2 * H * W,) + a.shape[3:])[pix]
     part = oracle.backward(v, f, (H, W), flat(o["p2f"]), flat(gz), flat(gb), flat(gd), pixels=pix, N=2)
     np.testing.assert_allclose(part, full, rtol=1e-12, atol=1e-12)
+
+
+def test_fragments_fixed_pixel_list_matches_full():
+    v, f, fi, nf = sphere_batch([2, 3], seed=16)
+    H = W = 20
+    o = oracle.rasterize(v, f, fi, nf, (H, W), 1e-3, 4)
+    full = oracle.fragments_fixed(v, f, (H, W), o["p2f"])
+    pix = np.sort(np.random.default_rng(3).choice(2 * H * W, 250, replace=False))
+    rows = o["p2f"].reshape(2 * H * W, 4)[pix]
+    part = oracle.fragments_fixed(v, f, (H, W), rows, pixels=pix)
+    for a, b in zip(full, part):
+        np.testing.assert_array_equal(a.reshape((2 * H * W,) + a.shape[3:])[pix], b)
+    # the frozen-selection values are those of the free forward at the same slots
+    np.testing.assert_allclose(part[0], o["zbuf"].reshape(2 * H * W, 4)[pix], rtol=0, atol=1e-12)
