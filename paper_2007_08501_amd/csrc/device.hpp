@@ -56,7 +56,7 @@ __device__ __forceinline__ Pix make_pix(int r, int c, int H, int W) {
     return p;
 }
 
-// Per-face record, 96 bytes, built once per call by the setup kernel.
+// Per-face record, 112 bytes, built once per call by the setup kernel.
 struct FaceRec {
     double2 pa;  // vertex a (x, y)
     double2 ab;  // b - a (exact)
@@ -66,7 +66,9 @@ struct FaceRec {
     int mesh_;   // mesh (image) id; -1 = the face never counts
     float dz1, dz2;  // bz - az, cz - az
     float invE;      // 1 / E rounded to FP32
-    float pad_;
+    float il0;       // 1 / |b - a|^2
+    float il1, il2;  // 1 / |c - b|^2, 1 / |a - c|^2
+    float pad_[2];
     float4 bb;   // xmin, xmax, ymin, ymax: xy box grown by sqrt(blur) plus a pad;
                  // empty (+inf, -inf) for faces that never count
     __device__ __forceinline__ int mesh() const { return mesh_; }
@@ -92,7 +94,12 @@ __device__ __forceinline__ FaceRec make_rec(float ax, float ay, float az, float 
     R.dz1 = bz - az;
     R.dz2 = cz - az;
     R.invE = ok ? (float)(1.0 / R.E) : 0.0f;
-    R.pad_ = 0.0f;
+    // edge lengths from the exact FP64 edge vectors (c - b = (c - a) - (b - a) is exact too)
+    const double bcx = R.ac.x - R.ab.x, bcy = R.ac.y - R.ab.y;
+    R.il0 = ok ? (float)(1.0 / (R.ab.x * R.ab.x + R.ab.y * R.ab.y)) : 0.0f;
+    R.il1 = ok ? (float)(1.0 / (bcx * bcx + bcy * bcy)) : 0.0f;
+    R.il2 = ok ? (float)(1.0 / (R.ac.x * R.ac.x + R.ac.y * R.ac.y)) : 0.0f;
+    R.pad_[0] = R.pad_[1] = 0.0f;
     if (ok) {
         // The pad covers the FP32 error of the distance test: a pixel whose
         // FP32 squared distance is < blur is never farther than rb*(1+1e-6)+1e-7.
@@ -106,21 +113,6 @@ __device__ __forceinline__ FaceRec make_rec(float ax, float ay, float az, float 
     return R;
 }
 
-// Squared distance from the origin (the pixel) to segment S + t*V, t in [0,1],
-// with S, V in pixel-relative coordinates; returns the clamped parameter too.
-__device__ __forceinline__ float seg_d2(float sx, float sy, float vx, float vy, float& u) {
-    float l2 = vx * vx + vy * vy;
-    float t = -(sx * vx + sy * vy);
-    float uu = 0.0f;
-    if (l2 > 0.0f) {
-        uu = t * __builtin_amdgcn_rcpf(l2);
-        uu = uu < 0.0f ? 0.0f : (uu > 1.0f ? 1.0f : uu);
-    }
-    u = uu;
-    float qx = fmaf(uu, vx, sx), qy = fmaf(uu, vy, sy);
-    return qx * qx + qy * qy;
-}
-
 // Everything the forward writes for one (pixel, face) pair, and what the
 // backward needs besides.
 struct Eval {
@@ -131,51 +123,75 @@ struct Eval {
     int edge;      // nearest edge: 0 = (a,b), 1 = (b,c), 2 = (c,a); lowest index on ties
     bool inside;   // all three barycentrics > 0
     float sx, sy;  // p - a (rounded): the pixel relative to vertex a
+    float f0, f1, f2;  // the edge functions e0, e1, e2 rounded to FP32
 };
 
 // Barycentrics, z and inside-ness of pixel p in face R.
 //   e1 = cross(p - a, c - a), e2 = cross(b - a, p - a), e0 = E - e1 - e2
 // (the same three sub-triangle areas as cross(b-p, c-p), cross(c-p, a-p) and
-// cross(a-p, b-p)), each FP64; w_i = e_i / E.
-__device__ __forceinline__ void eval_bary(const FaceRec& R, const Pix& p, float& w0, float& w1, float& w2, float& z,
-                                          bool& inside, float& sx, float& sy) {
+// cross(a-p, b-p)), each FP64; w_i = e_i / E.  The pixel is inside when all
+// three w_i are positive (each w_i has the sign of e_i / E).
+__device__ __forceinline__ void eval_bary(const FaceRec& R, const Pix& p, Eval& o) {
     const double dx = p.x - R.pa.x, dy = p.y - R.pa.y;
     const double e1 = fma(dx, R.ac.y, -(dy * R.ac.x));
     const double e2 = fma(R.ab.x, dy, -(R.ab.y * dx));
     const double e0 = (R.E - e1) - e2;
-    w0 = (float)e0 * R.invE;
-    w1 = (float)e1 * R.invE;
-    w2 = (float)e2 * R.invE;
+    o.f0 = (float)e0;
+    o.f1 = (float)e1;
+    o.f2 = (float)e2;
+    o.w0 = o.f0 * R.invE;
+    o.w1 = o.f1 * R.invE;
+    o.w2 = o.f2 * R.invE;
     // z = w0 az + w1 bz + w2 cz, rearranged with w0 = 1 - w1 - w2 so that the
     // large common depth az is added last
-    z = fmaf(w2, R.dz2, w1 * R.dz1) + R.az;
-    inside = (R.E > 0.0) ? (e0 > 0.0 && e1 > 0.0 && e2 > 0.0) : (e0 < 0.0 && e1 < 0.0 && e2 < 0.0);
-    sx = (float)dx;
-    sy = (float)dy;
+    o.z = fmaf(o.w2, R.dz2, o.w1 * R.dz1) + R.az;
+    o.inside = fminf(o.w0, fminf(o.w1, o.w2)) > 0.0f;
+    o.sx = (float)dx;
+    o.sy = (float)dy;
 }
 
-// Squared distance to the triangle boundary and its nearest edge, from the
-// pixel offset s = p - a.
-__device__ __forceinline__ float eval_dist(const FaceRec& R, float sx, float sy, int& edge, float& u) {
+// Squared distances from the pixel to the three boundary segments.  For
+// segment P->Q with t = (p - P).(Q - P) / |Q - P|^2 the nearest point is P
+// (t <= 0), Q (t >= 1) or the foot of the perpendicular, at squared distance
+// e^2 / |Q - P|^2 from the edge function e of that edge (2 * the area of
+// (P, Q, p)), which is formed in FP64 and so keeps its accuracy however
+// close the pixel is to the line.
+struct EdgeD {
+    float d[3];  // squared distance per edge
+    float t[3];  // unclamped parameter per edge
+};
+__device__ __forceinline__ void eval_edges(const FaceRec& R, const Eval& b, EdgeD& o) {
     const float abx = (float)R.ab.x, aby = (float)R.ab.y, acx = (float)R.ac.x, acy = (float)R.ac.y;
-    const float Ax = -sx, Ay = -sy;  // a - p
-    float u0, u1, u2;
-    float d0 = seg_d2(Ax, Ay, abx, aby, u0);
-    float d1 = seg_d2(Ax + abx, Ay + aby, acx - abx, acy - aby, u1);
-    float d2 = seg_d2(Ax + acx, Ay + acy, -acx, -acy, u2);
-    float d = d0;
+    const float pax = b.sx, pay = b.sy;              // p - a
+    const float pbx = pax - abx, pby = pay - aby;    // p - b
+    const float pcx = pax - acx, pcy = pay - acy;    // p - c
+    const float bcx = acx - abx, bcy = acy - aby;    // c - b
+    const float da = fmaf(pax, pax, pay * pay), db = fmaf(pbx, pbx, pby * pby), dc = fmaf(pcx, pcx, pcy * pcy);
+    o.t[0] = fmaf(pax, abx, pay * aby) * R.il0;
+    o.t[1] = fmaf(pbx, bcx, pby * bcy) * R.il1;
+    o.t[2] = -fmaf(pcx, acx, pcy * acy) * R.il2;
+    const float q0 = b.f2 * b.f2 * R.il0, q1 = b.f0 * b.f0 * R.il1, q2 = b.f1 * b.f1 * R.il2;
+    o.d[0] = o.t[0] <= 0.0f ? da : (o.t[0] >= 1.0f ? db : q0);
+    o.d[1] = o.t[1] <= 0.0f ? db : (o.t[1] >= 1.0f ? dc : q1);
+    o.d[2] = o.t[2] <= 0.0f ? dc : (o.t[2] >= 1.0f ? da : q2);
+}
+
+// Nearest edge (lowest index on ties), its squared distance and clamped parameter.
+__device__ __forceinline__ void eval_dist(const FaceRec& R, Eval& o) {
+    EdgeD ed;
+    eval_edges(R, o, ed);
+    float d = ed.d[0], t = ed.t[0];
     int e = 0;
-    float uu = u0;
-    if (d1 < d) { d = d1; e = 1; uu = u1; }
-    if (d2 < d) { d = d2; e = 2; uu = u2; }
-    edge = e;
-    u = uu;
-    return d;
+    if (ed.d[1] < d) { d = ed.d[1]; e = 1; t = ed.t[1]; }
+    if (ed.d[2] < d) { d = ed.d[2]; e = 2; t = ed.t[2]; }
+    o.d2 = d;
+    o.edge = e;
+    o.u = fminf(fmaxf(t, 0.0f), 1.0f);
 }
 
 __device__ __forceinline__ void eval_full(const FaceRec& R, const Pix& p, Eval& o) {
-    eval_bary(R, p, o.w0, o.w1, o.w2, o.z, o.inside, o.sx, o.sy);
-    o.d2 = eval_dist(R, o.sx, o.sy, o.edge, o.u);
+    eval_bary(R, p, o);
+    eval_dist(R, o);
 }
 
 __device__ __forceinline__ bool in_bbox(const FaceRec& R, const Pix& p) {
@@ -185,29 +201,20 @@ __device__ __forceinline__ bool in_bbox(const FaceRec& R, const Pix& p) {
 // Does face R count for pixel p, given that p lies in R's grown box?  On
 // success z is its depth.
 __device__ __forceinline__ bool face_counts_in_box(const FaceRec& R, const Pix& p, float blur, float& z) {
-    float w0, w1, w2, sx, sy;
-    bool inside;
-    eval_bary(R, p, w0, w1, w2, z, inside, sx, sy);
-    if (!(z >= 0.0f)) return false;
-    if (inside) return true;
-    int e;
-    float u;
-    float d2 = eval_dist(R, sx, sy, e, u);
-    return d2 < blur;
+    Eval b;
+    eval_bary(R, p, b);
+    z = b.z;
+    if (!(b.z >= 0.0f)) return false;
+    if (b.inside) return true;
+    EdgeD ed;
+    eval_edges(R, b, ed);
+    return fminf(ed.d[0], fminf(ed.d[1], ed.d[2])) < blur;
 }
 
 // Does face R count for pixel p?  On success z is its depth.
 __device__ __forceinline__ bool face_counts(const FaceRec& R, const Pix& p, float blur, float& z) {
     if (!in_bbox(R, p)) return false;
-    float w0, w1, w2, sx, sy;
-    bool inside;
-    eval_bary(R, p, w0, w1, w2, z, inside, sx, sy);
-    if (!(z >= 0.0f)) return false;
-    if (inside) return true;
-    int e;
-    float u;
-    float d2 = eval_dist(R, sx, sy, e, u);
-    return d2 < blur;
+    return face_counts_in_box(R, p, blur, z);
 }
 
 // Mesh of face f: the last n with first[n] <= f, if f lies in its range.

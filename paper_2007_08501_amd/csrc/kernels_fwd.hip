@@ -1,6 +1,6 @@
 // kernels_fwd.hip -- forward rasterization kernels for gfx950.
 //
-//   face_setup      one thread per face: mesh id, 96-byte record, padded bbox
+//   face_setup      one thread per face: mesh id, 112-byte record, padded bbox
 //   bin_faces       one thread per face: append the face to every bin its bbox
 //                   touches (counting only when lists == nullptr)
 //   bin_max         largest bin count -> workspace header, overflow flag
@@ -353,11 +353,12 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
         const int64_t e = c0 + lane;
         const bool in_list = e < cnt;
         const int fid = in_list ? (BINNED ? list[e] : (int)(base + e)) : 0;
-        // the record as six 16-byte words (see FaceRec): [3].z = a.z,
-        // [4].x/.y = b.z - a.z / c.z - a.z, [5] = grown box
+        // the record as seven 16-byte words, the last one the grown box
+        static_assert(sizeof(FaceRec) == 7 * sizeof(float4), "face record layout");
         const float4* rsrc = reinterpret_cast<const float4*>(a.recs + (in_list ? fid : (BINNED ? list[0] : (int)base)));
         const float4 rv0 = rsrc[0], rv1 = rsrc[1], rv2 = rsrc[2], rv3 = rsrc[3], rv4 = rsrc[4], rv5 = rsrc[5];
-        const float4 bb = rv5;
+        const float4 rv6 = rsrc[6];
+        const float4 bb = rv6;
         const bool keep = in_list && !(bb.y < tx_lo || bb.x > tx_hi || bb.w < ty_lo || bb.z > ty_hi);
         const uint64_t kept = __ballot(keep);
         const int m = __popcll(kept);
@@ -370,6 +371,7 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
             rdst[3] = rv3;
             rdst[4] = rv4;
             rdst[5] = rv5;
+            rdst[6] = rv6;
             L.id[dst] = fid;
         }
         __syncthreads();
