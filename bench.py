@@ -167,7 +167,7 @@ def cpu_baseline_leg(b, cpu_seconds, v, f, fi, nf, out, gz_np, gb_np, gd_np, bs,
     p2f_s[pix_t] = torch.from_numpy(o["p2f"].astype(np.int32)).to(dev)
     gv_s = torch.empty_like(v)
     t = lambda a: torch.from_numpy(a).to(dev)
-    _lib.rasterize_meshes_bwd(v, f, fi, nf, H, W, b.blur_radius, K, bs, M, p2f_s.view(N, H, W, K), t(gz_np),
+    _lib.rasterize_meshes_bwd(v, f, fi, nf, H, W, b.blur_radius, K, bs, M, 0, p2f_s.view(N, H, W, K), t(gz_np),
                               t(gb_np), t(gd_m), gv_s, bws)
     gvs = gv_s.cpu().numpy().astype(np.float64)
     gerr = float(np.abs(gvs - ref).max() / max(1e-30, np.abs(ref).max()))
@@ -243,8 +243,8 @@ def main():
     def step():
         _lib.rasterize_meshes_fwd(v, f, fi, nf, H, W, b.blur_radius, K, bs, M, sched, out.pix_to_face, out.zbuf,
                                   out.bary, out.dists, ws)
-        _lib.rasterize_meshes_bwd(v, f, fi, nf, H, W, b.blur_radius, K, bs, M, out.pix_to_face, gz, gb, gd, gv,
-                                  bws)
+        _lib.rasterize_meshes_bwd(v, f, fi, nf, H, W, b.blur_radius, K, bs, M, _lib.RAST_BWD_REUSE_FORWARD,
+                                  out.pix_to_face, gz, gb, gd, gv, ws)
 
     ev = HipEvents()
     for _ in range(args.warmup):
@@ -315,7 +315,7 @@ def main():
             for fm, o1, z0, c1 in calls:
                 _lib.rasterize_meshes_fwd(v, fm, z0, c1, H, W, b.blur_radius, K, 0, 0, 0, o1.pix_to_face, o1.zbuf,
                                           o1.bary, o1.dists, one_ws)
-                _lib.rasterize_meshes_bwd(v, fm, z0, c1, H, W, b.blur_radius, K, 0, 0, o1.pix_to_face, gz[:1],
+                _lib.rasterize_meshes_bwd(v, fm, z0, c1, H, W, b.blur_radius, K, 0, 0, 0, o1.pix_to_face, gz[:1],
                                           gb[:1], gd[:1], gvm, one_ws)
 
         per_mesh_step()

@@ -63,11 +63,15 @@ enum rast_status {
     RAST_EHIP = -3,        /* a HIP launch failed */
     RAST_EOVERFLOW = -4,   /* device: a bin received more than max_faces_per_bin faces */
     RAST_EMESH = -5,       /* device: mesh face ranges out of [0, F) or not ascending */
+    RAST_EREUSE = -6,      /* device: a backward asked to reuse bins that the workspace does not hold */
 };
 
 #define RAST_KMAX 64     /* largest faces_per_pixel */
 #define RAST_TILE 8      /* the forward's work unit is an 8x8 pixel tile */
 #define RAST_MAX_BIN 512 /* largest bin_size */
+
+/* Flags for rasterize_meshes_bwd. */
+#define RAST_BWD_REUSE_FORWARD 1 /* take face records and bins from the forward's workspace */
 
 /* Scheduling flags for rasterize_meshes_fwd. */
 #define RAST_SCHED_GRID 0       /* one workgroup per tile, hardware dispatch order */
@@ -118,6 +122,15 @@ int rasterize_meshes_fwd(const float* verts_packed, int64_t V, const int32_t* fa
  *   face's pixel box; > 0: it re-bins the faces and streams each bin's slots).
  *   A bin overflow sets RAST_EOVERFLOW in the workspace status and leaves
  *   grad_verts incomplete.
+ *   flags: 0 or RAST_BWD_REUSE_FORWARD.  With RAST_BWD_REUSE_FORWARD and
+ *   bin_size > 0, `workspace` must be the one the forward that produced
+ *   pix_to_face used, not used by any call since, and the vertices must not
+ *   have changed: the backward then takes the forward's face records and bins
+ *   (and keeps its status) instead of rebuilding them.  The forward stamps its
+ *   face count, image size, bin size, capacity and blur radius into the
+ *   workspace; if they differ from this call's, the status becomes RAST_EREUSE
+ *   and grad_verts is left zero.  Changed vertex contents cannot be detected.
+ *   With bin_size == 0 the flag has no effect.
  * The result accumulates with float atomics, so its last bits may differ
  * between runs.  workspace: at least rast_workspace_size(N, H, W, F,
  * bin_size, max_faces_per_bin) bytes.
@@ -125,7 +138,7 @@ int rasterize_meshes_fwd(const float* verts_packed, int64_t V, const int32_t* fa
 int rasterize_meshes_bwd(const float* verts_packed, int64_t V, const int32_t* faces_packed, int64_t F,
                          const int64_t* mesh_to_face_first_idx, const int64_t* num_faces_per_mesh,
                          int N, int H, int W, float blur_radius, int faces_per_pixel, int bin_size,
-                         int max_faces_per_bin, const int32_t* pix_to_face, const float* grad_zbuf,
+                         int max_faces_per_bin, int flags, const int32_t* pix_to_face, const float* grad_zbuf,
                          const float* grad_bary, const float* grad_dists, float* grad_verts, void* workspace,
                          size_t workspace_bytes, void* stream);
 
@@ -142,7 +155,7 @@ int rast_bin_count(const float* verts_packed, int64_t V, const int32_t* faces_pa
 
 /*
  * Synchronises `stream`, then reads the sticky status of the last call that
- * used this workspace: *status = RAST_OK, RAST_EOVERFLOW or RAST_EMESH;
+ * used this workspace: *status = RAST_OK, RAST_EOVERFLOW, RAST_EMESH or RAST_EREUSE;
  * *max_bin_count (may be NULL) = the largest bin count seen by the last
  * binned forward or rast_bin_count.
  */

@@ -7,7 +7,8 @@ imports the product path: the two share nothing but the seeded input
 generator, which holds none of the method's arithmetic.
 
 The rasterizer oracle is plain C (``oracle_rast.c``, built here with gcc and
-loaded with ctypes); the blend oracle is NumPy in float64 (``blend.py``).
+loaded with ctypes); the blend oracle is NumPy in float64 (``blend.py``); the
+silhouette-fitting loss and its gradient chain them (``silfit.py``).
 """
 from __future__ import annotations
 

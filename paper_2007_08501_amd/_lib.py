@@ -21,6 +21,8 @@ RAST_EWORKSPACE = -2
 RAST_EHIP = -3
 RAST_EOVERFLOW = -4
 RAST_EMESH = -5
+RAST_EREUSE = -6
+RAST_BWD_REUSE_FORWARD = 1
 RAST_KMAX = 64
 RAST_TILE = 8
 RAST_MAX_BIN = 512
@@ -56,7 +58,7 @@ def lib() -> ctypes.CDLL:
         sz = ctypes.c_size_t
         L.rast_workspace_size.argtypes = [ci, ci, ci, i64, ci, ci, ctypes.POINTER(sz)]
         L.rasterize_meshes_fwd.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, cf, ci, ci, ci, ci, P, P, P, P, P, sz, P]
-        L.rasterize_meshes_bwd.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, cf, ci, ci, ci, P, P, P, P, P, P, sz, P]
+        L.rasterize_meshes_bwd.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, cf, ci, ci, ci, ci, P, P, P, P, P, P, sz, P]
         L.rast_bin_count.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, cf, ci, P, sz, P]
         L.rast_query_status.argtypes = [P, ctypes.POINTER(ci), ctypes.POINTER(ci), P]
         L.rast_status_string.argtypes = [ci]
@@ -140,7 +142,7 @@ def rasterize_meshes_fwd(verts, faces, first_idx, num_faces, H, W, blur_radius, 
 
 
 def rasterize_meshes_bwd(verts, faces, first_idx, num_faces, H, W, blur_radius, K, bin_size, max_faces_per_bin,
-                         pix_to_face, grad_zbuf, grad_bary, grad_dists, grad_verts, workspace):
+                         flags, pix_to_face, grad_zbuf, grad_bary, grad_dists, grad_verts, workspace):
     dev = verts.device
     _require(verts, "verts", torch.float32, dev)
     _require(faces, "faces", torch.int32, dev)
@@ -154,8 +156,9 @@ def rasterize_meshes_bwd(verts, faces, first_idx, num_faces, H, W, blur_radius, 
     N = first_idx.shape[0]
     rc = lib().rasterize_meshes_bwd(_p(verts), verts.shape[0], _p(faces), faces.shape[0], _p(first_idx),
                                     _p(num_faces), int(N), int(H), int(W), float(blur_radius), int(K),
-                                    int(bin_size), int(max_faces_per_bin or 0), _p(pix_to_face), _p(grad_zbuf), _p(grad_bary), _p(grad_dists), _p(grad_verts),
-                                    _p(workspace), workspace.numel(), _stream(dev))
+                                    int(bin_size), int(max_faces_per_bin or 0), int(flags), _p(pix_to_face),
+                                    _p(grad_zbuf), _p(grad_bary), _p(grad_dists), _p(grad_verts), _p(workspace),
+                                    workspace.numel(), _stream(dev))
     _check("rasterize_meshes_bwd", rc)
 
 

@@ -72,14 +72,13 @@ def _time_candidate(verts, faces, first_idx, num_faces, H, W, blur, K, bs, M, sc
     out = empty_fragments(N, H, W, K, verts.device)
     ws = workspace(verts.device, _lib.rast_workspace_size(N, H, W, faces.shape[0], bs, M))
     gv = torch.empty_like(verts)
-    bws = torch.empty(_lib.rast_workspace_size(N, H, W, faces.shape[0], bs, M), dtype=torch.uint8,
-                      device=verts.device)
 
     def step():
         forward_into(verts, faces, first_idx, num_faces, H, W, blur, K, bs, M, sched, out, ws)
         if grads is not None:
-            _lib.rasterize_meshes_bwd(verts, faces, first_idx, num_faces, H, W, blur, K, bs, M, out.pix_to_face,
-                                      grads[0], grads[1], grads[2], gv, bws)
+            _lib.rasterize_meshes_bwd(verts, faces, first_idx, num_faces, H, W, blur, K, bs, M,
+                                      _lib.RAST_BWD_REUSE_FORWARD, out.pix_to_face, grads[0], grads[1], grads[2], gv,
+                                      ws)
 
     step()
     st, _ = _lib.rast_query_status(ws)

@@ -5,6 +5,7 @@
 #include <math.h>
 #include <stddef.h>
 #include <stdint.h>
+#include <string.h>
 
 #include <hip/hip_runtime.h>
 
@@ -101,6 +102,15 @@ thread_local KernelEvents tl_events;
 
 }  // namespace
 
+static rast::BinSig bin_signature(int64_t F, int N, int H, int W, int bs, int M, float blur) {
+    rast::BinSig g;
+    uint32_t bb;
+    memcpy(&bb, &blur, sizeof(bb));
+    const int w[rast::kSigWords] = {rast::kSigMarker, (int)F, N, H, W, bs, M, (int)bb};
+    for (int i = 0; i < rast::kSigWords; ++i) g.w[i] = w[i];
+    return g;
+}
+
 extern "C" {
 
 int rast_workspace_size(int N, int H, int W, int64_t F, int bin_size, int max_faces_per_bin, size_t* bytes_out) {
@@ -139,7 +149,9 @@ int rasterize_meshes_fwd(const float* verts_packed, int64_t V, const int32_t* fa
     rast::FaceRec* recs = (rast::FaceRec*)(ws + L.recs);
     int n_workers = (sched == RAST_SCHED_PERSISTENT) ? n_workers_for_current_device() : 0;
 
-    hipError_t e = rast::launch_fill_i32(hdr, rast::kHdrWords, 0, s);
+    // the header carries this call's binning signature for a backward that reuses the bins
+    hipError_t e = rast::launch_header_init(
+        hdr, bin_signature(F, N, H, W, bin_size, bin_size > 0 ? max_faces_per_bin : 0, blur_radius), s);
     if (e != hipSuccess) return RAST_EHIP;
     e = rast::launch_face_setup(verts_packed, V, faces_packed, F, mesh_to_face_first_idx, num_faces_per_mesh, N,
                                 sqrtf(blur_radius), recs, hdr, s);
@@ -149,7 +161,8 @@ int rasterize_meshes_fwd(const float* verts_packed, int64_t V, const int32_t* fa
     if (bin_size > 0) {
         counts = (int*)(ws + L.counts);
         lists = (int*)(ws + L.lists);
-        e = rast::launch_binning(recs, F, N, H, W, bin_size, max_faces_per_bin, counts, lists, hdr, s);
+        e = rast::launch_binning(recs, F, N, H, W, bin_size, max_faces_per_bin, counts, lists, hdr, s,
+                                 (int*)(ws + L.fpos));
         if (e != hipSuccess) return RAST_EHIP;
     }
     e = rast::launch_fine(recs, mesh_to_face_first_idx, num_faces_per_mesh, counts, lists, F, N, H, W,
@@ -162,7 +175,7 @@ int rasterize_meshes_fwd(const float* verts_packed, int64_t V, const int32_t* fa
 int rasterize_meshes_bwd(const float* verts_packed, int64_t V, const int32_t* faces_packed, int64_t F,
                          const int64_t* mesh_to_face_first_idx, const int64_t* num_faces_per_mesh, int N, int H,
                          int W, float blur_radius, int faces_per_pixel, int bin_size, int max_faces_per_bin,
-                         const int32_t* pix_to_face, const float* grad_zbuf, const float* grad_bary,
+                         int flags, const int32_t* pix_to_face, const float* grad_zbuf, const float* grad_bary,
                          const float* grad_dists, float* grad_verts, void* workspace, size_t workspace_bytes,
                          void* stream) {
     if (bad_dims(N, H, W, faces_per_pixel)) return RAST_EINVAL;
@@ -171,6 +184,7 @@ int rasterize_meshes_bwd(const float* verts_packed, int64_t V, const int32_t* fa
         return RAST_EINVAL;
     if (mesh_to_face_first_idx == nullptr || num_faces_per_mesh == nullptr) return RAST_EINVAL;
     if (pix_to_face == nullptr) return RAST_EINVAL;
+    if ((flags & ~RAST_BWD_REUSE_FORWARD) != 0) return RAST_EINVAL;
     if (!(blur_radius >= 0.0f) || !isfinite(blur_radius)) return RAST_EINVAL;
     if (bin_size < 0 || bin_size > RAST_MAX_BIN || (bin_size % RAST_TILE) != 0) return RAST_EINVAL;
     if (bin_size > 0 && max_faces_per_bin < 1) return RAST_EINVAL;
@@ -185,8 +199,9 @@ int rasterize_meshes_bwd(const float* verts_packed, int64_t V, const int32_t* fa
         verts_packed, V, faces_packed, F, mesh_to_face_first_idx, num_faces_per_mesh, N, H, W, faces_per_pixel,
         blur_radius, bin_size, max_faces_per_bin, pix_to_face, grad_zbuf, grad_bary, grad_dists, grad_verts,
         (int*)(ws + L.hdr), (rast::FaceRec*)(ws + L.recs), (int*)(ws + L.counts), (int*)(ws + L.lists),
-        (float*)(ws + L.partial), (int*)(ws + L.fpos), (int*)(ws + L.big), s, tl_events.begin[RAST_KERNEL_BWD],
-        tl_events.end[RAST_KERNEL_BWD]));
+        (float*)(ws + L.partial), (int*)(ws + L.fpos), (int*)(ws + L.big), (flags & RAST_BWD_REUSE_FORWARD) != 0,
+        bin_signature(F, N, H, W, bin_size, bin_size > 0 ? max_faces_per_bin : 0, blur_radius), s,
+        tl_events.begin[RAST_KERNEL_BWD], tl_events.end[RAST_KERNEL_BWD]));
 }
 
 int rast_set_kernel_events(int kernel, void* begin, void* end) {
@@ -232,6 +247,8 @@ int rast_query_status(const void* workspace, int* status, int* max_bin_count, vo
     int st = RAST_OK;
     if (h[0] & rast::kStatMesh)
         st = RAST_EMESH;
+    else if (h[0] & rast::kStatReuse)
+        st = RAST_EREUSE;
     else if (h[0] & rast::kStatOverflow)
         st = RAST_EOVERFLOW;
     *status = st;
@@ -247,6 +264,7 @@ const char* rast_status_string(int status) {
         case RAST_EHIP: return "HIP launch failed";
         case RAST_EOVERFLOW: return "a bin received more faces than max_faces_per_bin";
         case RAST_EMESH: return "mesh face ranges or vertex ids out of range";
+        case RAST_EREUSE: return "the workspace does not hold the bins of a matching forward";
         default: return "unknown status";
     }
 }

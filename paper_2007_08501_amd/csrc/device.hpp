@@ -33,9 +33,19 @@ enum : int {
     kHdrWorkTotal = 3,  // persistent scheduler: number of work items
     kHdrBigCount = 8,   // backward: number of faces with large pixel boxes
     kHdrBigNext = 9,    // backward: next large face to scan
+    kHdrSig = 16,       // kSigWords words: what the last forward binned (see BinSig)
     kHdrWords = 64,
 };
-enum : int { kStatOverflow = 1, kStatMesh = 2 };
+enum : int { kStatOverflow = 1, kStatMesh = 2, kStatReuse = 4 };
+
+// What a binned forward leaves in its workspace for a backward that reuses
+// its face records and bins: a marker, F, N, H, W, bin size, capacity and
+// the bit pattern of the blur radius.
+constexpr int kSigWords = 8;
+constexpr int kSigMarker = 0x52535447;
+struct BinSig {
+    int w[kSigWords];
+};
 
 // Pixel centre in NDC: x = 1 - (2c+1)/W, y = 1 - (2r+1)/H.  The FP32 value
 // (exact for power-of-two sizes) is used for box tests and tile extents, the
@@ -279,13 +289,15 @@ constexpr uint64_t kEmptyKey = ~0ull;
 // Register-resident sorted list of the KB smallest keys; every slot is a
 // compare-exchange with the travelling key, so the array is only ever
 // indexed with compile-time constants.
-// Compare-exchange: a <- min, b <- max.
+// Compare-exchange: a <- min, b <- max.  One 64-bit compare drives four
+// 32-bit selects (written on the halves so that the compiler does not turn
+// the pair into a separate min and max with a compare each).
 __device__ __forceinline__ void cex(uint64_t& a, uint64_t& b) {
     const bool lt = b < a;
-    const uint64_t lo = lt ? b : a;
-    const uint64_t hi = lt ? a : b;
-    a = lo;
-    b = hi;
+    const uint32_t al = (uint32_t)a, ah = (uint32_t)(a >> 32), bl = (uint32_t)b, bh = (uint32_t)(b >> 32);
+    const uint32_t ll = lt ? bl : al, lh = lt ? bh : ah, hl = lt ? al : bl, hh = lt ? ah : bh;
+    a = ((uint64_t)lh << 32) | ll;
+    b = ((uint64_t)hh << 32) | hl;
 }
 
 // Sorts eight keys ascending with a 19-comparator network.

@@ -52,7 +52,21 @@ struct BwdArgs {
     float fix_limit;   // contributions below this magnitude use the fixed-point sums
     const int* fpos;   // (F, 4): position of a face in each bin of its range (ranges of <= 4 bins)
     int bs, nby, nbx, M;
+    int reuse;         // records and bins come from the forward: check its signature first
+    BinSig sig;        // the signature this call expects
 };
+
+// False (and the status flagged) when a backward that reuses the forward's
+// bins finds another call's signature in the workspace.  Every thread of a
+// workgroup reads the same words, so the answer is uniform.
+__device__ __forceinline__ bool bins_usable(const BwdArgs& a) {
+    if (!a.reuse) return true;
+    bool same = true;
+#pragma unroll
+    for (int i = 0; i < kSigWords; ++i) same = same && (a.hdr[kHdrSig + i] == a.sig.w[i]);
+    if (!same && threadIdx.x == 0) atomicOr(&a.hdr[kHdrStatus], kStatReuse);
+    return same;
+}
 
 struct FaceGrad {
     float gx[3], gy[3], gzv[3];
@@ -349,6 +363,7 @@ __global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a) {
     __shared__ float acc[kP1Chunk * 9];
     __shared__ int tkey[kP1Table];
     __shared__ int tval[kP1Table];
+    if (!bins_usable(a)) return;
     const int64_t bin = blockIdx.x;
     const int per_img = a.nby * a.nbx;
     const int n = (int)(bin / per_img);
@@ -460,6 +475,7 @@ __global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a) {
 __global__ __launch_bounds__(kBwdBlock) void bwd_face_sum_kernel(BwdArgs a) {
     __shared__ int keys[kHash];
     __shared__ float vals[3 * kHash];
+    if (!bins_usable(a)) return;
     for (int i = threadIdx.x; i < kHash; i += kBwdBlock) {
         keys[i] = -1;
         vals[3 * i] = vals[3 * i + 1] = vals[3 * i + 2] = 0.0f;
@@ -508,11 +524,14 @@ hipError_t launch_backward(const float* verts, int64_t V, const int32_t* faces, 
                            const int64_t* nf, int N, int H, int W, int K, float blur, int bs, int M,
                            const int32_t* p2f, const float* gz, const float* gb, const float* gd, float* grad,
                            int* hdr, FaceRec* recs, int* counts, int* lists, float* partial, int* fpos, int* big,
-                           hipStream_t s, hipEvent_t eb, hipEvent_t ee) {
+                           bool reuse, const BinSig& sig, hipStream_t s, hipEvent_t eb, hipEvent_t ee) {
+    reuse = reuse && bs > 0;
     hipError_t e = launch_fill_f32(grad, V * 3, 0.0f, s);
     if (e != hipSuccess) return e;
-    e = launch_fill_i32(hdr, kHdrWords, 0, s);
-    if (e != hipSuccess) return e;
+    if (!reuse) {
+        e = launch_fill_i32(hdr, kHdrWords, 0, s);
+        if (e != hipSuccess) return e;
+    }
     if (F == 0) return hipSuccess;
     BwdArgs a;
     a.verts = verts;
@@ -549,12 +568,17 @@ hipError_t launch_backward(const float* verts, int64_t V, const int32_t* faces, 
     a.nby = bs > 0 ? (H + bs - 1) / bs : 0;
     a.nbx = bs > 0 ? (W + bs - 1) / bs : 0;
     a.M = M;
+    a.reuse = reuse ? 1 : 0;
+    a.sig = sig;
     if (bs > 0) {
-        // the same face setup and binning as the forward, then the two passes
-        e = launch_face_setup(verts, V, faces, F, first, nf, N, a.rb, recs, hdr, s);
-        if (e != hipSuccess) return e;
-        e = launch_binning(recs, F, N, H, W, bs, M, counts, lists, hdr, s, fpos);
-        if (e != hipSuccess) return e;
+        // the same face setup and binning as the forward (unless the forward's
+        // are reused), then the two passes
+        if (!reuse) {
+            e = launch_face_setup(verts, V, faces, F, first, nf, N, a.rb, recs, hdr, s);
+            if (e != hipSuccess) return e;
+            e = launch_binning(recs, F, N, H, W, bs, M, counts, lists, hdr, s, fpos);
+            if (e != hipSuccess) return e;
+        }
         const int64_t nbins = (int64_t)N * a.nby * a.nbx;
         if (eb) (void)hipEventRecord(eb, s);
         hipLaunchKernelGGL(bwd_bins_kernel, dim3((unsigned)nbins), dim3(kP1Threads), 0, s, a);

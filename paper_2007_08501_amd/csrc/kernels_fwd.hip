@@ -42,6 +42,17 @@ hipError_t launch_fill_i32(int* p, int64_t n, int v, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Clears the workspace header and stamps the binning signature.
+__global__ void header_init_kernel(int* __restrict__ hdr, BinSig sig) {
+    for (int i = threadIdx.x; i < kHdrWords; i += blockDim.x)
+        hdr[i] = (i >= kHdrSig && i < kHdrSig + kSigWords) ? sig.w[i - kHdrSig] : 0;
+}
+
+hipError_t launch_header_init(int* hdr, const BinSig& sig, hipStream_t s) {
+    hipLaunchKernelGGL(header_init_kernel, dim3(1), dim3(64), 0, s, hdr, sig);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill_f32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);

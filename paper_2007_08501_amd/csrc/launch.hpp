@@ -10,6 +10,7 @@ namespace rast {
 
 hipError_t launch_fill_i32(int* p, int64_t n, int v, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+hipError_t launch_header_init(int* hdr, const BinSig& sig, hipStream_t s);
 
 hipError_t launch_face_setup(const float* verts, int64_t V, const int32_t* faces, int64_t F, const int64_t* first,
                              const int64_t* nf, int N, float rb, FaceRec* recs, int* hdr, hipStream_t s);
@@ -26,8 +27,7 @@ hipError_t launch_backward(const float* verts, int64_t V, const int32_t* faces, 
                            const int64_t* nf, int N, int H, int W, int K, float blur, int bs, int M,
                            const int32_t* p2f, const float* gz, const float* gb, const float* gd, float* grad,
                            int* hdr, FaceRec* recs, int* counts, int* lists, float* partial, int* fpos, int* big,
-                           hipStream_t s,
-                           hipEvent_t ev_begin, hipEvent_t ev_end);
+                           bool reuse, const BinSig& sig, hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end);
 
 hipError_t launch_blend_fwd(const int32_t* p2f, const float* d, int64_t P, int K, float sigma, float* alpha,
                             hipStream_t s);

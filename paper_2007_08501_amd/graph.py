@@ -37,8 +37,6 @@ class GraphRunner:
             self.grad_bary = torch.zeros((N, H, W, K, 3), device=dev)
             self.grad_dists = torch.zeros((N, H, W, K), device=dev)
             self.grad_verts = torch.empty_like(self.verts)
-            self.bws = torch.empty(_lib.rast_workspace_size(N, H, W, self.faces.shape[0], bin_size,
-                                                            max_faces_per_bin), dtype=torch.uint8, device=dev)
         self.graph = None
 
     def set_verts(self, verts):
@@ -55,9 +53,11 @@ class GraphRunner:
         _lib.rasterize_meshes_fwd(self.verts, self.faces, self.first_idx, self.num_faces, H, W, blur, K, bs, M, sched,
                                   self.out.pix_to_face, self.out.zbuf, self.out.bary, self.out.dists, self.ws)
         if self.backward:
+            # the backward reuses the forward's face records and bins in the same workspace
             _lib.rasterize_meshes_bwd(self.verts, self.faces, self.first_idx, self.num_faces, H, W, blur, K, bs, M,
+                                      _lib.RAST_BWD_REUSE_FORWARD,
                                       self.out.pix_to_face, self.grad_zbuf, self.grad_bary, self.grad_dists,
-                                      self.grad_verts, self.bws)
+                                      self.grad_verts, self.ws)
 
     def capture(self, warmup: int = 2):
         s = torch.cuda.Stream(device=self.device)

@@ -102,8 +102,8 @@ class _RasterizeMeshes(torch.autograd.Function):
         N = first_idx.shape[0]
         out = empty_fragments(N, H, W, K, verts.device)
         vd = verts.detach().contiguous()
-        need = _lib.rast_workspace_size(N, H, W, faces.shape[0], bs, M)
-        ws = workspace(verts.device, need)
+        # a workspace of this call's own: its backward reuses the face records and bins
+        ws = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, faces.shape[0], bs, M), verts.device)
         forward_into(vd, faces, first_idx, num_faces, H, W, blur, K, bs, M, sched, out, ws)
         if check:
             st, mx = _lib.rast_query_status(ws)
@@ -116,6 +116,7 @@ class _RasterizeMeshes(torch.autograd.Function):
         ctx.dims = (N, H, W, K)
         ctx.blur = blur
         ctx.bins = (bs, M)
+        ctx.ws = ws
         return out.pix_to_face, out.zbuf, out.bary, out.dists
 
     @staticmethod
@@ -128,9 +129,12 @@ class _RasterizeMeshes(torch.autograd.Function):
 
         grad_verts = torch.empty_like(verts)
         bs, M = ctx.bins
-        ws = workspace(verts.device, _lib.rast_workspace_size(N, H, W, faces.shape[0], bs, M))
-        _lib.rasterize_meshes_bwd(verts, faces, first_idx, num_faces, H, W, ctx.blur, K, bs, M, p2f, prep(g_zbuf),
-                                  prep(g_bary), prep(g_dists), grad_verts, ws)
+        # the saved vertices cannot have changed (autograd checks their version),
+        # so the forward's face records and bins are still valid
+        _lib.rasterize_meshes_bwd(verts, faces, first_idx, num_faces, H, W, ctx.blur, K, bs, M,
+                                  _lib.RAST_BWD_REUSE_FORWARD, p2f, prep(g_zbuf), prep(g_bary), prep(g_dists),
+                                  grad_verts, ctx.ws)
+        ctx.ws = None
         return (grad_verts,) + (None,) * 11
 
 
@@ -153,8 +157,11 @@ def rasterize_meshes(verts, faces, first_idx, num_faces, settings: RasterSetting
         bs, M, sched = choice.bin_size, choice.max_faces_per_bin, choice.sched
     else:
         sched = settings.sched
-    auto_M = bs > 0 and M is None
-    if auto_M:
+    # a capacity the caller did not fix is recounted when a bin overflows (the
+    # autotuner's comes from a cache keyed on the batch's statistics, not on
+    # these vertices)
+    auto_M = bs > 0 and settings.max_faces_per_bin is None
+    if bs > 0 and M is None:
         M = round_up(count_max_faces_per_bin(verts.detach(), faces, first_idx, num_faces, H, W,
                                              settings.blur_radius, bs), 32)
     try:

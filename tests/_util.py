@@ -67,18 +67,20 @@ def bin_capacity(b, bs, dev_inputs=None):
     return max(1, mx)
 
 
-def run_bwd(b, p2f, gz, gb, gd, dev_inputs=None, bs=0, M=None, check=True):
+def run_bwd(b, p2f, gz, gb, gd, dev_inputs=None, bs=0, M=None, check=True, flags=0, ws=None):
     """Backward through the C ABI; bs/M are the binning of the forward
-    (bs 0 = per-face form)."""
+    (bs 0 = per-face form).  flags/ws: reuse a forward's workspace."""
     v, f, fi, nf = dev_inputs or to_dev(b)
     H, W = b.image_size
     N, K = p2f.shape[0], p2f.shape[-1]
     if bs > 0 and M is None:
         M = bin_capacity(b, bs, (v, f, fi, nf))
     gv = torch.empty_like(v)
-    ws = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, f.shape[0], bs, M or 0), v.device)
+    if ws is None:
+        ws = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, f.shape[0], bs, M or 0), v.device)
     t = lambda a: None if a is None else (a if isinstance(a, torch.Tensor) else torch.from_numpy(a).to(v.device))
-    _lib.rasterize_meshes_bwd(v, f, fi, nf, H, W, b.blur_radius, K, bs, M or 0, p2f, t(gz), t(gb), t(gd), gv, ws)
+    _lib.rasterize_meshes_bwd(v, f, fi, nf, H, W, b.blur_radius, K, bs, M or 0, flags, p2f, t(gz), t(gb), t(gd), gv,
+                              ws)
     if check:
         st, _ = _lib.rast_query_status(ws)
         assert st == _lib.RAST_OK, _lib.status_string(st)

@@ -93,9 +93,13 @@ def test_forward_rejects_bad_workspace():
 
 def test_backward_rejects_bad_arguments():
     L = _lib.lib()
-    args = [FAKE, 3, FAKE, 1, FAKE, FAKE, 1, 8, 8, 0.0, 1, 0, 0, FAKE, None, None, None, FAKE, None, 0, None]
+    args = [FAKE, 3, FAKE, 1, FAKE, FAKE, 1, 8, 8, 0.0, 1, 0, 0, 0, FAKE, None, None, None, FAKE, None, 0, None]
     assert L.rasterize_meshes_bwd(*args) == _lib.RAST_EWORKSPACE
-    for i, v in ((13, None), (17, None), (10, 100), (9, -1.0), (4, None), (5, None), (6, 0), (11, 12), (11, -8)):
+    reuse = list(args)
+    reuse[13] = _lib.RAST_BWD_REUSE_FORWARD
+    assert L.rasterize_meshes_bwd(*reuse) == _lib.RAST_EWORKSPACE
+    for i, v in ((14, None), (18, None), (10, 100), (9, -1.0), (4, None), (5, None), (6, 0), (11, 12), (11, -8),
+                 (13, 2), (13, -1)):
         bad = list(args)
         bad[i] = v
         assert L.rasterize_meshes_bwd(*bad) == _lib.RAST_EINVAL, i

@@ -5,6 +5,8 @@ seeded pixel samples (forward, and backward over the oracle's selection on
 those pixels), plus size-independent invariants.  The oracle never takes an
 input produced by the GPU.
 """
+import copy
+
 import numpy as np
 import pytest
 import torch
@@ -13,7 +15,7 @@ import oracle
 from paper_2007_08501_amd import _lib, meshgen
 from paper_2007_08501_amd.raster import empty_fragments
 
-from _util import (compare_fwd, compare_grad, frag_numpy, invariants_torch, log, run_bwd, run_fwd,
+from _util import (bin_capacity, compare_fwd, compare_grad, frag_numpy, invariants_torch, log, run_bwd, run_fwd,
                    threads, tie_masked_grads, to_dev)
 
 pytestmark = pytest.mark.gpu
@@ -365,3 +367,39 @@ def test_graph_replay_matches_eager():
     e, _ = run_fwd(b2, 16, M=2 * mx + 64, sched=1)
     for x, y in zip(e, gr.out):
         assert torch.equal(x, y)
+
+
+# ----------------------------------------------------------------- backward reusing the forward's bins
+
+def test_backward_reuse_matches_rebuild_and_checks_signature():
+    b = meshgen.make_config(3, n_override=5, level_override=4, image_override=96)
+    d = to_dev(b)
+    gz, gb, gd = [torch.from_numpy(x).cuda() for x in meshgen.upstream_grads(b)]
+    for bs in (8, 16):
+        out, ws = run_fwd(b, bs, dev_inputs=d)
+        M = bin_capacity(b, bs, d)
+        fresh = run_bwd(b, out.pix_to_face, gz, gb, gd, dev_inputs=d, bs=bs, M=M)
+        out, ws = run_fwd(b, bs, M=M, dev_inputs=d)
+        reused = run_bwd(b, out.pix_to_face, gz, gb, gd, dev_inputs=d, bs=bs, M=M,
+                         flags=_lib.RAST_BWD_REUSE_FORWARD, ws=ws)
+        torch.testing.assert_close(reused, fresh, rtol=0, atol=1e-5 * float(fresh.abs().max()))
+        # a second reuse of the same workspace is still valid (nothing rebuilt it)
+        again = run_bwd(b, out.pix_to_face, gz, gb, gd, dev_inputs=d, bs=bs, M=M,
+                        flags=_lib.RAST_BWD_REUSE_FORWARD, ws=ws)
+        torch.testing.assert_close(again, fresh, rtol=0, atol=1e-5 * float(fresh.abs().max()))
+        # another blur radius than the forward's: refused, gradients left zero
+        b2 = copy.copy(b)
+        b2.blur_radius = b.blur_radius * 2
+        bad = run_bwd(b2, out.pix_to_face, gz, gb, gd, dev_inputs=d, bs=bs, M=M,
+                      flags=_lib.RAST_BWD_REUSE_FORWARD, ws=ws, check=False)
+        st, _ = _lib.rast_query_status(ws)
+        assert st == _lib.RAST_EREUSE and not bad.any()
+        # a counting pass in between clears the forward's signature
+        out, ws = run_fwd(b, bs, M=M, dev_inputs=d)
+        v, f, fi, nf = d
+        H, W = b.image_size
+        _lib.rast_bin_count(v, f, fi, nf, H, W, b.blur_radius, bs, ws)
+        run_bwd(b, out.pix_to_face, gz, gb, gd, dev_inputs=d, bs=bs, M=M, flags=_lib.RAST_BWD_REUSE_FORWARD, ws=ws,
+                check=False)
+        st, _ = _lib.rast_query_status(ws)
+        assert st == _lib.RAST_EREUSE

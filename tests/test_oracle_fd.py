@@ -180,3 +180,51 @@ def test_fragments_fixed_pixel_list_matches_full():
         np.testing.assert_array_equal(a.reshape((2 * H * W,) + a.shape[3:])[pix], b)
     # the frozen-selection values are those of the free forward at the same slots
     np.testing.assert_allclose(part[0], o["zbuf"].reshape(2 * H * W, 4)[pix], rtol=0, atol=1e-12)
+
+
+def _tiny_fit(seed=11):
+    prob = meshgen.silhouette_fit_problem(level=1, n_views=3, seed=seed)
+    return prob
+
+
+def test_silfit_gradient_matches_frozen_selection_fd():
+    """The fitting loss's analytic gradient (fixed selection) against central
+    differences of the frozen-selection loss, every coordinate of a level-1
+    template in three 24x24 views."""
+    from oracle import silfit
+    prob = _tiny_fit()
+    H, K, blur, sigma = 24, 8, 5e-3, 2e-3
+    target = silfit.target_silhouettes(prob.target, prob.rotations, prob.faces, H, K, blur, sigma)
+    off = np.random.default_rng(4).standard_normal(prob.base.shape) * 0.01
+    loss, g, p2f = silfit.loss_and_grad(prob.base, prob.rotations, prob.faces, off, target, H, K, blur, sigma)
+    assert 0.0 < loss < 1.0
+    h = 1e-6
+    fd = np.zeros_like(g)
+    for i in range(g.shape[0]):
+        for c in range(3):
+            e = np.zeros_like(off)
+            e[i, c] = h
+            lp = silfit.frozen_loss(prob.base, prob.rotations, prob.faces, off + e, target, H, p2f, sigma)
+            lm = silfit.frozen_loss(prob.base, prob.rotations, prob.faces, off - e, target, H, p2f, sigma)
+            fd[i, c] = (lp - lm) / (2 * h)
+    scale = np.abs(fd).max()
+    assert scale > 0
+    # the analytic side sees FP32 vertices (as the rasterizer does), the FD side FP64 ones
+    np.testing.assert_allclose(g, fd, rtol=0, atol=2e-4 * scale)
+
+
+def test_iou_grad_fd_and_zero_loss_at_target():
+    from oracle import silfit
+    rng = np.random.default_rng(9)
+    S = rng.uniform(0, 1, (2, 5, 6))
+    T = rng.uniform(0, 1, (2, 5, 6))
+    g = silfit.iou_loss_grad(S, T)
+    h = 1e-7
+    for idx in [(0, 1, 2), (1, 4, 5), (0, 0, 0)]:
+        e = np.zeros_like(S)
+        e[idx] = h
+        fd = (oracle.iou_loss(S + e, T) - oracle.iou_loss(S - e, T)) / (2 * h)
+        assert abs(fd - g[idx]) < 1e-6 * max(1.0, abs(fd))
+    # a binary silhouette that equals its target has IoU 1 and loss 0, and is a stationary point
+    B = (rng.uniform(0, 1, (2, 5, 6)) > 0.5).astype(np.float64)
+    assert oracle.iou_loss(B, B) == 0.0
