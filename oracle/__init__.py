@@ -165,4 +165,5 @@ def backward(verts, faces, image_size, p2f, grad_zbuf=None, grad_bary=None, grad
     return out
 
 
-from .blend import silhouette_blend, silhouette_blend_backward, iou_loss  # noqa: E402,F401
+from .blend import (iou_loss, silhouette_blend, silhouette_blend_backward, softmax_blend,  # noqa: E402,F401
+                    softmax_blend_backward)
