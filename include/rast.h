@@ -197,6 +197,37 @@ int silhouette_blend_fwd(const int32_t* pix_to_face, const float* dists, int64_t
 int silhouette_blend_bwd(const int32_t* pix_to_face, const float* dists, const float* grad_alpha, int64_t P,
                          int K, float sigma, float* grad_dists, void* stream);
 
+/*
+ * Softmax blend (paper, Section 3.2, Algorithm 2) over P pixels of K slots
+ * and C channels (C in [1, RAST_SOFTMAX_CMAX]):
+ *   prob_k = sigmoid(-dists_k / sigma), zinv_k = (zfar - zbuf_k) / (zfar - znear),
+ *   w_k = prob_k exp((zinv_k - max_j zinv_j) / gamma),
+ *   image_c = sum_k w_k colors_kc / sum_k w_k.
+ * Slots with pix_to_face == -1 take no part (no weight, no say in the max);
+ * a pixel whose weights sum to 0 gets 0.
+ *   pix_to_face (P,K) i32, zbuf (P,K) f32, dists (P,K) f32 -- Fragments;
+ *   colors (P,K,C) f32 -- per-slot colours; image (P,C) f32, overwritten.
+ *   sigma > 0, gamma > 0, zfar > znear, all finite.
+ */
+#define RAST_SOFTMAX_CMAX 8
+int softmax_blend_fwd(const int32_t* pix_to_face, const float* zbuf, const float* dists, const float* colors,
+                      int64_t P, int K, int C, float sigma, float gamma, float znear, float zfar, float* image,
+                      void* stream);
+
+/*
+ * Backward of softmax_blend_fwd for L = <grad_image, image>.  With
+ * G_k = sum_c grad_image_c (colors_kc - image_c) / sum_j w_j:
+ *   grad_dists_k = -G_k w_k (1 - prob_k) / sigma,
+ *   grad_zbuf_k = -G_k w_k / (gamma (zfar - znear)),
+ *   grad_colors_kc = grad_image_c w_k / sum_j w_j;
+ * 0 for empty slots and for pixels whose weights sum to 0.  Each of
+ * grad_zbuf (P,K), grad_dists (P,K), grad_colors (P,K,C) may be NULL (not
+ * computed); the others are overwritten.
+ */
+int softmax_blend_bwd(const int32_t* pix_to_face, const float* zbuf, const float* dists, const float* colors,
+                      int64_t P, int K, int C, float sigma, float gamma, float znear, float zfar,
+                      const float* grad_image, float* grad_zbuf, float* grad_dists, float* grad_colors, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -66,8 +66,11 @@ def lib() -> ctypes.CDLL:
         L.rast_set_kernel_events.argtypes = [ci, P, P]
         L.silhouette_blend_fwd.argtypes = [P, P, i64, ci, cf, P, P]
         L.silhouette_blend_bwd.argtypes = [P, P, P, i64, ci, cf, P, P]
+        L.softmax_blend_fwd.argtypes = [P, P, P, P, i64, ci, ci, cf, cf, cf, cf, P, P]
+        L.softmax_blend_bwd.argtypes = [P, P, P, P, i64, ci, ci, cf, cf, cf, cf, P, P, P, P, P]
         for fn in ("rast_workspace_size", "rasterize_meshes_fwd", "rasterize_meshes_bwd", "rast_bin_count",
-                   "rast_query_status", "silhouette_blend_fwd", "silhouette_blend_bwd", "rast_set_kernel_events"):
+                   "rast_query_status", "silhouette_blend_fwd", "silhouette_blend_bwd", "rast_set_kernel_events",
+                   "softmax_blend_fwd", "softmax_blend_bwd"):
             getattr(L, fn).restype = ci
         _lib = L
         return L
@@ -75,7 +78,7 @@ def lib() -> ctypes.CDLL:
 
 EXPORTS = ("rast_workspace_size", "rasterize_meshes_fwd", "rasterize_meshes_bwd", "rast_bin_count",
            "rast_query_status", "rast_status_string", "silhouette_blend_fwd", "silhouette_blend_bwd",
-           "rast_set_kernel_events")
+           "rast_set_kernel_events", "softmax_blend_fwd", "softmax_blend_bwd")
 RAST_KERNEL_FINE = 0
 RAST_KERNEL_BWD = 1
 
@@ -123,6 +126,17 @@ def alloc_workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
+def _mesh_shapes(verts, faces, first_idx, num_faces):
+    """Shapes of the packed mesh inputs; returns N."""
+    if verts.dim() != 2 or verts.shape[1] != 3:
+        raise ValueError(f"verts must be (V,3), got {tuple(verts.shape)}")
+    if faces.dim() != 2 or faces.shape[1] != 3:
+        raise ValueError(f"faces must be (F,3), got {tuple(faces.shape)}")
+    if first_idx.dim() != 1 or tuple(num_faces.shape) != tuple(first_idx.shape):
+        raise ValueError("mesh_to_face_first_idx and num_faces_per_mesh must be (N,) each")
+    return first_idx.shape[0]
+
+
 def rasterize_meshes_fwd(verts, faces, first_idx, num_faces, H, W, blur_radius, K, bin_size, max_faces_per_bin,
                          sched, pix_to_face, zbuf, bary, dists, workspace):
     dev = verts.device
@@ -133,7 +147,10 @@ def rasterize_meshes_fwd(verts, faces, first_idx, num_faces, H, W, blur_radius, 
     for t, n, d in ((pix_to_face, "pix_to_face", torch.int32), (zbuf, "zbuf", torch.float32),
                     (bary, "bary", torch.float32), (dists, "dists", torch.float32), (workspace, "workspace", torch.uint8)):
         _require(t, n, d, dev)
-    N = first_idx.shape[0]
+    N = _mesh_shapes(verts, faces, first_idx, num_faces)
+    shp = (N, int(H), int(W), int(K))
+    _same_shape("N,H,W,K", shp, (pix_to_face, "pix_to_face"), (zbuf, "zbuf"), (dists, "dists"))
+    _same_shape("N,H,W,K", shp + (3,), (bary, "bary"))
     rc = lib().rasterize_meshes_fwd(_p(verts), verts.shape[0], _p(faces), faces.shape[0], _p(first_idx),
                                     _p(num_faces), int(N), int(H), int(W), float(blur_radius), int(K), int(bin_size),
                                     int(max_faces_per_bin or 0), int(sched), _p(pix_to_face), _p(zbuf), _p(bary),
@@ -153,7 +170,11 @@ def rasterize_meshes_bwd(verts, faces, first_idx, num_faces, H, W, blur_radius, 
                  (grad_verts, "grad_verts")):
         _require(t, n, torch.float32, dev)
     _require(workspace, "workspace", torch.uint8, dev)
-    N = first_idx.shape[0]
+    N = _mesh_shapes(verts, faces, first_idx, num_faces)
+    shp = (N, int(H), int(W), int(K))
+    _same_shape("N,H,W,K", shp, (pix_to_face, "pix_to_face"), (grad_zbuf, "grad_zbuf"), (grad_dists, "grad_dists"))
+    _same_shape("N,H,W,K", shp + (3,), (grad_bary, "grad_bary"))
+    _same_shape("verts", verts.shape, (grad_verts, "grad_verts"))
     rc = lib().rasterize_meshes_bwd(_p(verts), verts.shape[0], _p(faces), faces.shape[0], _p(first_idx),
                                     _p(num_faces), int(N), int(H), int(W), float(blur_radius), int(K),
                                     int(bin_size), int(max_faces_per_bin or 0), int(flags), _p(pix_to_face),
@@ -169,6 +190,7 @@ def rast_bin_count(verts, faces, first_idx, num_faces, H, W, blur_radius, bin_si
     _require(first_idx, "mesh_to_face_first_idx", torch.int64, dev)
     _require(num_faces, "num_faces_per_mesh", torch.int64, dev)
     _require(workspace, "workspace", torch.uint8, dev)
+    _mesh_shapes(verts, faces, first_idx, num_faces)
     rc = lib().rast_bin_count(_p(verts), verts.shape[0], _p(faces), faces.shape[0], _p(first_idx), _p(num_faces),
                               int(first_idx.shape[0]), int(H), int(W), float(blur_radius), int(bin_size),
                               _p(workspace), workspace.numel(), _stream(dev))
@@ -184,11 +206,20 @@ def rast_query_status(workspace):
     return int(st.value), int(mx.value)
 
 
+def _same_shape(ref, shape, *named):
+    """Raise unless every given tensor has exactly `shape` (checked before any launch)."""
+    for t, n in named:
+        if t is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{n} has shape {tuple(t.shape)}, expected {tuple(shape)} (from {ref})")
+
+
 def silhouette_blend_fwd(pix_to_face, dists, sigma, alpha):
     dev = dists.device
     _require(pix_to_face, "pix_to_face", torch.int32, dev)
     _require(dists, "dists", torch.float32, dev)
     _require(alpha, "alpha", torch.float32, dev)
+    _same_shape("dists", dists.shape, (pix_to_face, "pix_to_face"))
+    _same_shape("dists", dists.shape[:-1], (alpha, "alpha"))
     K = dists.shape[-1]
     P = dists.numel() // K
     _check("silhouette_blend_fwd",
@@ -201,6 +232,8 @@ def silhouette_blend_bwd(pix_to_face, dists, grad_alpha, sigma, grad_dists):
     _require(dists, "dists", torch.float32, dev)
     _require(grad_alpha, "grad_alpha", torch.float32, dev)
     _require(grad_dists, "grad_dists", torch.float32, dev)
+    _same_shape("dists", dists.shape, (pix_to_face, "pix_to_face"), (grad_dists, "grad_dists"))
+    _same_shape("dists", dists.shape[:-1], (grad_alpha, "grad_alpha"))
     K = dists.shape[-1]
     P = dists.numel() // K
     _check("silhouette_blend_bwd",
@@ -213,3 +246,39 @@ def rast_set_kernel_events(kernel: int, begin, end):
     b = None if begin is None else ctypes.c_void_p(begin)
     e = None if end is None else ctypes.c_void_p(end)
     _check("rast_set_kernel_events", lib().rast_set_kernel_events(int(kernel), b, e))
+
+
+def softmax_blend_fwd(pix_to_face, zbuf, dists, colors, sigma, gamma, znear, zfar, image):
+    dev = dists.device
+    _require(pix_to_face, "pix_to_face", torch.int32, dev)
+    for t, n in ((zbuf, "zbuf"), (dists, "dists"), (colors, "colors"), (image, "image")):
+        _require(t, n, torch.float32, dev)
+    C = colors.shape[-1]
+    _same_shape("dists", dists.shape, (pix_to_face, "pix_to_face"), (zbuf, "zbuf"))
+    _same_shape("dists", tuple(dists.shape) + (C,), (colors, "colors"))
+    _same_shape("dists", tuple(dists.shape[:-1]) + (C,), (image, "image"))
+    K = dists.shape[-1]
+    P = dists.numel() // K
+    _check("softmax_blend_fwd",
+           lib().softmax_blend_fwd(_p(pix_to_face), _p(zbuf), _p(dists), _p(colors), P, K, C, float(sigma),
+                                   float(gamma), float(znear), float(zfar), _p(image), _stream(dev)))
+
+
+def softmax_blend_bwd(pix_to_face, zbuf, dists, colors, sigma, gamma, znear, zfar, grad_image, grad_zbuf, grad_dists,
+                      grad_colors):
+    dev = dists.device
+    _require(pix_to_face, "pix_to_face", torch.int32, dev)
+    for t, n in ((zbuf, "zbuf"), (dists, "dists"), (colors, "colors"), (grad_image, "grad_image"),
+                 (grad_zbuf, "grad_zbuf"), (grad_dists, "grad_dists"), (grad_colors, "grad_colors")):
+        _require(t, n, torch.float32, dev)
+    C = colors.shape[-1]
+    _same_shape("dists", dists.shape, (pix_to_face, "pix_to_face"), (zbuf, "zbuf"), (grad_zbuf, "grad_zbuf"),
+                (grad_dists, "grad_dists"))
+    _same_shape("dists", tuple(dists.shape) + (C,), (colors, "colors"), (grad_colors, "grad_colors"))
+    _same_shape("dists", tuple(dists.shape[:-1]) + (C,), (grad_image, "grad_image"))
+    K = dists.shape[-1]
+    P = dists.numel() // K
+    _check("softmax_blend_bwd",
+           lib().softmax_blend_bwd(_p(pix_to_face), _p(zbuf), _p(dists), _p(colors), P, K, C, float(sigma),
+                                   float(gamma), float(znear), float(zfar), _p(grad_image), _p(grad_zbuf),
+                                   _p(grad_dists), _p(grad_colors), _stream(dev)))

@@ -285,4 +285,33 @@ int silhouette_blend_bwd(const int32_t* pix_to_face, const float* dists, const f
                                          (hipStream_t)stream));
 }
 
+static bool bad_softmax(int64_t P, int K, int C, float sigma, float gamma, float znear, float zfar) {
+    if (P < 0 || K < 1 || K > RAST_KMAX || C < 1 || C > RAST_SOFTMAX_CMAX) return true;
+    if (!(sigma > 0.0f) || !isfinite(sigma) || !(gamma > 0.0f) || !isfinite(gamma)) return true;
+    if (!isfinite(znear) || !isfinite(zfar) || !(zfar > znear) || !isfinite(1.0f / (zfar - znear))) return true;
+    return false;
+}
+
+int softmax_blend_fwd(const int32_t* pix_to_face, const float* zbuf, const float* dists, const float* colors,
+                      int64_t P, int K, int C, float sigma, float gamma, float znear, float zfar, float* image,
+                      void* stream) {
+    if (bad_softmax(P, K, C, sigma, gamma, znear, zfar)) return RAST_EINVAL;
+    if (P > 0 && (pix_to_face == nullptr || zbuf == nullptr || dists == nullptr || colors == nullptr ||
+                  image == nullptr))
+        return RAST_EINVAL;
+    return hip_rc(rast::launch_softmax_fwd(pix_to_face, zbuf, dists, colors, P, K, C, sigma, gamma, znear, zfar, image,
+                                           (hipStream_t)stream));
+}
+
+int softmax_blend_bwd(const int32_t* pix_to_face, const float* zbuf, const float* dists, const float* colors,
+                      int64_t P, int K, int C, float sigma, float gamma, float znear, float zfar,
+                      const float* grad_image, float* grad_zbuf, float* grad_dists, float* grad_colors, void* stream) {
+    if (bad_softmax(P, K, C, sigma, gamma, znear, zfar)) return RAST_EINVAL;
+    if (P > 0 && (pix_to_face == nullptr || zbuf == nullptr || dists == nullptr || colors == nullptr ||
+                  grad_image == nullptr))
+        return RAST_EINVAL;
+    return hip_rc(rast::launch_softmax_bwd(pix_to_face, zbuf, dists, colors, P, K, C, sigma, gamma, znear, zfar,
+                                           grad_image, grad_zbuf, grad_dists, grad_colors, (hipStream_t)stream));
+}
+
 }  // extern "C"

@@ -33,5 +33,10 @@ hipError_t launch_blend_fwd(const int32_t* p2f, const float* d, int64_t P, int K
                             hipStream_t s);
 hipError_t launch_blend_bwd(const int32_t* p2f, const float* d, const float* ga, int64_t P, int K, float sigma,
                             float* gd, hipStream_t s);
+hipError_t launch_softmax_fwd(const int32_t* p2f, const float* z, const float* d, const float* col, int64_t P, int K,
+                              int C, float sigma, float gamma, float znear, float zfar, float* img, hipStream_t s);
+hipError_t launch_softmax_bwd(const int32_t* p2f, const float* z, const float* d, const float* col, int64_t P, int K,
+                              int C, float sigma, float gamma, float znear, float zfar, const float* gimg, float* gz,
+                              float* gd, float* gc, hipStream_t s);
 
 }  // namespace rast

@@ -199,3 +199,35 @@ def silhouette_blend(pix_to_face, dists, sigma: float):
     """Algorithm 1 of the paper: alpha = 1 - prod_k (1 - sigmoid(-dists_k / sigma)),
     with empty slots (pix_to_face == -1) left out.  Differentiable in dists."""
     return _SilhouetteBlend.apply(pix_to_face.contiguous(), dists, float(sigma))
+
+
+class _SoftmaxBlend(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, pix_to_face, zbuf, dists, colors, sigma, gamma, znear, zfar):
+        z = zbuf.detach().contiguous()
+        d = dists.detach().contiguous()
+        c = colors.detach().contiguous().to(torch.float32)
+        img = torch.empty(d.shape[:-1] + (c.shape[-1],), dtype=torch.float32, device=d.device)
+        _lib.softmax_blend_fwd(pix_to_face, z, d, c, sigma, gamma, znear, zfar, img)
+        ctx.save_for_backward(pix_to_face, z, d, c)
+        ctx.params = (sigma, gamma, znear, zfar)
+        return img
+
+    @staticmethod
+    def backward(ctx, grad_image):
+        p2f, z, d, c = ctx.saved_tensors
+        need_z, need_d, need_c = ctx.needs_input_grad[1:4]
+        gz = torch.empty_like(z) if need_z else None
+        gd = torch.empty_like(d) if need_d else None
+        gc = torch.empty_like(c) if need_c else None
+        _lib.softmax_blend_bwd(p2f, z, d, c, *ctx.params, grad_image.contiguous().to(torch.float32), gz, gd, gc)
+        return None, gz, gd, gc, None, None, None, None
+
+
+def softmax_blend(pix_to_face, zbuf, dists, colors, sigma: float, gamma: float, znear: float, zfar: float):
+    """Algorithm 2 of the paper: image = sum_k w_k colors_k / sum_k w_k with
+    w_k = sigmoid(-dists_k / sigma) exp((zinv_k - max zinv) / gamma),
+    zinv = (zfar - zbuf) / (zfar - znear); empty slots are left out.
+    colors (..., K, C) with C <= 8.  Differentiable in zbuf, dists and colors."""
+    return _SoftmaxBlend.apply(pix_to_face.contiguous(), zbuf, dists, colors, float(sigma), float(gamma), float(znear),
+                               float(zfar))

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     for code in (_lib.RAST_OK, _lib.RAST_EINVAL, _lib.RAST_EWORKSPACE, _lib.RAST_EHIP, _lib.RAST_EOVERFLOW,
-                 _lib.RAST_EMESH):
+                 _lib.RAST_EMESH, _lib.RAST_EREUSE):
         s = _lib.status_string(code)
         assert s and s != "unknown status"
     assert _lib.status_string(12345) == "unknown status"
@@ -135,3 +135,24 @@ def test_product_path_never_imports_the_oracle():
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in text and "from oracle" not in text, fn
                 assert "oracle_rast" not in text and "liboracle" not in text, fn
+
+
+def test_softmax_blend_rejects_bad_arguments():
+    L = _lib.lib()
+    # p2f, zbuf, dists, colors, P, K, C, sigma, gamma, znear, zfar, image, stream
+    good = [FAKE, FAKE, FAKE, FAKE, 0, 4, 3, 1e-4, 1e-4, 1.0, 100.0, FAKE, None]
+    assert L.softmax_blend_fwd(*good) == _lib.RAST_OK  # P = 0: nothing to launch
+    for i, v in ((5, 0), (5, 65), (6, 0), (6, 9), (7, 0.0), (7, float("nan")), (8, -1.0), (9, 100.0), (10, 1.0),
+                 (10, float("inf")), (4, -1)):
+        bad = list(good)
+        bad[i] = v
+        assert L.softmax_blend_fwd(*bad) == _lib.RAST_EINVAL, i
+    bad = list(good)
+    bad[4], bad[0] = 10, None
+    assert L.softmax_blend_fwd(*bad) == _lib.RAST_EINVAL
+    # bwd: ..., grad_image, grad_zbuf, grad_dists, grad_colors, stream; the gradients may be NULL
+    gb = good[:11] + [FAKE, None, None, None, None]
+    assert L.softmax_blend_bwd(*gb) == _lib.RAST_OK
+    bad = list(gb)
+    bad[4], bad[11] = 10, None
+    assert L.softmax_blend_bwd(*bad) == _lib.RAST_EINVAL

@@ -403,3 +403,29 @@ def test_backward_reuse_matches_rebuild_and_checks_signature():
                 check=False)
         st, _ = _lib.rast_query_status(ws)
         assert st == _lib.RAST_EREUSE
+
+
+# ----------------------------------------------------------------- softmax blend (Algorithm 2)
+
+@pytest.mark.parametrize("C", [3, 6])
+def test_softmax_blend_vs_oracle(C):
+    from paper_2007_08501_amd.raster import softmax_blend
+    # the oracle's fragments of a reduced textured-render batch, random per-slot colours
+    b = meshgen.make_config(3, n_override=4, level_override=3, image_override=48)
+    o = oracle_full(b)
+    p2f, z, d = o["p2f"], o["zbuf"].astype(np.float32), o["dists"].astype(np.float32)
+    rng = np.random.default_rng(C)
+    col = rng.uniform(0, 1, p2f.shape + (C,)).astype(np.float32)
+    gimg = rng.standard_normal(p2f.shape[:-1] + (C,)).astype(np.float32)
+    prm = dict(sigma=1e-4, gamma=1e-4, znear=1.0, zfar=100.0)
+    ref = oracle.softmax_blend(p2f, z.astype(np.float64), d.astype(np.float64), col.astype(np.float64), **prm)
+    rgz, rgd, rgc = oracle.softmax_blend_backward(p2f, z.astype(np.float64), d.astype(np.float64),
+                                                  col.astype(np.float64), **prm, grad_image=gimg)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    zt, dt, ct = t(z).requires_grad_(True), t(d).requires_grad_(True), t(col).requires_grad_(True)
+    img = softmax_blend(t(p2f.astype(np.int32)), zt, dt, ct, **prm)
+    assert np.abs(img.detach().cpu().numpy() - ref).max() < 1e-5
+    (img * t(gimg)).sum().backward()
+    compare_grad(zt.grad.cpu().numpy(), rgz, "softmax zbuf")
+    compare_grad(dt.grad.cpu().numpy(), rgd, "softmax dists")
+    compare_grad(ct.grad.cpu().numpy(), rgc, "softmax colors")
