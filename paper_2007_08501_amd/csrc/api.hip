@@ -288,7 +288,8 @@ int silhouette_blend_bwd(const int32_t* pix_to_face, const float* dists, const f
 static bool bad_softmax(int64_t P, int K, int C, float sigma, float gamma, float znear, float zfar) {
     if (P < 0 || K < 1 || K > RAST_KMAX || C < 1 || C > RAST_SOFTMAX_CMAX) return true;
     if (!(sigma > 0.0f) || !isfinite(sigma) || !(gamma > 0.0f) || !isfinite(gamma)) return true;
-    if (!isfinite(znear) || !isfinite(zfar) || !(zfar > znear) || !isfinite(1.0f / (zfar - znear))) return true;
+    if (!isfinite(znear) || !isfinite(zfar) || !(zfar > znear)) return true;
+    if (!isfinite((float)(1.0 / (((double)zfar - (double)znear) * (double)gamma)))) return true;
     return false;
 }
 

@@ -66,6 +66,9 @@ __global__ __launch_bounds__(256) void blend_bwd_kernel(const int32_t* __restric
 // w_k = prob_k exp((zinv_k - max_j zinv_j) / gamma), image = sum_k w_k c_k / sum_k w_k.
 // Empty slots take no part; a pixel whose weights sum to 0 is 0.  CB is a
 // compile-time bound on the channel count C.
+// The exponent is evaluated as (min_j z_j - z_k) / ((zfar - znear) gamma),
+// which equals (zinv_k - max zinv) / gamma: forming zinv first would round
+// zfar - z (about zfar) and then divide that rounding by a small gamma.
 struct SoftmaxArgs {
     const int32_t* p2f;
     const float* z;
@@ -73,21 +76,22 @@ struct SoftmaxArgs {
     const float* col;
     int64_t P;
     int K, C;
-    float inv_sigma, inv_gamma, zfar, inv_range;
+    float inv_sigma;
+    float zscale;  // 1 / ((zfar - znear) gamma)
 };
 
-// Max zinv over the pixel's filled slots (0 when there are none).
-__device__ __forceinline__ float softmax_zmax(const SoftmaxArgs& a, int64_t p) {
-    float m = -INFINITY;
+// Smallest depth over the pixel's filled slots (the largest zinv); 0 when there are none.
+__device__ __forceinline__ float softmax_zmin(const SoftmaxArgs& a, int64_t p) {
+    float m = INFINITY;
     for (int k = 0; k < a.K; ++k) {
         const int64_t o = p * a.K + k;
-        if (a.p2f[o] >= 0) m = fmaxf(m, (a.zfar - a.z[o]) * a.inv_range);
+        if (a.p2f[o] >= 0) m = fminf(m, a.z[o]);
     }
-    return m == -INFINITY ? 0.0f : m;
+    return m == INFINITY ? 0.0f : m;
 }
 
-__device__ __forceinline__ float softmax_weight(const SoftmaxArgs& a, int64_t o, float m) {
-    return sigmoidf(-a.d[o] * a.inv_sigma) * expf(((a.zfar - a.z[o]) * a.inv_range - m) * a.inv_gamma);
+__device__ __forceinline__ float softmax_weight(const SoftmaxArgs& a, int64_t o, float zmin) {
+    return sigmoidf(-a.d[o] * a.inv_sigma) * expf((zmin - a.z[o]) * a.zscale);
 }
 
 // Weight sum and the blended colour of pixel p.
@@ -116,7 +120,7 @@ __global__ __launch_bounds__(256) void softmax_fwd_kernel(SoftmaxArgs a, float* 
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.P) return;
     float out[CB];
-    softmax_pixel<CB>(a, p, softmax_zmax(a, p), out);
+    softmax_pixel<CB>(a, p, softmax_zmin(a, p), out);
 #pragma unroll
     for (int c = 0; c < CB; ++c)
         if (c < a.C) img[p * a.C + c] = out[c];
@@ -131,7 +135,7 @@ __global__ __launch_bounds__(256) void softmax_bwd_kernel(SoftmaxArgs a, const f
                                                           float* __restrict__ gc) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.P) return;
-    const float m = softmax_zmax(a, p);
+    const float m = softmax_zmin(a, p);
     float out[CB];
     const float W = softmax_pixel<CB>(a, p, m, out);
     const float inv = W > 0.0f ? 1.0f / W : 0.0f;
@@ -150,7 +154,7 @@ __global__ __launch_bounds__(256) void softmax_bwd_kernel(SoftmaxArgs a, const f
             G *= inv;
         }
         if (gd) gd[o] = -G * w * om * a.inv_sigma;
-        if (gz) gz[o] = -G * w * a.inv_gamma * a.inv_range;
+        if (gz) gz[o] = -G * w * a.zscale;
         if (gc) {
 #pragma unroll
             for (int c = 0; c < CB; ++c)
@@ -170,9 +174,7 @@ static SoftmaxArgs softmax_args(const int32_t* p2f, const float* z, const float*
     a.K = K;
     a.C = C;
     a.inv_sigma = 1.0f / sigma;
-    a.inv_gamma = 1.0f / gamma;
-    a.zfar = zfar;
-    a.inv_range = 1.0f / (zfar - znear);
+    a.zscale = (float)(1.0 / (((double)zfar - (double)znear) * (double)gamma));
     return a;
 }
 
