@@ -92,7 +92,8 @@ int rast_workspace_size(int N, int H, int W, int64_t F, int bin_size, int max_fa
  * K-nearest selection, Fragment outputs).
  *   verts_packed (V,3) f32, faces_packed (F,3) i32, mesh_to_face_first_idx (N) i64,
  *   num_faces_per_mesh (N) i64 -- inputs, see the conventions above.
- *   N, H, W > 0; blur_radius >= 0 (squared NDC); faces_per_pixel K in [1, RAST_KMAX];
+ *   N, H, W > 0 with H*W <= 2^30 and 24*W*K < 2^31; blur_radius >= 0 (squared NDC);
+ *   faces_per_pixel K in [1, RAST_KMAX];
  *   bin_size 0 or a multiple of RAST_TILE <= RAST_MAX_BIN; max_faces_per_bin > 0 if bin_size > 0;
  *   sched: RAST_SCHED_GRID or RAST_SCHED_PERSISTENT (ignored when bin_size == 0).
  *   Outputs, row-major, fully overwritten:

@@ -75,6 +75,8 @@ bool bad_dims(int N, int H, int W, int K) {
     // keep N*H*W*K*3 well inside int64 and every per-image pixel index in int32
     if ((int64_t)H * W > ((int64_t)1 << 30)) return true;
     if ((int64_t)N * H * W * K > ((int64_t)1 << 40)) return true;
+    // the fine pass addresses a tile's fragments with 32-bit offsets (8 rows of 3*K floats per pixel)
+    if ((int64_t)W * K * 3 * RAST_TILE > INT32_MAX) return true;
     return false;
 }
 

@@ -229,13 +229,22 @@ constexpr int kStageG2 = 8;   // slots per pass for barycentrics and distances
 // element e of a pass that stages `per` values per pixel: pixel e / per
 __device__ __forceinline__ int stage_pixel(int e, float inv_per) { return (int)(((float)e + 0.5f) * inv_per); }
 
-template <int KB>
+// EXACT: K equals the bucket size KB, so every group width, stride and index
+// below is a compile-time constant (the common case); otherwise K < KB is a
+// run-time value.  Addresses are 32-bit offsets from the tile's first
+// fragment, a wave-uniform base.
+template <int KB, bool EXACT>
 __device__ __forceinline__ void write_fragments(const FineArgs& a, TileLds& L, const TopK<KB>& top, const Pix& p,
                                                 int n, int tx, int ty) {
     const int lane = threadIdx.x & 63;
-    const int K = a.K;
+    const int K = EXACT ? KB : a.K;
     const int rows = min(kTile, a.H - ty * kTile), cols = min(kTile, a.W - tx * kTile);
     const int64_t pix0 = ((int64_t)n * a.H + ty * kTile) * a.W + tx * kTile;
+    const int rowK = a.W * K;  // fragments per image row
+    int32_t* const p2f_t = a.p2f + pix0 * K;
+    float* const zbuf_t = a.zbuf + pix0 * K;
+    float* const dist_t = a.dists + pix0 * K;
+    float* const bary_t = a.bary + pix0 * K * 3;
     static_assert(sizeof(TileLds) >= sizeof(float) * 64 * 2 * (kStageG1 + 1), "id/depth staging exceeds the tile LDS");
     static_assert(sizeof(TileLds) >= sizeof(float) * 64 * (4 * kStageG2 + 2), "bary/dist staging exceeds the tile LDS");
     float* stage = reinterpret_cast<float*>(&L);
@@ -258,14 +267,17 @@ __device__ __forceinline__ void write_fragments(const FineArgs& a, TileLds& L, c
             __syncthreads();
             const int gw = min(G, K - g0);
             const float inv = 1.0f / (float)gw;
-            for (int e = lane; e < 64 * gw; e += 64) {
-                const int px = stage_pixel(e, inv);
+#pragma unroll
+            for (int e0 = 0; e0 < 64 * G; e0 += 64) {
+                const int e = e0 + lane;
+                if (e >= 64 * gw) break;
+                const int px = EXACT ? e / gw : stage_pixel(e, inv);
                 const int k = e - px * gw;
                 const int r = px >> 3, c = px & 7;
                 if (r < rows && c < cols) {
-                    const int64_t o = (pix0 + (int64_t)r * a.W + c) * K + g0 + k;
-                    a.p2f[o] = sid[px * S + k];
-                    a.zbuf[o] = sz[px * S + k];
+                    const int o = r * rowK + c * K + g0 + k;
+                    p2f_t[o] = sid[px * S + k];
+                    zbuf_t[o] = sz[px * S + k];
                 }
             }
             __syncthreads();
@@ -279,7 +291,7 @@ __device__ __forceinline__ void write_fragments(const FineArgs& a, TileLds& L, c
         float* sd = stage + 64 * SB;
 #pragma unroll
         for (int g0 = 0; g0 < KB; g0 += G) {
-            if (g0 >= K) continue;  // K is uniform: the whole wave skips
+            if (g0 >= K) continue;
 #pragma unroll
             for (int k = 0; k < G; ++k) {
                 const uint64_t key = top.q[g0 + k];
@@ -301,17 +313,23 @@ __device__ __forceinline__ void write_fragments(const FineArgs& a, TileLds& L, c
             __syncthreads();
             const int gw = min(G, K - g0);
             const float inv3 = 1.0f / (float)(3 * gw), inv1 = 1.0f / (float)gw;
-            for (int e = lane; e < 64 * 3 * gw; e += 64) {
-                const int px = stage_pixel(e, inv3);
+#pragma unroll
+            for (int e0 = 0; e0 < 64 * 3 * G; e0 += 64) {
+                const int e = e0 + lane;
+                if (e >= 64 * 3 * gw) break;
+                const int px = EXACT ? e / (3 * gw) : stage_pixel(e, inv3);
                 const int m = e - px * 3 * gw;
                 const int r = px >> 3, c = px & 7;
-                if (r < rows && c < cols) a.bary[((pix0 + (int64_t)r * a.W + c) * K + g0) * 3 + m] = sb[px * SB + m];
+                if (r < rows && c < cols) bary_t[3 * (r * rowK + c * K + g0) + m] = sb[px * SB + m];
             }
-            for (int e = lane; e < 64 * gw; e += 64) {
-                const int px = stage_pixel(e, inv1);
+#pragma unroll
+            for (int e0 = 0; e0 < 64 * G; e0 += 64) {
+                const int e = e0 + lane;
+                if (e >= 64 * gw) break;
+                const int px = EXACT ? e / gw : stage_pixel(e, inv1);
                 const int k = e - px * gw;
                 const int r = px >> 3, c = px & 7;
-                if (r < rows && c < cols) a.dists[(pix0 + (int64_t)r * a.W + c) * K + g0 + k] = sd[px * SD + k];
+                if (r < rows && c < cols) dist_t[r * rowK + c * K + g0 + k] = sd[px * SD + k];
             }
             __syncthreads();
         }
@@ -412,7 +430,10 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
         }
         __syncthreads();
     }
-    write_fragments<KB>(a, L, top, p, n, tx, ty);
+    if (a.K == KB)
+        write_fragments<KB, true>(a, L, top, p, n, tx, ty);
+    else
+        write_fragments<KB, false>(a, L, top, p, n, tx, ty);
 }
 
 template <int KB, bool BINNED>

@@ -78,7 +78,7 @@ def fwd(**kw):
 @pytest.mark.parametrize("kw", [
     dict(N=0), dict(H=0), dict(W=-3), dict(K=0), dict(K=65), dict(blur=-1.0), dict(blur=float("nan")),
     dict(blur=float("inf")), dict(bs=4), dict(bs=8, M=0), dict(bs=520, M=4), dict(sched=2), dict(V=-1),
-    dict(F=-1), dict(F=1 << 31), dict(verts=None), dict(faces=None), dict(first=None), dict(nf=None),
+    dict(F=-1), dict(F=1 << 31), dict(H=1, W=1 << 22, K=64), dict(verts=None), dict(faces=None), dict(first=None), dict(nf=None),
     dict(p2f=None), dict(zbuf=None), dict(bary=None), dict(dists=None),
 ])
 def test_forward_rejects_bad_arguments(kw):
