@@ -34,6 +34,8 @@ if ROOT not in sys.path:
 METRIC = "fwd+bwd rasterized Mpixel·K/s and ms/batch, batched vs per-mesh, at oracle tol"
 UNIT = "Mpixel·K/s"
 HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: one non-packed FP32/FP64 VALU lane-op each
+VALU_PEAK_LANE_OPS = 3.932e13
 
 
 def log(*a):
@@ -104,6 +106,27 @@ def measured_traffic(kernel, config, K, bs):
         return None
     try:
         return int(float(vals["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
+def measured_valu(kernel, config, K, bs):
+    """VALU wave instructions per launch of `kernel` from the committed
+    kernel-trace summary (SQ_INSTS_VALU), or None when there is none for this
+    workload or the kernel changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"kernels_cfg{config}_K{K}_bs{bs}.txt")
+    if kernel != "fine" or not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith((" ", "#")):
+                k, _, v = line.partition(":")
+                vals[k.strip()] = v.strip().split()[0] if v.strip() else ""
+    if vals.get("sources_sha256") != sources_digest(kernel):
+        return None
+    try:
+        return float(vals["valu_wave_instructions_per_launch"])
     except (KeyError, ValueError):
         return None
 
@@ -295,6 +318,13 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(dom, args.config, K, bs), "kernel_ms": round(dom_ms, 5),
                 "algorithmic_bytes": dom_bytes}
+    # the same kernel against the VALU issue rate: its counted VALU instructions
+    # (64 lanes each) over the live kernel time
+    valu = measured_valu(dom, args.config, K, bs)
+    if valu is not None:
+        lane_ops = valu * 64 / (dom_ms * 1e-3)
+        roofline["valu"] = {"lane_ops_per_s": float(f"{lane_ops:.4g}"), "peak": VALU_PEAK_LANE_OPS,
+                            "frac": round(lane_ops / VALU_PEAK_LANE_OPS, 4), "wave_instructions": int(valu)}
 
     # ---------------------------------------------------------------- per-mesh plain form
     per_mesh = None

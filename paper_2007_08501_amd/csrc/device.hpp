@@ -123,6 +123,11 @@ __device__ __forceinline__ FaceRec make_rec(float ax, float ay, float az, float 
     return R;
 }
 
+// The evaluation below takes any record with FaceRec's geometry fields (pa,
+// ab, ac, E, az, dz1, dz2, invE, il0, il1, il2): the same source expressions,
+// built without contraction, give bit-identical results for every record
+// type.
+//
 // Everything the forward writes for one (pixel, face) pair, and what the
 // backward needs besides.
 struct Eval {
@@ -141,7 +146,8 @@ struct Eval {
 // (the same three sub-triangle areas as cross(b-p, c-p), cross(c-p, a-p) and
 // cross(a-p, b-p)), each FP64; w_i = e_i / E.  The pixel is inside when all
 // three w_i are positive (each w_i has the sign of e_i / E).
-__device__ __forceinline__ void eval_bary(const FaceRec& R, const Pix& p, Eval& o) {
+template <class Rec>
+__device__ __forceinline__ void eval_bary(const Rec& R, const Pix& p, Eval& o) {
     const double dx = p.x - R.pa.x, dy = p.y - R.pa.y;
     const double e1 = fma(dx, R.ac.y, -(dy * R.ac.x));
     const double e2 = fma(R.ab.x, dy, -(R.ab.y * dx));
@@ -170,7 +176,8 @@ struct EdgeD {
     float d[3];  // squared distance per edge
     float t[3];  // unclamped parameter per edge
 };
-__device__ __forceinline__ void eval_edges(const FaceRec& R, const Eval& b, EdgeD& o) {
+template <class Rec>
+__device__ __forceinline__ void eval_edges(const Rec& R, const Eval& b, EdgeD& o) {
     const float abx = (float)R.ab.x, aby = (float)R.ab.y, acx = (float)R.ac.x, acy = (float)R.ac.y;
     const float pax = b.sx, pay = b.sy;              // p - a
     const float pbx = pax - abx, pby = pay - aby;    // p - b
@@ -187,7 +194,8 @@ __device__ __forceinline__ void eval_edges(const FaceRec& R, const Eval& b, Edge
 }
 
 // Nearest edge (lowest index on ties), its squared distance and clamped parameter.
-__device__ __forceinline__ void eval_dist(const FaceRec& R, Eval& o) {
+template <class Rec>
+__device__ __forceinline__ void eval_dist(const Rec& R, Eval& o) {
     EdgeD ed;
     eval_edges(R, o, ed);
     float d = ed.d[0], t = ed.t[0];
@@ -199,7 +207,8 @@ __device__ __forceinline__ void eval_dist(const FaceRec& R, Eval& o) {
     o.u = fminf(fmaxf(t, 0.0f), 1.0f);
 }
 
-__device__ __forceinline__ void eval_full(const FaceRec& R, const Pix& p, Eval& o) {
+template <class Rec>
+__device__ __forceinline__ void eval_full(const Rec& R, const Pix& p, Eval& o) {
     eval_bary(R, p, o);
     eval_dist(R, o);
 }
@@ -210,7 +219,8 @@ __device__ __forceinline__ bool in_bbox(const FaceRec& R, const Pix& p) {
 
 // Does face R count for pixel p, given that p lies in R's grown box?  On
 // success z is its depth.
-__device__ __forceinline__ bool face_counts_in_box(const FaceRec& R, const Pix& p, float blur, float& z) {
+template <class Rec>
+__device__ __forceinline__ bool face_counts_in_box(const Rec& R, const Pix& p, float blur, float& z) {
     Eval b;
     eval_bary(R, p, b);
     z = b.z;

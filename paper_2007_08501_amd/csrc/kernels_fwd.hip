@@ -200,13 +200,47 @@ struct FineArgs {
 
 // LDS of one tile's wave: a chunk of up to 64 candidate faces that overlap the
 // tile, and per lane the indices (within the chunk) of the faces whose boxes
-// contain the lane's pixel.
+// contain the lane's pixel.  The gather gives every lane one list entry, so a
+// chunk is exactly one wave wide.  The per-lane lists are bytes: a smaller LDS
+// block lets more tile waves share a CU, and the fine pass is latency-bound
+// enough for that to pay (measured).
 constexpr int kChunk = 64;
-struct TileLds {
-    FaceRec rec[kChunk];
-    int id[kChunk];
-    unsigned short lst[kChunk * 64];  // entry i of lane l at [i * 64 + l]: conflict-free
+static_assert(kChunk == 64, "the chunk gather takes one list entry per lane of a wave64");
+
+// A face as the tile pass keeps it in LDS: the geometry the pixel tests read
+// (the fields of FaceRec that the evaluation uses), the face id, and the
+// tile's pixels that the face's grown box may cover, as a 64-bit mask
+// (bit r*8 + c), which replaces the box.
+struct TileRec {
+    double2 pa, ab, ac;
+    double E;
+    float az, dz1, dz2, invE, il0, il1, il2;
+    int fid;
+    uint64_t mask;
 };
+static_assert(sizeof(TileRec) == 6 * sizeof(float4), "tile record layout");
+
+struct TileLds {
+    TileRec rec[kChunk];
+    unsigned char lst[kChunk * 64];  // entry i of lane l at [i * 64 + l]
+};
+
+// Pixels of the 8x8 tile (x0, y0) whose centres the box [bb.x, bb.y] x
+// [bb.z, bb.w] may contain, from the same conservative pixel ranges as the
+// binning (an empty box gives 0).
+__device__ __forceinline__ uint64_t tile_mask(const float4 bb, int H, int W, int x0, int y0) {
+    int c0, c1, r0, r1;
+    pix_range(bb.x, bb.y, W, c0, c1);
+    pix_range(bb.z, bb.w, H, r0, r1);
+    c0 = max(c0 - x0, 0);
+    c1 = min(c1 - x0, kTile - 1);
+    r0 = max(r0 - y0, 0);
+    r1 = min(r1 - y0, kTile - 1);
+    if (c1 < c0 || r1 < r0) return 0ull;
+    const uint64_t cols = (uint64_t)((0xffu >> (kTile - 1 - (c1 - c0))) << c0) * 0x0101010101010101ull;
+    const uint64_t rows = (~0ull >> (8 * (kTile - 1 - r1))) & (~0ull << (8 * r0));
+    return cols & rows;
+}
 
 // Largest value of v over the wave.
 __device__ __forceinline__ int wave_max(int v) {
@@ -345,7 +379,7 @@ __device__ __forceinline__ void write_fragments(const FineArgs& a, TileLds& L, c
 //     faces that count into its register top-K.
 // Step 3 is where the arithmetic is; compacting the (pixel, face) pairs first
 // keeps lanes from idling on faces that miss their pixel.
-template <int KB, bool BINNED>
+template <int KB, bool BINNED, bool EXACT>
 __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n, int tx, int ty) {
     const int lane = threadIdx.x & 63;
     const int r = ty * kTile + (lane >> 3);
@@ -353,10 +387,6 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
     const bool live = (r < a.H) && (c < a.W);
     const Pix p = make_pix(r, c, a.H, a.W);
     // extent of the tile's pixel centres (x decreases with c, y with r)
-    const int c_last = min(tx * kTile + kTile - 1, a.W - 1);
-    const int r_last = min(ty * kTile + kTile - 1, a.H - 1);
-    const float tx_hi = pix_x(tx * kTile, a.W), tx_lo = pix_x(c_last, a.W);
-    const float ty_hi = pix_y(ty * kTile, a.H), ty_lo = pix_y(r_last, a.H);
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     TopK<KB> top;
@@ -376,19 +406,20 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
         base = lo;
         cnt = hi > lo ? hi - lo : 0;
     }
-    unsigned short* mylst = L.lst + lane;
+    unsigned char* mylst = L.lst + lane;
     for (int64_t c0 = 0; c0 < cnt; c0 += kChunk) {
         // 1. gather and compact the chunk's faces that overlap the tile
         const int64_t e = c0 + lane;
         const bool in_list = e < cnt;
         const int fid = in_list ? (BINNED ? list[e] : (int)(base + e)) : 0;
-        // the record as seven 16-byte words, the last one the grown box
+        // the record as seven 16-byte words (pa | ab | ac | E, a.z, mesh |
+        // dz1, dz2, 1/E, il0 | il1, il2, pad | grown box)
         static_assert(sizeof(FaceRec) == 7 * sizeof(float4), "face record layout");
         const float4* rsrc = reinterpret_cast<const float4*>(a.recs + (in_list ? fid : (BINNED ? list[0] : (int)base)));
         const float4 rv0 = rsrc[0], rv1 = rsrc[1], rv2 = rsrc[2], rv3 = rsrc[3], rv4 = rsrc[4], rv5 = rsrc[5];
         const float4 rv6 = rsrc[6];
-        const float4 bb = rv6;
-        const bool keep = in_list && !(bb.y < tx_lo || bb.x > tx_hi || bb.w < ty_lo || bb.z > ty_hi);
+        const uint64_t pm = in_list ? tile_mask(rv6, a.H, a.W, tx * kTile, ty * kTile) : 0ull;
+        const bool keep = pm != 0ull;
         const uint64_t kept = __ballot(keep);
         const int m = __popcll(kept);
         if (keep) {
@@ -397,19 +428,16 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
             rdst[0] = rv0;
             rdst[1] = rv1;
             rdst[2] = rv2;
-            rdst[3] = rv3;
-            rdst[4] = rv4;
-            rdst[5] = rv5;
-            rdst[6] = rv6;
-            L.id[dst] = fid;
+            rdst[3] = make_float4(rv3.x, rv3.y, rv3.z, rv4.x);  // E | a.z, dz1
+            rdst[4] = make_float4(rv4.y, rv4.z, rv4.w, rv5.x);  // dz2, 1/E, il0, il1
+            rdst[5] = make_float4(rv5.y, __int_as_float(fid), __uint_as_float((uint32_t)pm),
+                                  __uint_as_float((uint32_t)(pm >> 32)));  // il2, id, mask
         }
         __syncthreads();
-        // 2. per-lane lists of the faces whose boxes contain the lane's pixel
+        // 2. per-lane lists of the faces whose boxes may contain the lane's pixel
         int nl = 0;
-        for (int j = 0; j < m; ++j) {
-            const float4 bb = L.rec[j].bb;
-            if (live && p.xf >= bb.x && p.xf <= bb.y && p.yf >= bb.z && p.yf <= bb.w) mylst[64 * nl++] = (unsigned short)j;
-        }
+        for (int j = 0; j < m; ++j)
+            if ((L.rec[j].mask >> lane) & 1ull) mylst[64 * nl++] = (unsigned char)j;
         // 3. full test of the lane's own candidates, eight per round; the
         //    round count is the wave's longest list, so the loop is uniform
         //    and the queue stays in place across rounds
@@ -422,7 +450,7 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
                 if (i0 + u < nl) {
                     const int j = mylst[64 * (i0 + u)];
                     float z;
-                    if (face_counts_in_box(L.rec[j], p, a.blur, z)) key = make_key(z, L.id[j]);
+                    if (face_counts_in_box(L.rec[j], p, a.blur, z)) key = make_key(z, L.rec[j].fid);
                 }
                 b[u] = key;
             }
@@ -430,23 +458,29 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
         }
         __syncthreads();
     }
-    if (a.K == KB)
-        write_fragments<KB, true>(a, L, top, p, n, tx, ty);
-    else
-        write_fragments<KB, false>(a, L, top, p, n, tx, ty);
+    write_fragments<KB, EXACT>(a, L, top, p, n, tx, ty);
 }
 
-template <int KB, bool BINNED>
+// EXACT: faces_per_pixel equals the queue size KB (chosen at launch).
+template <int KB, bool BINNED, bool EXACT>
 __global__ __launch_bounds__(64) void raster_tiles_kernel(FineArgs a) {
     __shared__ TileLds L;
-    raster_tile<KB, BINNED>(a, L, blockIdx.z, blockIdx.x, blockIdx.y);
+    raster_tile<KB, BINNED, EXACT>(a, L, blockIdx.z, blockIdx.x, blockIdx.y);
 }
 
 // Persistent form: a device-sized grid; each wave pulls the next tile id from
 // a counter in the workspace header.  order[] lists tile ids (image-major
 // linear ids) most-loaded bins first.  Every wave leaves when the counter
 // passes the number of tiles.
-template <int KB>
+// One tile of the persistent form, kept out of line: inlined into the work
+// loop, the tile's loop-invariant address arithmetic is hoisted out of it and
+// held live across tiles, far beyond the register file.
+template <int KB, bool EXACT>
+__device__ __noinline__ void raster_tile_persistent(const FineArgs& a, TileLds& L, int n, int tx, int ty) {
+    raster_tile<KB, true, EXACT>(a, L, n, tx, ty);
+}
+
+template <int KB, bool EXACT>
 __global__ __launch_bounds__(64) void raster_persistent_kernel(FineArgs a, const int* __restrict__ order,
                                                                int* __restrict__ hdr, int total) {
     __shared__ TileLds L;
@@ -461,7 +495,7 @@ __global__ __launch_bounds__(64) void raster_persistent_kernel(FineArgs a, const
         int rem = t - n * per_img;
         int ty = rem / a.tiles_x;
         int tx = rem - ty * a.tiles_x;
-        raster_tile<KB, true>(a, L, n, tx, ty);
+        raster_tile_persistent<KB, EXACT>(a, L, n, tx, ty);
     }
 }
 
@@ -514,7 +548,7 @@ __global__ void order_scan_kernel(int* __restrict__ hist, int* __restrict__ hdr,
     }
 }
 
-template <int KB>
+template <int KB, bool EXACT>
 static hipError_t launch_fine_k(const FineArgs& a, bool binned, int sched, int* order, int* hist, int* hdr,
                                 int n_workers, hipStream_t s, hipEvent_t eb, hipEvent_t ee) {
     if (binned && sched == 1) {
@@ -529,16 +563,16 @@ static hipError_t launch_fine_k(const FineArgs& a, bool binned, int sched, int* 
                            a.nby, a.nbx, a.M, hist, order);
         int workers = n_workers < total ? n_workers : total;
         if (eb) (void)hipEventRecord(eb, s);
-        hipLaunchKernelGGL(raster_persistent_kernel<KB>, dim3(workers), dim3(64), 0, s, a, order, hdr, total);
+        hipLaunchKernelGGL((raster_persistent_kernel<KB, EXACT>), dim3(workers), dim3(64), 0, s, a, order, hdr, total);
         if (ee) (void)hipEventRecord(ee, s);
         return hipGetLastError();
     }
     dim3 grid(a.tiles_x, a.tiles_y, a.N);
     if (eb) (void)hipEventRecord(eb, s);
     if (binned)
-        hipLaunchKernelGGL((raster_tiles_kernel<KB, true>), grid, dim3(64), 0, s, a);
+        hipLaunchKernelGGL((raster_tiles_kernel<KB, true, EXACT>), grid, dim3(64), 0, s, a);
     else
-        hipLaunchKernelGGL((raster_tiles_kernel<KB, false>), grid, dim3(64), 0, s, a);
+        hipLaunchKernelGGL((raster_tiles_kernel<KB, false, EXACT>), grid, dim3(64), 0, s, a);
     if (ee) (void)hipEventRecord(ee, s);
     return hipGetLastError();
 }
@@ -570,13 +604,21 @@ hipError_t launch_fine(const FaceRec* recs, const int64_t* first, const int64_t*
     a.bary = bary;
     a.dists = dists;
     bool binned = bs > 0;
-    if (K <= 1) return launch_fine_k<1>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
-    if (K <= 2) return launch_fine_k<2>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
-    if (K <= 4) return launch_fine_k<4>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
-    if (K <= 8) return launch_fine_k<8>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
-    if (K <= 16) return launch_fine_k<16>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
-    if (K <= 32) return launch_fine_k<32>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
-    return launch_fine_k<64>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
+    // queue sizes are powers of two; K equal to one gets the compile-time-K kernels
+#define RAST_FINE_BUCKET(KB)                                                                          \
+    if (K <= KB) {                                                                                    \
+        if (K == KB) return launch_fine_k<KB, true>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee); \
+        return launch_fine_k<KB, false>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);     \
+    }
+    if (K <= 1) return launch_fine_k<1, true>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
+    if (K <= 2) return launch_fine_k<2, true>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
+    RAST_FINE_BUCKET(4)
+    RAST_FINE_BUCKET(8)
+    RAST_FINE_BUCKET(16)
+    RAST_FINE_BUCKET(32)
+    RAST_FINE_BUCKET(64)
+#undef RAST_FINE_BUCKET
+    return hipErrorInvalidValue;
 }
 
 }  // namespace rast
