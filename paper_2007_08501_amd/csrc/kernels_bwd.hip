@@ -73,7 +73,8 @@ struct FaceGrad {
 };
 
 // Adds the contribution of slot s (pixel p) of face R to g.
-__device__ __forceinline__ void slot_grad(const BwdArgs& a, const FaceRec& R, const float (&vz)[3], const Pix& p,
+template <class Rec>
+__device__ __forceinline__ void slot_grad(const BwdArgs& a, const Rec& R, const float (&vz)[3], const Pix& p,
                                           int64_t s, FaceGrad& g) {
     Eval ev;
     eval_full(R, p, ev);
@@ -348,19 +349,47 @@ __device__ __forceinline__ void atomic_face(const BwdArgs& a, int f, const float
     }
 }
 
-// One 1024-thread workgroup per bin.  The bin's face list is taken in chunks
+// A face as the bin pass keeps it in LDS: the fields the slot recomputation
+// reads (FaceRec without the mesh id and the box), 88 bytes.
+struct Dbl2 {  // a pair of doubles at 8-byte alignment (double2 would pad the record to 96 bytes)
+    double x, y;
+};
+struct BinRec {
+    Dbl2 pa, ab, ac;
+    double E;
+    float az, dz1, dz2, invE, il0, il1, il2, pad_;
+};
+static_assert(sizeof(BinRec) == 88, "bin record layout");
+
+__device__ __forceinline__ void store_bin_rec(BinRec& d, const FaceRec& R) {
+    d.pa = {R.pa.x, R.pa.y};
+    d.ab = {R.ab.x, R.ab.y};
+    d.ac = {R.ac.x, R.ac.y};
+    d.E = R.E;
+    d.az = R.az;
+    d.dz1 = R.dz1;
+    d.dz2 = R.dz2;
+    d.invE = R.invE;
+    d.il0 = R.il0;
+    d.il1 = R.il1;
+    d.il2 = R.il2;
+    d.pad_ = 0.0f;
+}
+
+// One 256-thread workgroup per bin.  The bin's face list is taken in chunks
 // of kP1Chunk faces: the chunk's records go to LDS (one coalesced gather) with
 // a hash table from face id to chunk index, then every thread streams its
 // slots of the bin (kP1Unroll at a time, loads issued together), and the slots
 // whose face is in the chunk add their nine coordinate sums into the chunk's
-// LDS accumulators.  A bin of up to kP1Chunk faces -- most of them --
-// is one chunk and reads its slots once.
+// LDS accumulators, as exact 64-bit fixed point; the rare contribution too
+// large for that goes straight to grad_verts with a float atomic.  The LDS
+// block (about 30 KB) lets five workgroups share a CU.  A bin of up to
+// kP1Chunk faces -- most of them -- is one chunk and reads its slots once.
 constexpr double kFixScale = 4294967296.0;  // 2^32
 
 __global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a) {
-    __shared__ FaceRec srec[kP1Chunk];
+    __shared__ BinRec srec[kP1Chunk];
     __shared__ unsigned long long acci[kP1Chunk * 9];
-    __shared__ float acc[kP1Chunk * 9];
     __shared__ int tkey[kP1Table];
     __shared__ int tval[kP1Table];
     if (!bins_usable(a)) return;
@@ -377,14 +406,11 @@ __global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a) {
     for (int base = 0; base < cnt; base += kP1Chunk) {
         const int m = min(kP1Chunk, cnt - base);
         for (int i = threadIdx.x; i < kP1Table; i += kP1Threads) tkey[i] = -1;
-        for (int i = threadIdx.x; i < m * 9; i += kP1Threads) {
-            acc[i] = 0.0f;
-            acci[i] = 0ull;
-        }
+        for (int i = threadIdx.x; i < m * 9; i += kP1Threads) acci[i] = 0ull;
         __syncthreads();
         for (int j = threadIdx.x; j < m; j += kP1Threads) {
             const int f = list[base + j];
-            srec[j] = a.recs[f];
+            store_bin_rec(srec[j], a.recs[f]);
             uint32_t h = fhash(f);
             for (int probe = 0; probe < kP1Table; ++probe) {
                 if (atomicCAS(&tkey[h], -1, f) == -1) {
@@ -428,7 +454,7 @@ __global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a) {
                     h = (h + 1) & (kP1Table - 1);
                 }
                 if (j < 0) continue;
-                const FaceRec R = srec[j];
+                const BinRec R = srec[j];
                 const float vz[3] = {R.az, R.az + R.dz1, R.az + R.dz2};
                 FaceGrad g;
 #pragma unroll
@@ -442,7 +468,9 @@ __global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a) {
                     if (fabsf(v) < a.fix_limit) {
                         atomicAdd(&acci[9 * j + x], (unsigned long long)__double2ll_rn((double)v * kFixScale));
                     } else {
-                        atomicAdd(&acc[9 * j + x], v);
+                        // too large for the fixed-point sums (never for sane inputs): straight to the vertex
+                        const int vtx = a.faces[3 * (int64_t)list[base + j] + x / 3];
+                        if (vtx >= 0 && vtx < a.V) atomicAdd(a.grad + 3 * (int64_t)vtx + x % 3, v);
                     }
                 }
             }
@@ -454,12 +482,11 @@ __global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a) {
         for (int j = threadIdx.x; j < m; j += kP1Threads) {
             const int f = list[base + j];
             int bx0, bx1, by0, by1;
-            if (!face_bins(srec[j], a.H, a.W, a.bs, bx0, bx1, by0, by1)) continue;
+            if (!face_bins(a.recs[f], a.H, a.W, a.bs, bx0, bx1, by0, by1)) continue;
             const int nb = (bx1 - bx0 + 1) * (by1 - by0 + 1);
             float g9[9];
 #pragma unroll
-            for (int x = 0; x < 9; ++x)
-                g9[x] = (float)((double)(long long)acci[9 * j + x] * (1.0 / kFixScale)) + acc[9 * j + x];
+            for (int x = 0; x < 9; ++x) g9[x] = (float)((double)(long long)acci[9 * j + x] * (1.0 / kFixScale));
             if (nb <= kMaxPartials) {
                 float* dst = a.partial + (bin * a.M + base + j) * 9;
 #pragma unroll
