@@ -21,7 +21,7 @@ constexpr int kMaxDevices = 64;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t hdr, recs, counts, lists, order, hist, partial, fpos, big, total;
+    size_t hdr, recs, counts, lists, order, hist, partial, big, total;
     int nby, nbx, tiles_x, tiles_y;
     int64_t nbins;
 };
@@ -55,14 +55,11 @@ bool make_layout(int N, int H, int W, int64_t F, int bs, int M, Layout* L) {
         L->hist = off;
         off = align_up(off + 64 * 4);
     }
-    // backward only: per-entry partial sums (bins x M x 9 floats), each face's
-    // position in its bins (F x 4 ints) and the list of large faces (F ints)
+    // backward only: per-face partial sums, one per bin of the face's range
+    // (F x 4 x 9 floats), and the list of large faces (F ints)
     L->partial = off;
-    size_t ps = (size_t)L->nbins * (size_t)(M > 0 ? M : 0);
-    if (ps > big / 36) return false;
-    off = align_up(off + ps * 36);
-    L->fpos = off;
-    off = align_up(off + (size_t)F * 16);
+    if ((size_t)F > big / 144) return false;
+    off = align_up(off + (size_t)F * 144);
     L->big = off;
     off = align_up(off + (size_t)F * 4);
     L->total = off;
@@ -163,8 +160,7 @@ int rasterize_meshes_fwd(const float* verts_packed, int64_t V, const int32_t* fa
     if (bin_size > 0) {
         counts = (int*)(ws + L.counts);
         lists = (int*)(ws + L.lists);
-        e = rast::launch_binning(recs, F, N, H, W, bin_size, max_faces_per_bin, counts, lists, hdr, s,
-                                 (int*)(ws + L.fpos));
+        e = rast::launch_binning(recs, F, N, H, W, bin_size, max_faces_per_bin, counts, lists, hdr, s);
         if (e != hipSuccess) return RAST_EHIP;
     }
     e = rast::launch_fine(recs, mesh_to_face_first_idx, num_faces_per_mesh, counts, lists, F, N, H, W,
@@ -201,7 +197,7 @@ int rasterize_meshes_bwd(const float* verts_packed, int64_t V, const int32_t* fa
         verts_packed, V, faces_packed, F, mesh_to_face_first_idx, num_faces_per_mesh, N, H, W, faces_per_pixel,
         blur_radius, bin_size, max_faces_per_bin, pix_to_face, grad_zbuf, grad_bary, grad_dists, grad_verts,
         (int*)(ws + L.hdr), (rast::FaceRec*)(ws + L.recs), (int*)(ws + L.counts), (int*)(ws + L.lists),
-        (float*)(ws + L.partial), (int*)(ws + L.fpos), (int*)(ws + L.big), (flags & RAST_BWD_REUSE_FORWARD) != 0,
+        (float*)(ws + L.partial), (int*)(ws + L.big), (flags & RAST_BWD_REUSE_FORWARD) != 0,
         bin_signature(F, N, H, W, bin_size, bin_size > 0 ? max_faces_per_bin : 0, blur_radius), s,
         tl_events.begin[RAST_KERNEL_BWD], tl_events.end[RAST_KERNEL_BWD]));
 }

@@ -48,9 +48,8 @@ struct BwdArgs {
     const FaceRec* recs;
     const int* counts;
     const int* lists;
-    float* partial;    // (bins, M, 9): nine coordinate sums per bin-list entry
+    float* partial;    // (F, 4, 9): a face's nine coordinate sums in the i-th bin of its range
     float fix_limit;   // contributions below this magnitude use the fixed-point sums
-    const int* fpos;   // (F, 4): position of a face in each bin of its range (ranges of <= 4 bins)
     int bs, nby, nbx, M;
     int reuse;         // records and bins come from the forward: check its signature first
     BinSig sig;        // the signature this call expects
@@ -322,12 +321,12 @@ __global__ __launch_bounds__(kBwdBlock) void bwd_big_faces_kernel(BwdArgs a) {
 // fixed-point integers (scale 2^32): integer LDS atomics are far cheaper than
 // float ones on this hardware, and the per-bin sums become exact and
 // independent of the order of the additions.  A contribution too large for
-// the fixed-point headroom goes to a float accumulator instead.  Each list
-// entry's nine sums are then written next to the entry (partial[bin][j],
-// coalesced, no global atomic).  Pass 2: one thread per face reads its (at
-// most four) partials through the positions the binning pass recorded,
-// merges per vertex in LDS and issues one atomic per (vertex, coordinate).
-// Faces spanning more than four bins take global atomics directly.
+// the fixed-point headroom goes to grad_verts directly.  Each listed face's
+// nine sums are then written to the face's own slot for this bin,
+// partial[f][i] for the i-th bin of its range (no global atomic).  Pass 2:
+// one thread per face reads its (at most four) partials, contiguous, merges
+// per vertex in LDS and issues one atomic per (vertex, coordinate).  Faces
+// spanning more than four bins take global atomics directly.
 // ---------------------------------------------------------------------------
 constexpr int kP1Threads = 256;
 constexpr int kP1Chunk = 160;    // faces staged in LDS per pass over a bin's slots
@@ -488,7 +487,9 @@ __global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a) {
 #pragma unroll
             for (int x = 0; x < 9; ++x) g9[x] = (float)((double)(long long)acci[9 * j + x] * (1.0 / kFixScale));
             if (nb <= kMaxPartials) {
-                float* dst = a.partial + (bin * a.M + base + j) * 9;
+                const int i = (by - by0) * (bx1 - bx0 + 1) + (bx - bx0);  // this bin within the face's range
+                if (bx < bx0 || bx > bx1 || by < by0 || by > by1) continue;  // only a stale list could do this
+                float* dst = a.partial + ((int64_t)f * kMaxPartials + i) * 9;
 #pragma unroll
                 for (int x = 0; x < 9; ++x) dst[x] = g9[x];
             } else {
@@ -517,15 +518,11 @@ __global__ __launch_bounds__(kBwdBlock) void bwd_face_sum_kernel(BwdArgs a) {
             const int nbw = bx1 - bx0 + 1;
             const int nb = nbw * (by1 - by0 + 1);
             if (nb <= kMaxPartials) {
-                const int n = R.mesh();
                 float g9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                const float* src = a.partial + f * kMaxPartials * 9;
                 for (int i = 0; i < nb; ++i) {
-                    const int64_t bin = ((int64_t)n * a.nby + by0 + i / nbw) * a.nbx + bx0 + i % nbw;
-                    const int pos = a.fpos[4 * f + i];
-                    if (pos < 0 || pos >= a.M) continue;  // cannot happen without an overflow
-                    const float* src = a.partial + (bin * a.M + pos) * 9;
 #pragma unroll
-                    for (int x = 0; x < 9; ++x) g9[x] += src[x];
+                    for (int x = 0; x < 9; ++x) g9[x] += src[9 * i + x];
                 }
                 const int32_t* fv = a.faces + 3 * f;
 #pragma unroll
@@ -550,7 +547,7 @@ __global__ __launch_bounds__(kBwdBlock) void bwd_face_sum_kernel(BwdArgs a) {
 hipError_t launch_backward(const float* verts, int64_t V, const int32_t* faces, int64_t F, const int64_t* first,
                            const int64_t* nf, int N, int H, int W, int K, float blur, int bs, int M,
                            const int32_t* p2f, const float* gz, const float* gb, const float* gd, float* grad,
-                           int* hdr, FaceRec* recs, int* counts, int* lists, float* partial, int* fpos, int* big,
+                           int* hdr, FaceRec* recs, int* counts, int* lists, float* partial, int* big,
                            bool reuse, const BinSig& sig, hipStream_t s, hipEvent_t eb, hipEvent_t ee) {
     reuse = reuse && bs > 0;
     hipError_t e = launch_fill_f32(grad, V * 3, 0.0f, s);
@@ -583,7 +580,6 @@ hipError_t launch_backward(const float* verts, int64_t V, const int32_t* faces, 
     a.counts = counts;
     a.lists = lists;
     a.partial = partial;
-    a.fpos = fpos;
     a.bs = bs;
     // a face appears in at most bs*bs slots of a bin, each below fix_limit, so
     // a 64-bit sum of fixed-point values (scale 2^32) stays below 2^62
@@ -603,7 +599,7 @@ hipError_t launch_backward(const float* verts, int64_t V, const int32_t* faces, 
         if (!reuse) {
             e = launch_face_setup(verts, V, faces, F, first, nf, N, a.rb, recs, hdr, s);
             if (e != hipSuccess) return e;
-            e = launch_binning(recs, F, N, H, W, bs, M, counts, lists, hdr, s, fpos);
+            e = launch_binning(recs, F, N, H, W, bs, M, counts, lists, hdr, s);
             if (e != hipSuccess) return e;
         }
         const int64_t nbins = (int64_t)N * a.nby * a.nbx;

@@ -102,13 +102,10 @@ hipError_t launch_face_setup(const float* verts, int64_t V, const int32_t* faces
 // wave hold consecutive faces, which are usually neighbours on the mesh and
 // share bins, so the appends are aggregated per wave: for each distinct bin
 // among the active lanes one lane reserves room for all of them with a single
-// atomic and each lane takes its rank among them.  With fpos, a face whose
-// range has at most four bins also records its position in each of them
-// (fpos[4f + i] for the i-th bin of its range, row-major), which the
-// backward uses to find the face's per-bin partial sums.
+// atomic and each lane takes its rank among them.
 __global__ __launch_bounds__(256) void bin_faces_kernel(const FaceRec* __restrict__ recs, int64_t F, int H, int W,
                                                         int bs, int nby, int nbx, int M, int* __restrict__ counts,
-                                                        int* __restrict__ lists, int* __restrict__ fpos) {
+                                                        int* __restrict__ lists) {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     int n = 0, bx0 = 0, by0 = 0, nbw = 1, nb = 0;
@@ -138,7 +135,6 @@ __global__ __launch_bounds__(256) void bin_faces_kernel(const FaceRec* __restric
             if (act && bin == lb) {
                 const int pos = base + __popcll(same & lt_mask);
                 if (lists != nullptr && pos < M) lists[lb * M + pos] = (int)f;
-                if (fpos != nullptr && nb <= 4) fpos[4 * f + i] = pos;
             }
             pending &= ~same;
         }
@@ -159,14 +155,14 @@ __global__ void bin_max_kernel(const int* __restrict__ counts, int64_t nbins, in
 }
 
 hipError_t launch_binning(const FaceRec* recs, int64_t F, int N, int H, int W, int bs, int M, int* counts, int* lists,
-                          int* hdr, hipStream_t s, int* fpos) {
+                          int* hdr, hipStream_t s) {
     int nby = (H + bs - 1) / bs, nbx = (W + bs - 1) / bs;
     int64_t nbins = (int64_t)N * nby * nbx;
     hipError_t e = launch_fill_i32(counts, nbins, 0, s);
     if (e != hipSuccess) return e;
     if (F > 0) {
         hipLaunchKernelGGL(bin_faces_kernel, dim3((unsigned)((F + 255) / 256)), dim3(256), 0, s, recs, F, H, W, bs, nby,
-                           nbx, M, counts, lists, fpos);
+                           nbx, M, counts, lists);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
