@@ -8,7 +8,10 @@ all through the C ABI of librast.so with inputs resident in HBM.
 Default workload: 4 icospheres at subdivision level 7 (327,680 faces each),
 1024x1024 images, K = 16 nearest faces per pixel, blur radius 1e-5 -- the
 large configuration on which the HBM roofline is measured.  ``--config`` picks
-one of the other synthetic workloads instead.
+one of the other synthetic workloads instead.  Each of ``--batches`` seeded
+batches (the paper averages five) is autotuned, its forward+backward captured
+in one HIP graph and replayed ``--steps`` times; the reported step time is the
+median over the batches.
 
 Prints ONE JSON line: throughput in Mpixel*K/s (N*H*W*K / step time), ms per
 step, the roofline of the dominant kernel (timed live with HIP events the
@@ -205,7 +208,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=4, choices=[1, 2, 3, 4, 5])
-    ap.add_argument("--batch", type=int, default=0, help="seeded batch index 0..4")
+    ap.add_argument("--batch", type=int, default=0, help="first seeded batch index")
+    ap.add_argument("--batches", type=int, default=5, help="seeded batches timed (the paper averages 5)")
     ap.add_argument("--bin-size", type=int, default=None, help="fixed bin size (default: autotune)")
     ap.add_argument("--max-faces-per-bin", type=int, default=None)
     ap.add_argument("--sched", type=int, default=None)
@@ -229,83 +233,110 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    b = meshgen.make_config(args.config, batch=args.batch)
-    N, (H, W), K = b.N, b.image_size, b.faces_per_pixel
-    log(f"[bench] cfg{args.config}: N={N} {H}x{W} K={K} blur={b.blur_radius:g} V={b.verts.shape[0]} "
-        f"F={b.faces.shape[0]}")
-    v = torch.from_numpy(b.verts).to(dev)
-    f = torch.from_numpy(b.faces).to(dev)
-    fi = torch.from_numpy(b.first_idx).to(dev)
-    nf = torch.from_numpy(b.num_faces).to(dev)
-    gz_np, gb_np, gd_np = meshgen.upstream_grads(b)
-    gz = torch.from_numpy(gz_np).to(dev)
-    gb = torch.from_numpy(gb_np).to(dev)
-    gd = torch.from_numpy(gd_np).to(dev)
-
-    # ---------------------------------------------------------------- setup (untimed)
-    t0 = time.time()
-    if args.bin_size is None:
-        ch = autotune(v, f, fi, nf, H, W, b.blur_radius, K, reps=3)
-        bs, M, sched = ch.bin_size, ch.max_faces_per_bin, ch.sched
-        log(f"[bench] autotune -> bin_size={bs} M={M} sched={sched} ({ch.ms:.3f} ms) in {time.time() - t0:.1f}s")
-    else:
-        bs = args.bin_size
-        sched = args.sched or 0
-        M = args.max_faces_per_bin
-        if bs > 0 and M is None:
-            M = round_up(count_max_faces_per_bin(v, f, fi, nf, H, W, b.blur_radius, bs), 32)
-    if args.sched is not None:
-        sched = args.sched
-    M = M or 0
-    out = empty_fragments(N, H, W, K, dev)
-    ws = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, f.shape[0], bs, M), dev)
-    bws = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, f.shape[0], bs, M), dev)
-    gv = torch.empty_like(v)
+    from paper_2007_08501_amd.graph import GraphRunner
+    ev = HipEvents()
     stream = torch.cuda.current_stream(dev).cuda_stream
 
-    def step():
-        _lib.rasterize_meshes_fwd(v, f, fi, nf, H, W, b.blur_radius, K, bs, M, sched, out.pix_to_face, out.zbuf,
-                                  out.bary, out.dists, ws)
-        _lib.rasterize_meshes_bwd(v, f, fi, nf, H, W, b.blur_radius, K, bs, M, _lib.RAST_BWD_REUSE_FORWARD,
-                                  out.pix_to_face, gz, gb, gd, gv, ws)
+    def setup(batch):
+        """Inputs of one seeded batch on the device, and its bin parameters (untimed)."""
+        b = meshgen.make_config(args.config, batch=batch)
+        N, (H, W), K = b.N, b.image_size, b.faces_per_pixel
+        t = lambda a: torch.from_numpy(a).to(dev)
+        v, f, fi, nf = t(b.verts), t(b.faces), t(b.first_idx), t(b.num_faces)
+        grads_np = meshgen.upstream_grads(b)
+        t0 = time.time()
+        if args.bin_size is None:
+            ch = autotune(v, f, fi, nf, H, W, b.blur_radius, K, reps=3)
+            bs, M, sched = ch.bin_size, ch.max_faces_per_bin, ch.sched
+            log(f"[bench] batch {batch}: autotune -> bin_size={bs} M={M} sched={sched} ({ch.ms:.3f} ms) in "
+                f"{time.time() - t0:.1f}s")
+        else:
+            bs, sched, M = args.bin_size, args.sched or 0, args.max_faces_per_bin
+            if bs > 0 and M is None:
+                M = round_up(count_max_faces_per_bin(v, f, fi, nf, H, W, b.blur_radius, bs), 32)
+        if args.sched is not None:
+            sched = args.sched
+        return b, (v, f, fi, nf), grads_np, bs, M or 0, sched
 
-    ev = HipEvents()
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    # ---------------------------------------------------------------- timed region
-    n = args.steps
-    kev = [[ev.create() for _ in range(4)] for _ in range(n)]
-    e_start, e_end = ev.create(), ev.create()
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    ev.record(e_start, stream)
-    for i in range(n):
-        _lib.rast_set_kernel_events(_lib.RAST_KERNEL_FINE, kev[i][0], kev[i][1])
-        _lib.rast_set_kernel_events(_lib.RAST_KERNEL_BWD, kev[i][2], kev[i][3])
-        step()
-    ev.record(e_end, stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    _lib.rast_set_kernel_events(_lib.RAST_KERNEL_FINE, None, None)
-    _lib.rast_set_kernel_events(_lib.RAST_KERNEL_BWD, None, None)
-    total_ms = ev.elapsed(e_start, e_end)
-    ms_step = total_ms / n
-    fine_ms = sum(ev.elapsed(k[0], k[1]) for k in kev) / n
-    bwd_ms = sum(ev.elapsed(k[2], k[3]) for k in kev) / n
-    for k in kev:
-        for e in k:
+    def time_batch(b, dev_in, grads_np, bs, M, sched):
+        """Graph-replayed fwd+bwd steps, then eager steps with the library's
+        per-kernel events (the roofline's kernel times)."""
+        N, (H, W), K = b.N, b.image_size, b.faces_per_pixel
+        v, f, fi, nf = dev_in
+        gz, gb, gd = [torch.from_numpy(x).to(dev) for x in grads_np]
+        gr = GraphRunner(v, f, fi, nf, H, W, b.blur_radius, K, bs, M, sched=sched)
+        gr.set_grads(gz, gb, gd)
+        gr.capture(warmup=2)
+        for _ in range(args.warmup):
+            gr.replay()
+        torch.cuda.synchronize()
+        n = args.steps
+        e0, e1 = ev.create(), ev.create()
+        torch.cuda.synchronize()
+        ev.record(e0, stream)
+        for _ in range(n):
+            gr.replay()
+        ev.record(e1, stream)
+        torch.cuda.synchronize()
+        graph_ms = ev.elapsed(e0, e1) / n
+        st, mx = gr.status()
+        if st != _lib.RAST_OK:
+            log(f"[bench] device status: {_lib.status_string(st)} (max bin count {mx})")
+            sys.exit(1)
+        # eager steps, each kernel bracketed by HIP events on the launch stream
+        kev = [[ev.create() for _ in range(4)] for _ in range(n)]
+        torch.cuda.synchronize()
+        ev.record(e0, stream)
+        for i in range(n):
+            _lib.rast_set_kernel_events(_lib.RAST_KERNEL_FINE, kev[i][0], kev[i][1])
+            _lib.rast_set_kernel_events(_lib.RAST_KERNEL_BWD, kev[i][2], kev[i][3])
+            gr.step_eager()
+        ev.record(e1, stream)
+        torch.cuda.synchronize()
+        _lib.rast_set_kernel_events(_lib.RAST_KERNEL_FINE, None, None)
+        _lib.rast_set_kernel_events(_lib.RAST_KERNEL_BWD, None, None)
+        eager_ms = ev.elapsed(e0, e1) / n
+        fine_ms = sum(ev.elapsed(k[0], k[1]) for k in kev) / n
+        bwd_ms = sum(ev.elapsed(k[2], k[3]) for k in kev) / n
+        for e in [e0, e1] + [x for k in kev for x in k]:
             ev.destroy(e)
-    st, mx = _lib.rast_query_status(ws)
-    if st != _lib.RAST_OK:
-        log(f"[bench] device status: {_lib.status_string(st)} (max bin count {mx})")
-        sys.exit(1)
-    log(f"[bench] {n} steps: {ms_step:.4f} ms/step (wall {wall * 1e3 / n:.4f}); fine {fine_ms:.4f} ms, "
-        f"bwd {bwd_ms:.4f} ms")
+        valid = int((gr.out.pix_to_face >= 0).sum().item())
+        return dict(graph_ms=graph_ms, eager_ms=eager_ms, fine_ms=fine_ms, bwd_ms=bwd_ms, valid=valid,
+                    out=gr.out, gv=gr.grad_verts)
+
+    # ---------------------------------------------------------------- timed region, per seeded batch
+    per_batch = []
+    first_setup = None
+    for batch in range(args.batch, args.batch + args.batches):
+        su = setup(batch)
+        if first_setup is None:
+            first_setup = su
+        r = time_batch(*su)
+        r.update(batch=batch, bs=su[3], M=su[4], sched=su[5])
+        log(f"[bench] batch {batch}: {r['graph_ms']:.4f} ms/step graph-replayed, {r['eager_ms']:.4f} eager; "
+            f"fine {r['fine_ms']:.4f} ms, bwd {r['bwd_ms']:.4f} ms")
+        per_batch.append(r)
+        if batch != args.batch:
+            del r["out"], r["gv"]
+    first = per_batch[0]
+    b, dev_in, grads_np, bs, M, sched = first_setup
+    v, f, fi, nf = dev_in
+    gz_np, gb_np, gd_np = grads_np
+    gz, gb, gd = [torch.from_numpy(x).to(dev) for x in grads_np]
+    out = first["out"]
+    N, (H, W), K = b.N, b.image_size, b.faces_per_pixel
+    bws = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, f.shape[0], bs, M), dev)
+    n = args.steps
+    ms_all = [r["graph_ms"] for r in per_batch]
+    ms_step = float(np.median(ms_all))
+    ms_mean = float(np.mean(ms_all))
+    fine_ms = float(np.median([r["fine_ms"] for r in per_batch]))
+    bwd_ms = float(np.median([r["bwd_ms"] for r in per_batch]))
+    log(f"[bench] {len(per_batch)} batches x {n} steps: median {ms_step:.4f} ms/step (mean {ms_mean:.4f}); "
+        f"fine {fine_ms:.4f} ms, bwd {bwd_ms:.4f} ms")
 
     S = N * H * W * K
-    S_valid = int((out.pix_to_face >= 0).sum().item())
+    S_valid = first["valid"]
     V, F = b.verts.shape[0], b.faces.shape[0]
     fine_bytes = 24 * S + 12 * V + 12 * F
     bwd_bytes = 4 * S + 20 * S_valid + 24 * V + 12 * F
@@ -326,41 +357,53 @@ def main():
         roofline["valu"] = {"lane_ops_per_s": float(f"{lane_ops:.4g}"), "peak": VALU_PEAK_LANE_OPS,
                             "frac": round(lane_ops / VALU_PEAK_LANE_OPS, 4), "wave_instructions": int(valu)}
 
-    # ---------------------------------------------------------------- per-mesh plain form
+    # ---------------------------------------------------------------- per-mesh forms
     per_mesh = None
     if not args.no_per_mesh:
-        one_ws = None
-        outs, gvs1, calls = [], [], []
+        calls = []
         for m in range(N):
             a0, cnt = int(b.first_idx[m]), int(b.num_faces[m])
             fm = f[a0:a0 + cnt].contiguous()
-            o1 = empty_fragments(1, H, W, K, dev)
-            calls.append((fm, o1, torch.zeros(1, dtype=torch.int64, device=dev),
-                          torch.full((1,), cnt, dtype=torch.int64, device=dev)))
-        need = max(_lib.rast_workspace_size(1, H, W, c[0].shape[0], 0, 0) for c in calls)
-        one_ws = _lib.alloc_workspace(need, dev)
+            z0 = torch.zeros(1, dtype=torch.int64, device=dev)
+            c1 = torch.full((1,), cnt, dtype=torch.int64, device=dev)
+            m32 = round_up(count_max_faces_per_bin(v, fm, z0, c1, H, W, b.blur_radius, 32), 32)
+            ws1 = _lib.alloc_workspace(_lib.rast_workspace_size(1, H, W, cnt, 32, m32), dev)
+            calls.append((fm, empty_fragments(1, H, W, K, dev), z0, c1, m32, ws1, slice(m, m + 1)))
+        one_ws = _lib.alloc_workspace(max(_lib.rast_workspace_size(1, H, W, c[0].shape[0], 0, 0) for c in calls), dev)
         gvm = torch.empty_like(v)
 
-        def per_mesh_step():
-            for fm, o1, z0, c1 in calls:
-                _lib.rasterize_meshes_fwd(v, fm, z0, c1, H, W, b.blur_radius, K, 0, 0, 0, o1.pix_to_face, o1.zbuf,
-                                          o1.bary, o1.dists, one_ws)
-                _lib.rasterize_meshes_bwd(v, fm, z0, c1, H, W, b.blur_radius, K, 0, 0, 0, o1.pix_to_face, gz[:1],
-                                          gb[:1], gd[:1], gvm, one_ws)
+        def per_mesh_step(binned):
+            # one call pair per mesh, no graph: single pass, or bins of 32 pixels
+            for fm, o1, z0, c1, m32, ws1, sl in calls:
+                bs1, M1, w = (32, m32, ws1) if binned else (0, 0, one_ws)
+                _lib.rasterize_meshes_fwd(v, fm, z0, c1, H, W, b.blur_radius, K, bs1, M1, 0, o1.pix_to_face, o1.zbuf,
+                                          o1.bary, o1.dists, w)
+                _lib.rasterize_meshes_bwd(v, fm, z0, c1, H, W, b.blur_radius, K, bs1, M1,
+                                          _lib.RAST_BWD_REUSE_FORWARD if binned else 0, o1.pix_to_face, gz[sl],
+                                          gb[sl], gd[sl], gvm, w)
 
-        per_mesh_step()
-        torch.cuda.synchronize()
-        reps = 2
-        a, c = ev.create(), ev.create()
-        ev.record(a, stream)
-        for _ in range(reps):
-            per_mesh_step()
-        ev.record(c, stream)
-        pm_ms = ev.elapsed(a, c) / reps
+        def time_form(binned, reps):
+            per_mesh_step(binned)
+            torch.cuda.synchronize()
+            a, c = ev.create(), ev.create()
+            ev.record(a, stream)
+            for _ in range(reps):
+                per_mesh_step(binned)
+            ev.record(c, stream)
+            ms = ev.elapsed(a, c) / reps
+            ev.destroy(a)
+            ev.destroy(c)
+            return ms
+
+        pm_ms = time_form(False, 2)
+        pb_ms = time_form(True, 5)
         per_mesh = {"ms_per_batch": round(pm_ms, 4), "value": round(S / (pm_ms * 1e-3) / 1e6, 2),
                     "form": "one single-pass fwd+bwd call per mesh (no bins, no graph)",
-                    "speedup_batched": round(pm_ms / ms_step, 2)}
-        log(f"[bench] per-mesh plain {pm_ms:.3f} ms/batch")
+                    "speedup_batched": round(pm_ms / ms_step, 2),
+                    "binned32": {"ms_per_batch": round(pb_ms, 4), "value": round(S / (pb_ms * 1e-3) / 1e6, 2),
+                                 "form": "one fwd+bwd call per mesh with 32-pixel bins (no graph)",
+                                 "speedup_batched": round(pb_ms / ms_step, 2)}}
+        log(f"[bench] per-mesh plain {pm_ms:.3f} ms/batch, per-mesh bins-32 {pb_ms:.3f} ms/batch")
 
     # ---------------------------------------------------------------- CPU baseline (oracle) + sampled parity
     cpu, parity = None, None
@@ -388,6 +431,13 @@ def main():
         "slots": S, "slots_valid": S_valid, "step_algorithmic_bytes": step_bytes,
         "step_hbm_frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "kernels_ms": {"fine": round(fine_ms, 5), "backward": round(bwd_ms, 5)},
+        "timing": {"form": "autotuned, fwd+bwd captured in one HIP graph and replayed; value and ms_per_step are "
+                           "the median over seeded batches",
+                   "batches": [r["batch"] for r in per_batch],
+                   "ms_per_step_graph": [round(r["graph_ms"], 5) for r in per_batch],
+                   "ms_per_step_mean": round(ms_mean, 5),
+                   "ms_per_step_eager": round(float(np.median([r["eager_ms"] for r in per_batch])), 5),
+                   "bins": [[r["bs"], r["M"], r["sched"]] for r in per_batch]},
         "roofline": roofline, "cpu_baseline": cpu, "per_mesh": per_mesh, "parity": parity,
     }
     print(json.dumps(res), flush=True)

@@ -224,7 +224,10 @@ struct TileLds {
 // Pixels of the 8x8 tile (x0, y0) whose centres the box [bb.x, bb.y] x
 // [bb.z, bb.w] may contain, from the same conservative pixel ranges as the
 // binning (an empty box gives 0).
-__device__ __forceinline__ uint64_t tile_mask(const float4 bb, int H, int W, int x0, int y0) {
+__device__ __forceinline__ uint64_t tile_mask(const float4 bb, int H, int W, int x0, int y0, float tx_lo, float tx_hi,
+                                              float ty_lo, float ty_hi) {
+    // most faces of a single-pass tile miss it: reject those on the box alone
+    if (bb.y < tx_lo || bb.x > tx_hi || bb.w < ty_lo || bb.z > ty_hi) return 0ull;
     int c0, c1, r0, r1;
     pix_range(bb.x, bb.y, W, c0, c1);
     pix_range(bb.z, bb.w, H, r0, r1);
@@ -382,7 +385,13 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
     const int c = tx * kTile + (lane & 7);
     const bool live = (r < a.H) && (c < a.W);
     const Pix p = make_pix(r, c, a.H, a.W);
-    // extent of the tile's pixel centres (x decreases with c, y with r)
+    // extent of the tile's pixel centres (x decreases with c, y with r), less a
+    // margin so that the float test never rejects what the pixel ranges keep
+    const int c_last = min(tx * kTile + kTile - 1, a.W - 1);
+    const int r_last = min(ty * kTile + kTile - 1, a.H - 1);
+    const float mx = 0.1f / (float)a.W, my = 0.1f / (float)a.H;  // 0.05 px, looser than pix_range (0.01 px)
+    const float tx_hi = pix_x(tx * kTile, a.W) + mx, tx_lo = pix_x(c_last, a.W) - mx;
+    const float ty_hi = pix_y(ty * kTile, a.H) + my, ty_lo = pix_y(r_last, a.H) - my;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     TopK<KB> top;
@@ -414,7 +423,8 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
         const float4* rsrc = reinterpret_cast<const float4*>(a.recs + (in_list ? fid : (BINNED ? list[0] : (int)base)));
         const float4 rv0 = rsrc[0], rv1 = rsrc[1], rv2 = rsrc[2], rv3 = rsrc[3], rv4 = rsrc[4], rv5 = rsrc[5];
         const float4 rv6 = rsrc[6];
-        const uint64_t pm = in_list ? tile_mask(rv6, a.H, a.W, tx * kTile, ty * kTile) : 0ull;
+        const uint64_t pm =
+            in_list ? tile_mask(rv6, a.H, a.W, tx * kTile, ty * kTile, tx_lo, tx_hi, ty_lo, ty_hi) : 0ull;
         const bool keep = pm != 0ull;
         const uint64_t kept = __ballot(keep);
         const int m = __popcll(kept);

@@ -1,9 +1,9 @@
 """hipGraph capture of a whole forward+backward rasterization step.
 
 The runner owns static device buffers (vertex positions, fragments, upstream
-gradients, vertex gradients and both workspaces), captures one forward and one
-backward call of the C ABI into a HIP graph through torch.cuda.graph, and
-replays it.  Inputs are updated in place with ``set_verts`` / ``set_grads``
+gradients, vertex gradients and one workspace, whose face records and bins the
+backward reuses from the forward), captures one forward and one backward call
+of the C ABI into a HIP graph through torch.cuda.graph, and replays it.  Inputs are updated in place with ``set_verts`` / ``set_grads``
 between replays; the device status (bin overflow) is read after a replay,
 never inside the graph.  Every kernel in the captured calls clears its
 counters with a fill kernel, so a replay needs no memset node.
