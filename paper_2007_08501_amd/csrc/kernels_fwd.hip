@@ -274,6 +274,9 @@ __device__ __forceinline__ void write_fragments(const FineArgs& a, TileLds& L, c
     const int rows = min(kTile, a.H - ty * kTile), cols = min(kTile, a.W - tx * kTile);
     const int64_t pix0 = ((int64_t)n * a.H + ty * kTile) * a.W + tx * kTile;
     const int rowK = a.W * K;  // fragments per image row
+    // EXACT with K a multiple of 4 (the launcher also checked that the four
+    // outputs are 16-byte aligned): 16-byte stores of four slots
+    constexpr bool V4 = EXACT && (KB % 4 == 0);
     int32_t* const p2f_t = a.p2f + pix0 * K;
     float* const zbuf_t = a.zbuf + pix0 * K;
     float* const dist_t = a.dists + pix0 * K;
@@ -298,19 +301,37 @@ __device__ __forceinline__ void write_fragments(const FineArgs& a, TileLds& L, c
                 sz[lane * S + k] = empty ? -1.0f : __uint_as_float((uint32_t)(key >> 32));
             }
             __syncthreads();
-            const int gw = min(G, K - g0);
-            const float inv = 1.0f / (float)gw;
+            if constexpr (V4) {
+                // four consecutive slots of one pixel per lane and store
+                constexpr int Q = G / 4;
 #pragma unroll
-            for (int e0 = 0; e0 < 64 * G; e0 += 64) {
-                const int e = e0 + lane;
-                if (e >= 64 * gw) break;
-                const int px = EXACT ? e / gw : stage_pixel(e, inv);
-                const int k = e - px * gw;
-                const int r = px >> 3, c = px & 7;
-                if (r < rows && c < cols) {
-                    const int o = r * rowK + c * K + g0 + k;
-                    p2f_t[o] = sid[px * S + k];
-                    zbuf_t[o] = sz[px * S + k];
+                for (int e0 = 0; e0 < 64 * Q; e0 += 64) {
+                    const int e = e0 + lane;
+                    const int px = e / Q, q = e - px * Q;
+                    const int r = px >> 3, c = px & 7;
+                    if (r < rows && c < cols) {
+                        const int o = r * rowK + c * K + g0 + 4 * q;
+                        const int* si = sid + px * S + 4 * q;
+                        const float* zi = sz + px * S + 4 * q;
+                        *reinterpret_cast<int4*>(p2f_t + o) = make_int4(si[0], si[1], si[2], si[3]);
+                        *reinterpret_cast<float4*>(zbuf_t + o) = make_float4(zi[0], zi[1], zi[2], zi[3]);
+                    }
+                }
+            } else {
+                const int gw = min(G, K - g0);
+                const float inv = 1.0f / (float)gw;
+#pragma unroll
+                for (int e0 = 0; e0 < 64 * G; e0 += 64) {
+                    const int e = e0 + lane;
+                    if (e >= 64 * gw) break;
+                    const int px = EXACT ? e / gw : stage_pixel(e, inv);
+                    const int k = e - px * gw;
+                    const int r = px >> 3, c = px & 7;
+                    if (r < rows && c < cols) {
+                        const int o = r * rowK + c * K + g0 + k;
+                        p2f_t[o] = sid[px * S + k];
+                        zbuf_t[o] = sz[px * S + k];
+                    }
                 }
             }
             __syncthreads();
@@ -344,25 +365,51 @@ __device__ __forceinline__ void write_fragments(const FineArgs& a, TileLds& L, c
                 sd[lane * SD + k] = d;
             }
             __syncthreads();
-            const int gw = min(G, K - g0);
-            const float inv3 = 1.0f / (float)(3 * gw), inv1 = 1.0f / (float)gw;
+            if constexpr (V4) {
+                constexpr int QB = 3 * G / 4, QD = G / 4;
 #pragma unroll
-            for (int e0 = 0; e0 < 64 * 3 * G; e0 += 64) {
-                const int e = e0 + lane;
-                if (e >= 64 * 3 * gw) break;
-                const int px = EXACT ? e / (3 * gw) : stage_pixel(e, inv3);
-                const int m = e - px * 3 * gw;
-                const int r = px >> 3, c = px & 7;
-                if (r < rows && c < cols) bary_t[3 * (r * rowK + c * K + g0) + m] = sb[px * SB + m];
-            }
+                for (int e0 = 0; e0 < 64 * QB; e0 += 64) {
+                    const int e = e0 + lane;
+                    const int px = e / QB, q = e - px * QB;
+                    const int r = px >> 3, c = px & 7;
+                    if (r < rows && c < cols) {
+                        const float* bi = sb + px * SB + 4 * q;
+                        *reinterpret_cast<float4*>(bary_t + 3 * (r * rowK + c * K + g0) + 4 * q) =
+                            make_float4(bi[0], bi[1], bi[2], bi[3]);
+                    }
+                }
 #pragma unroll
-            for (int e0 = 0; e0 < 64 * G; e0 += 64) {
-                const int e = e0 + lane;
-                if (e >= 64 * gw) break;
-                const int px = EXACT ? e / gw : stage_pixel(e, inv1);
-                const int k = e - px * gw;
-                const int r = px >> 3, c = px & 7;
-                if (r < rows && c < cols) dist_t[r * rowK + c * K + g0 + k] = sd[px * SD + k];
+                for (int e0 = 0; e0 < 64 * QD; e0 += 64) {
+                    const int e = e0 + lane;
+                    const int px = e / QD, q = e - px * QD;
+                    const int r = px >> 3, c = px & 7;
+                    if (r < rows && c < cols) {
+                        const float* di = sd + px * SD + 4 * q;
+                        *reinterpret_cast<float4*>(dist_t + r * rowK + c * K + g0 + 4 * q) =
+                            make_float4(di[0], di[1], di[2], di[3]);
+                    }
+                }
+            } else {
+                const int gw = min(G, K - g0);
+                const float inv3 = 1.0f / (float)(3 * gw), inv1 = 1.0f / (float)gw;
+#pragma unroll
+                for (int e0 = 0; e0 < 64 * 3 * G; e0 += 64) {
+                    const int e = e0 + lane;
+                    if (e >= 64 * 3 * gw) break;
+                    const int px = EXACT ? e / (3 * gw) : stage_pixel(e, inv3);
+                    const int m = e - px * 3 * gw;
+                    const int r = px >> 3, c = px & 7;
+                    if (r < rows && c < cols) bary_t[3 * (r * rowK + c * K + g0) + m] = sb[px * SB + m];
+                }
+#pragma unroll
+                for (int e0 = 0; e0 < 64 * G; e0 += 64) {
+                    const int e = e0 + lane;
+                    if (e >= 64 * gw) break;
+                    const int px = EXACT ? e / gw : stage_pixel(e, inv1);
+                    const int k = e - px * gw;
+                    const int r = px >> 3, c = px & 7;
+                    if (r < rows && c < cols) dist_t[r * rowK + c * K + g0 + k] = sd[px * SD + k];
+                }
             }
             __syncthreads();
         }
@@ -610,10 +657,13 @@ hipError_t launch_fine(const FaceRec* recs, const int64_t* first, const int64_t*
     a.bary = bary;
     a.dists = dists;
     bool binned = bs > 0;
-    // queue sizes are powers of two; K equal to one gets the compile-time-K kernels
+    // queue sizes are powers of two; K equal to one gets the compile-time-K
+    // kernels, which store four slots at a time and so need 16-byte aligned
+    // outputs
+    const bool aligned = (((uintptr_t)p2f | (uintptr_t)zbuf | (uintptr_t)bary | (uintptr_t)dists) & 15) == 0;
 #define RAST_FINE_BUCKET(KB)                                                                          \
     if (K <= KB) {                                                                                    \
-        if (K == KB) return launch_fine_k<KB, true>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee); \
+        if (K == KB && aligned) return launch_fine_k<KB, true>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee); \
         return launch_fine_k<KB, false>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);     \
     }
     if (K <= 1) return launch_fine_k<1, true>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);

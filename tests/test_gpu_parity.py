@@ -429,3 +429,29 @@ def test_softmax_blend_vs_oracle(C):
     compare_grad(zt.grad.cpu().numpy(), rgz, "softmax zbuf")
     compare_grad(dt.grad.cpu().numpy(), rgd, "softmax dists")
     compare_grad(ct.grad.cpu().numpy(), rgc, "softmax colors")
+
+
+def test_unaligned_outputs_match_aligned():
+    """Outputs that are not 16-byte aligned take the general store path; the
+    fragments must be identical to those of aligned outputs."""
+    b = meshgen.make_config(2, n_override=2, level_override=3, image_override=40)
+    d = to_dev(b)
+    ref, _ = run_fwd(b, 8, dev_inputs=d)
+    v, f, fi, nf = d
+    N, (H, W), K = b.N, b.image_size, b.faces_per_pixel
+    M = bin_capacity(b, 8, d)
+
+    def shifted(shape, dtype):
+        n = int(np.prod(shape))
+        return torch.empty(n + 1, dtype=dtype, device="cuda")[1:].view(shape)
+
+    p2f = shifted((N, H, W, K), torch.int32)
+    zb = shifted((N, H, W, K), torch.float32)
+    ba = shifted((N, H, W, K, 3), torch.float32)
+    di = shifted((N, H, W, K), torch.float32)
+    assert p2f.data_ptr() % 16 != 0
+    ws = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, f.shape[0], 8, M), v.device)
+    _lib.rasterize_meshes_fwd(v, f, fi, nf, H, W, b.blur_radius, K, 8, M, 0, p2f, zb, ba, di, ws)
+    torch.cuda.synchronize()
+    for x, y in zip(ref, (p2f, zb, ba, di)):
+        assert torch.equal(x, y)
