@@ -84,7 +84,7 @@ def test_reduced_cfg5_K50_vs_oracle():
     log(st)
 
 
-@pytest.mark.parametrize("K", [1, 2, 3, 5, 7, 12, 16, 20, 33, 64])
+@pytest.mark.parametrize("K", [1, 2, 3, 4, 5, 7, 8, 12, 16, 20, 32, 33, 64])
 def test_every_K_bucket(K):
     b = meshgen.make_config(2, n_override=2, level_override=3, image_override=40)
     b.blur_radius = float(np.float32(3e-3))
