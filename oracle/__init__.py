@@ -1,4 +1,5 @@
-"""FP64 CPU oracle for the batched mesh rasterizer and the silhouette blend.
+"""FP64 CPU oracle for the batched mesh rasterizer, the point-cloud
+rasterizer, and the blending and compositing steps.
 
 TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU-baseline
 leg of the benchmark may import this package.  The product path (the HIP
@@ -6,9 +7,11 @@ library and its Python binding) never imports, links or calls it, and it never
 imports the product path: the two share nothing but the seeded input
 generator, which holds none of the method's arithmetic.
 
-The rasterizer oracle is plain C (``oracle_rast.c``, built here with gcc and
-loaded with ctypes); the blend oracle is NumPy in float64 (``blend.py``); the
-silhouette-fitting loss and its gradient chain them (``silfit.py``).
+The rasterizer oracles are plain C (``oracle_rast.c`` for meshes,
+``oracle_points.c`` for point clouds, built here with gcc and loaded with
+ctypes); the blend oracle is NumPy in float64 (``blend.py``), as are the
+point compositing oracle (``points.py``) and the silhouette-fitting loss and
+its gradient (``silfit.py``).
 """
 from __future__ import annotations
 
@@ -20,17 +23,21 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "oracle_rast.c")
+_SRCS = [os.path.join(_HERE, "oracle_rast.c"), os.path.join(_HERE, "oracle_points.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
+def _stale() -> bool:
+    return not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(s) for s in _SRCS)
+
+
 def build(force: bool = True) -> str:
     """Compile oracle_rast.c into liboracle.so (gcc, -O2, OpenMP, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or _stale():
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
-               "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", tmp, "-lm"]
+               "-fno-fast-math", "-ffp-contract=off"] + _SRCS + ["-o", tmp, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB)
     return _LIB
@@ -40,7 +47,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if _stale():
         build(force=True)
     lib = ctypes.CDLL(_LIB)
     P = ctypes.c_void_p
@@ -53,6 +60,10 @@ def _load():
     lib.oracle_fragments_fixed.restype = ci
     lib.oracle_backward.argtypes = [P, i64, P, ci, ci, ci, ci, P, i64, P, P, P, P, P, ci]
     lib.oracle_backward.restype = ci
+    lib.oracle_points_rasterize.argtypes = [P, i64, P, P, ci, ci, ci, ctypes.c_double, ci, P, i64, P, P, P, P, ci]
+    lib.oracle_points_rasterize.restype = ci
+    lib.oracle_points_backward.argtypes = [P, i64, ci, ci, ci, ci, P, i64, P, P, P, P, ci]
+    lib.oracle_points_backward.restype = ci
     lib.oracle_max_threads.argtypes = []
     lib.oracle_max_threads.restype = ci
     _lib = lib
@@ -165,5 +176,59 @@ def backward(verts, faces, image_size, p2f, grad_zbuf=None, grad_bary=None, grad
     return out
 
 
+def rasterize_points(points, first_idx, num_points, image_size, radius, points_per_pixel, pixels=None,
+                     nthreads: Optional[int] = None):
+    """FP64 brute-force point rasterizer (oracle_points.c).  points (P,3);
+    first_idx/num_points (N,).  Returns dict idx (int64), zbuf, dists
+    (float64) shaped (N,H,W,K) -- or (npix,K) rows with ``pixels`` -- and
+    amb (uint8 per pixel, see the C source)."""
+    lib = _load()
+    H, W = image_size
+    pts = _f64(points)
+    fi = _i64(first_idx)
+    npts = _i64(num_points)
+    N = fi.shape[0]
+    K = int(points_per_pixel)
+    pix = None if pixels is None else _i64(pixels)
+    rows = N * H * W if pix is None else pix.shape[0]
+    idx = np.empty((rows, K), np.int64)
+    zbuf = np.empty((rows, K), np.float64)
+    dists = np.empty((rows, K), np.float64)
+    amb = np.empty(rows, np.uint8)
+    rc = lib.oracle_points_rasterize(_ptr(pts), pts.shape[0], _ptr(fi), _ptr(npts), N, H, W, float(radius), K,
+                                     _ptr(pix), 0 if pix is None else pix.shape[0], _ptr(idx), _ptr(zbuf),
+                                     _ptr(dists), _ptr(amb), nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("oracle_points_rasterize rejected its arguments")
+    out = dict(idx=idx, zbuf=zbuf, dists=dists, amb=amb)
+    if pix is None:
+        out = {k: a.reshape((N, H, W) + a.shape[1:]) for k, a in out.items()}
+    return out
+
+
+def points_backward(points, image_size, idx, grad_zbuf=None, grad_dists=None, pixels=None, N=None,
+                    nthreads: Optional[int] = None):
+    """Analytic FP64 dL/dpoints (P,3) for L = <gz, zbuf> + <gd, dists> over
+    the slots of idx (N,H,W,K), or of (npix,K) rows with ``pixels``."""
+    lib = _load()
+    H, W = image_size
+    pts = _f64(points)
+    ix = _i64(idx)
+    K = ix.shape[-1]
+    pix = None if pixels is None else _i64(pixels)
+    if pix is None:
+        N = ix.shape[0]
+    gz = None if grad_zbuf is None else _f64(grad_zbuf)
+    gd = None if grad_dists is None else _f64(grad_dists)
+    out = np.empty(pts.shape, np.float64)
+    rc = lib.oracle_points_backward(_ptr(pts), pts.shape[0], int(N or 1), H, W, K, _ptr(pix),
+                                    0 if pix is None else pix.shape[0], _ptr(ix), _ptr(gz), _ptr(gd), _ptr(out),
+                                    nthreads or default_threads())
+    if rc != 0:
+        raise MemoryError("oracle_points_backward failed")
+    return out
+
+
+from .points import alpha_composite, alpha_composite_backward, norm_composite, norm_composite_backward  # noqa: E402,F401
 from .blend import (iou_loss, silhouette_blend, silhouette_blend_backward, softmax_blend,  # noqa: E402,F401
                     softmax_blend_backward)

@@ -19,7 +19,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
-from typing import List, Optional, Sequence
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -375,3 +375,99 @@ def silhouette_fit_problem(level=4, n_views=20, seed=5000, amplitude=0.1):
         rots.append(Rx @ Ry)
     return SilhouetteFitProblem(level=level, base=v, target=target, faces=f,
                                 rotations=np.stack(rots), n_views=n_views)
+
+
+# ---------------------------------------------------------------- point clouds
+
+POINT_CONFIG_NAMES = {
+    1: "1 cloud x 2,000 points, 64x64, K=8, radius 0.05",
+    2: "4 clouds x {1k, 3k, 5k, 8k} points, 96x96, K=16, radius 0.03",
+    3: "8 clouds x 200,000 points, 256x256, K=50, radius 0.01",
+}
+
+
+@dataclass
+class PointBatch:
+    """A packed heterogeneous point-cloud batch plus rasterization settings.
+
+    points: (P,3) float32, x and y in NDC, z the depth; first_idx /
+    num_points: (N,) int64 point range of each cloud."""
+
+    name: str
+    points: np.ndarray
+    first_idx: np.ndarray
+    num_points: np.ndarray
+    image_size: Tuple[int, int]
+    points_per_pixel: int
+    radius: float
+    seed: int
+
+    @property
+    def N(self) -> int:
+        return int(self.first_idx.shape[0])
+
+
+def sample_surface(level: int, n: int, rng: np.random.Generator) -> np.ndarray:
+    """n points uniformly distributed over the surface of the level-`level`
+    icosphere (faces chosen with probability proportional to their area,
+    then a uniform point in the face).  Float64 (n,3)."""
+    v, f = icosphere(level)
+    tri = v[f]
+    area = 0.5 * np.linalg.norm(np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0]), axis=1)
+    face = rng.choice(f.shape[0], size=n, p=area / area.sum())
+    r1 = np.sqrt(rng.uniform(size=n))
+    r2 = rng.uniform(size=n)
+    a, b, c = tri[face, 0], tri[face, 1], tri[face, 2]
+    return (1 - r1)[:, None] * a + (r1 * (1 - r2))[:, None] * b + (r1 * r2)[:, None] * c
+
+
+def make_points_config(i: int, batch: int = 0, n_override: Optional[int] = None,
+                       image_override: Optional[int] = None, points_override: Optional[int] = None) -> PointBatch:
+    """Seeded synthetic point-cloud workloads: clouds sampled from sphere
+    surfaces (a stand-in for points sampled from ShapeNet meshes), each with a
+    random rotation, xy scaled into NDC and z shifted in front of the camera.
+    Seed 7000 + 100 * i + batch; per cloud the draws are: size, surface
+    samples, rotation, xy offset, z shift."""
+    seed = 7000 + 100 * i + batch
+    rng = np.random.default_rng(seed)
+    if i == 1:
+        sizes, img, K, radius, ndc = [2000], 64, 8, 0.05, 0.8
+    elif i == 2:
+        sizes, img, K, radius, ndc = [1000, 3000, 5000, 8000], 96, 16, 0.03, 0.7
+    elif i == 3:
+        sizes, img, K, radius, ndc = [200000] * 8, 256, 50, 0.01, 0.8
+    else:
+        raise ValueError(f"unknown point config {i}")
+    if n_override is not None:
+        sizes = (sizes * n_override)[:n_override]
+    if points_override is not None:
+        sizes = [points_override] * len(sizes)
+    clouds = []
+    for n in sizes:
+        u = sample_surface(3, n, rng)
+        R = random_rotation(rng)
+        off = rng.uniform(-0.1, 0.1, size=2)
+        dz = rng.uniform(1.8, 2.2)
+        clouds.append(transform_mesh(u, rot=R, ndc_scale=ndc, offset=off, dz=dz))
+    pts = np.concatenate(clouds).astype(np.float32)
+    num = np.array(sizes, dtype=np.int64)
+    first = np.concatenate([[0], np.cumsum(num)[:-1]]).astype(np.int64)
+    if image_override is not None:
+        img = image_override
+    return PointBatch(name=f"pts{i}", points=pts, first_idx=first, num_points=num, image_size=(img, img),
+                      points_per_pixel=K, radius=float(np.float32(radius)), seed=seed)
+
+
+def point_grads(batch: PointBatch, channels: int = 3):
+    """Seeded float32 inputs of the point backward and compositing tests:
+    upstream gradients for zbuf and dists (N,H,W,K), per-point features
+    (P, channels) in [0, 1), and an upstream gradient of the composited image
+    (N,H,W,channels); drawn in that order from default_rng(seed + 500)."""
+    rng = np.random.default_rng(batch.seed + 500)
+    H, W = batch.image_size
+    shp = (batch.N, H, W, batch.points_per_pixel)
+    gz = rng.standard_normal(shp, dtype=np.float32)
+    gd = rng.standard_normal(shp, dtype=np.float32)
+    feat = rng.uniform(size=(batch.points.shape[0], channels)).astype(np.float32)
+    gimg = rng.standard_normal((batch.N, H, W, channels), dtype=np.float32)
+    return gz, gd, feat, gimg

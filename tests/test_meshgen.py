@@ -59,3 +59,18 @@ def test_upstream_grads_seeded():
     for x, y in zip(g1, g2):
         assert x.dtype == np.float32 and np.array_equal(x, y)
     assert g1[1].shape == (8, 32, 32, 4, 3)
+
+
+def test_point_configs_are_seeded_and_on_surfaces():
+    a = meshgen.make_points_config(2, batch=1)
+    b = meshgen.make_points_config(2, batch=1)
+    np.testing.assert_array_equal(a.points, b.points)
+    assert not np.array_equal(a.points, meshgen.make_points_config(2, batch=2).points)
+    assert a.points.dtype == np.float32 and a.points.shape == (17000, 3)
+    assert list(a.num_points) == [1000, 3000, 5000, 8000] and list(a.first_idx) == [0, 1000, 4000, 9000]
+    # samples lie on the template's faces: within the unit sphere, near its surface
+    rng = np.random.default_rng(0)
+    u = meshgen.sample_surface(3, 5000, rng)
+    r = np.linalg.norm(u, axis=1)
+    assert (r <= 1 + 1e-12).all() and (r > 0.98).all()
+    assert (a.points[:, 2] > 0).all()
