@@ -1,5 +1,5 @@
 /*
- * rast.h -- C ABI of the MI355X (gfx950) batched differentiable mesh rasterizer.
+ * rast.h -- C ABI of the MI355X (gfx950) batched differentiable mesh and point-cloud rasterizer.
  *
  * The operation (paper, Section 3.2, "Rasterizer"): for every pixel of every
  * image in a heterogeneous batch of triangle meshes, find the K faces nearest
@@ -173,10 +173,13 @@ const char* rast_status_string(int status);
  * and after the launch of its per-pixel kernel, so the caller can time that
  * kernel alone.  Pass NULL for both to switch it off.  Do not leave events set
  * while capturing a graph.  Returns RAST_EINVAL for an unknown kernel or a
- * single NULL.
+ * single NULL.  The point-cloud entries take RAST_KERNEL_POINTS_FINE and
+ * RAST_KERNEL_POINTS_BWD the same way.
  */
 #define RAST_KERNEL_FINE 0
 #define RAST_KERNEL_BWD 1
+#define RAST_KERNEL_POINTS_FINE 2 /* rasterize_points_fwd: the per-tile pass */
+#define RAST_KERNEL_POINTS_BWD 3  /* rasterize_points_bwd: the per-point gather */
 int rast_set_kernel_events(int kernel, void* begin, void* end);
 
 /*
@@ -228,6 +231,109 @@ int softmax_blend_fwd(const int32_t* pix_to_face, const float* zbuf, const float
 int softmax_blend_bwd(const int32_t* pix_to_face, const float* zbuf, const float* dists, const float* colors,
                       int64_t P, int K, int C, float sigma, float gamma, float znear, float zfar,
                       const float* grad_image, float* grad_zbuf, float* grad_dists, float* grad_colors, void* stream);
+
+/* ==========================================================================
+ * Point clouds (paper, Section 3.3, "Differentiable point cloud renderer").
+ *
+ * Every point is splatted to a disc of radius `radius` (NDC units) in screen
+ * space.  For every pixel of image n the rasterizer returns the K points of
+ * cloud n nearest along z whose discs cover the pixel centre, with their z
+ * and their squared xy distance to the centre; compositing then blends the
+ * points' features by Alpha compositing or by a normalised weighted sum.
+ *
+ *  - points (P,3) float32: x, y in NDC (pixel centres as for meshes), z the
+ *    depth.  Cloud n owns points [cloud_to_first_idx[n], ... +
+ *    num_points_per_cloud[n]) (int64, device; ascending, non-overlapping,
+ *    inside [0, P]; a violation is reported as RAST_EMESH by
+ *    rast_query_status).  Points outside every cloud are ignored.
+ *  - A point covers a pixel iff its z >= 0 and (x - px)^2 + (y - py)^2 <
+ *    radius^2, the squared distance evaluated in FP64 from the float32
+ *    coordinates and the FP64 pixel centre as (dx*dx) + (dy*dy), with no
+ *    fused operations: the decision is the same bit for bit as that plain
+ *    evaluation.
+ *  - Slots are ordered by ascending z, ties by ascending point index.  Empty
+ *    slots hold idx = -1, zbuf = -1, dists = -1.  dists is the FP64 squared
+ *    distance rounded to float32.
+ *  - Limits: P <= RAST_POINTS_MAX, H and W <= RAST_POINTS_MAX_SIDE,
+ *    0 <= radius <= RAST_POINTS_MAX_RADIUS, K in [1, RAST_KMAX].
+ * ========================================================================== */
+#define RAST_POINTS_MAX ((int64_t)1 << 30)
+#define RAST_POINTS_MAX_SIDE 16384
+#define RAST_POINTS_MAX_RADIUS 2.0f
+
+/*
+ * Bytes of workspace for rasterize_points_fwd / _bwd with these sizes: a
+ * header, per-tile point counts and starts, and the points sorted by home
+ * tile (16 bytes per point), about 24 bytes per point in all.
+ */
+int rast_points_workspace_size(int N, int H, int W, int64_t P, size_t* bytes_out);
+
+/*
+ * Forward.  Outputs idx (N,H,W,K) int32, zbuf and dists (N,H,W,K) float32,
+ * all overwritten (K = points_per_pixel).  The workspace keeps the sorted
+ * points for a backward with RAST_BWD_REUSE_FORWARD.
+ * Errors: RAST_EINVAL (sizes, limits, NULL pointers), RAST_EWORKSPACE,
+ * RAST_EHIP; device-side RAST_EMESH via rast_query_status.
+ */
+int rasterize_points_fwd(const float* points, int64_t P, const int64_t* cloud_to_first_idx,
+                         const int64_t* num_points_per_cloud, int N, int H, int W, float radius,
+                         int points_per_pixel, int32_t* idx, float* zbuf, float* dists, void* workspace,
+                         size_t workspace_bytes, void* stream);
+
+/*
+ * Backward for L = <grad_zbuf, zbuf> + <grad_dists, dists> with the choice
+ * of points held fixed: dL/dz_p sums grad_zbuf over p's slots and
+ * dL/d(x_p, y_p) sums 2 grad_dists (x_p - px, y_p - py).  grad_points (P,3)
+ * float32 is overwritten; grad_zbuf or grad_dists may be NULL (no term).
+ * idx must be the output of rasterize_points_fwd for these points, cloud
+ * ranges, size and radius: each point's slots are looked up among the pixels
+ * its disc covers, so a slot naming a point at a pixel it does not cover is
+ * ignored.  flags: 0 (sort the points again) or RAST_BWD_REUSE_FORWARD (take
+ * the sorted points from the forward's workspace, unchanged since; a
+ * workspace last used by another call is detected from its signature, the
+ * gradient is then left zero and rast_query_status reports RAST_EREUSE).
+ */
+int rasterize_points_bwd(const float* points, int64_t P, const int64_t* cloud_to_first_idx,
+                         const int64_t* num_points_per_cloud, int N, int H, int W, float radius,
+                         int points_per_pixel, int flags, const int32_t* idx, const float* grad_zbuf,
+                         const float* grad_dists, float* grad_points, void* workspace, size_t workspace_bytes,
+                         void* stream);
+
+/*
+ * Point compositing (paper, Section 3.3) over npix pixels of K slots with
+ * features (P,D) float32 (D in [1, RAST_COMPOSITE_DMAX]).  For a pixel whose
+ * slots k hold points idx_k with opacities alpha_k, in slot order (nearest
+ * first):
+ *   RAST_COMPOSITE_ALPHA: image = sum_k alpha_k prod_{j<k} (1 - alpha_j) f_{idx_k}
+ *   RAST_COMPOSITE_NORM:  image = sum_k alpha_k f_{idx_k} / sum_k alpha_k
+ *                         (0 where the opacities sum to <= 0)
+ * Slots with idx < 0 or idx >= P take no part.  weights (npix,K) float32
+ * holds the opacities, or, with RAST_COMPOSITE_FROM_DISTS or-ed into mode,
+ * the rasterizer's squared distances d, the opacity being
+ * alpha = 1 - d / radius^2 (radius > 0).  image (npix,D) is overwritten.
+ */
+#define RAST_COMPOSITE_ALPHA 0
+#define RAST_COMPOSITE_NORM 1
+#define RAST_COMPOSITE_FROM_DISTS 2
+#define RAST_COMPOSITE_DMAX 8
+int points_composite_fwd(const int32_t* idx, const float* weights, const float* features, int64_t P, int64_t npix,
+                         int K, int D, int mode, float radius, float* image, void* stream);
+
+/*
+ * Backward of points_composite_fwd for L = <grad_image, image>, with
+ * g_k = <grad_image, f_{idx_k}> and T_k = prod_{j<k} (1 - alpha_j):
+ *   ALPHA: dL/dalpha_k = T_k (g_k - R_k), R_k = sum_{i>k} alpha_i g_i prod_{k<j<i} (1 - alpha_j);
+ *          dL/df_{idx_k} += alpha_k T_k grad_image
+ *   NORM:  dL/dalpha_k = (g_k - <grad_image, image>) / S, S = sum_k alpha_k;
+ *          dL/df_{idx_k} += alpha_k grad_image / S   (nothing where S <= 0)
+ * grad_weights (npix,K) is overwritten with dL/dalpha_k, or dL/dd_k =
+ * -dL/dalpha_k / radius^2 in RAST_COMPOSITE_FROM_DISTS mode; 0 for slots that
+ * take no part.  grad_features (P,D) is overwritten, or NULL (not computed);
+ * its sums are formed with float atomics, so their rounding order varies.
+ */
+int points_composite_bwd(const int32_t* idx, const float* weights, const float* features, int64_t P, int64_t npix,
+                         int K, int D, int mode, float radius, const float* grad_image, float* grad_weights,
+                         float* grad_features, void* stream);
 
 #ifdef __cplusplus
 }

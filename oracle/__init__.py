@@ -229,6 +229,7 @@ def points_backward(points, image_size, idx, grad_zbuf=None, grad_dists=None, pi
     return out
 
 
-from .points import alpha_composite, alpha_composite_backward, norm_composite, norm_composite_backward  # noqa: E402,F401
+from .points import (alpha_composite, alpha_composite_backward, norm_composite,  # noqa: E402,F401
+                     norm_composite_backward, splat_alpha)
 from .blend import (iou_loss, silhouette_blend, silhouette_blend_backward, softmax_blend,  # noqa: E402,F401
                     softmax_blend_backward)

@@ -14,6 +14,16 @@ from __future__ import annotations
 import numpy as np
 
 
+def splat_alpha(idx, dists, radius):
+    """Opacity of a splat at squared distance d from its point (a reading: the
+    paper only says that it falls away from the centre): 1 - d / r^2, from 1
+    at the point to 0 at the rim; 0 for empty slots."""
+    idx = np.asarray(idx)
+    d = np.asarray(dists, np.float64)
+    r2 = float(radius) * float(radius)
+    return np.where(idx >= 0, 1.0 - d / r2, 0.0)
+
+
 def _gather(idx, features):
     idx = np.asarray(idx)
     feat = np.asarray(features, np.float64)

@@ -68,9 +68,15 @@ def lib() -> ctypes.CDLL:
         L.silhouette_blend_bwd.argtypes = [P, P, P, i64, ci, cf, P, P]
         L.softmax_blend_fwd.argtypes = [P, P, P, P, i64, ci, ci, cf, cf, cf, cf, P, P]
         L.softmax_blend_bwd.argtypes = [P, P, P, P, i64, ci, ci, cf, cf, cf, cf, P, P, P, P, P]
+        L.rast_points_workspace_size.argtypes = [ci, ci, ci, i64, ctypes.POINTER(sz)]
+        L.rasterize_points_fwd.argtypes = [P, i64, P, P, ci, ci, ci, cf, ci, P, P, P, P, sz, P]
+        L.rasterize_points_bwd.argtypes = [P, i64, P, P, ci, ci, ci, cf, ci, ci, P, P, P, P, P, sz, P]
+        L.points_composite_fwd.argtypes = [P, P, P, i64, i64, ci, ci, ci, cf, P, P]
+        L.points_composite_bwd.argtypes = [P, P, P, i64, i64, ci, ci, ci, cf, P, P, P, P]
         for fn in ("rast_workspace_size", "rasterize_meshes_fwd", "rasterize_meshes_bwd", "rast_bin_count",
                    "rast_query_status", "silhouette_blend_fwd", "silhouette_blend_bwd", "rast_set_kernel_events",
-                   "softmax_blend_fwd", "softmax_blend_bwd"):
+                   "softmax_blend_fwd", "softmax_blend_bwd", "rast_points_workspace_size", "rasterize_points_fwd",
+                   "rasterize_points_bwd", "points_composite_fwd", "points_composite_bwd"):
             getattr(L, fn).restype = ci
         _lib = L
         return L
@@ -78,9 +84,19 @@ def lib() -> ctypes.CDLL:
 
 EXPORTS = ("rast_workspace_size", "rasterize_meshes_fwd", "rasterize_meshes_bwd", "rast_bin_count",
            "rast_query_status", "rast_status_string", "silhouette_blend_fwd", "silhouette_blend_bwd",
-           "rast_set_kernel_events", "softmax_blend_fwd", "softmax_blend_bwd")
+           "rast_set_kernel_events", "softmax_blend_fwd", "softmax_blend_bwd", "rast_points_workspace_size",
+           "rasterize_points_fwd", "rasterize_points_bwd", "points_composite_fwd", "points_composite_bwd")
 RAST_KERNEL_FINE = 0
 RAST_KERNEL_BWD = 1
+RAST_KERNEL_POINTS_FINE = 2
+RAST_KERNEL_POINTS_BWD = 3
+RAST_POINTS_MAX = 1 << 30
+RAST_POINTS_MAX_SIDE = 16384
+RAST_POINTS_MAX_RADIUS = 2.0
+RAST_COMPOSITE_ALPHA = 0
+RAST_COMPOSITE_NORM = 1
+RAST_COMPOSITE_FROM_DISTS = 2
+RAST_COMPOSITE_DMAX = 8
 
 
 def status_string(code: int) -> str:
@@ -282,3 +298,93 @@ def softmax_blend_bwd(pix_to_face, zbuf, dists, colors, sigma, gamma, znear, zfa
            lib().softmax_blend_bwd(_p(pix_to_face), _p(zbuf), _p(dists), _p(colors), P, K, C, float(sigma),
                                    float(gamma), float(znear), float(zfar), _p(grad_image), _p(grad_zbuf),
                                    _p(grad_dists), _p(grad_colors), _stream(dev)))
+
+
+# ---------------------------------------------------------------------------
+# point clouds
+# ---------------------------------------------------------------------------
+def rast_points_workspace_size(N, H, W, P) -> int:
+    out = ctypes.c_size_t(0)
+    _check("rast_points_workspace_size",
+           lib().rast_points_workspace_size(int(N), int(H), int(W), int(P), ctypes.byref(out)))
+    return int(out.value)
+
+
+def _cloud_shapes(points, first_idx, num_points):
+    """Shapes of the packed point inputs; returns N."""
+    if points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError(f"points must be (P,3), got {tuple(points.shape)}")
+    if first_idx.dim() != 1 or tuple(num_points.shape) != tuple(first_idx.shape):
+        raise ValueError("cloud_to_first_idx and num_points_per_cloud must be (N,) each")
+    return first_idx.shape[0]
+
+
+def rasterize_points_fwd(points, first_idx, num_points, H, W, radius, K, idx, zbuf, dists, workspace):
+    dev = points.device
+    _require(points, "points", torch.float32, dev)
+    _require(first_idx, "cloud_to_first_idx", torch.int64, dev)
+    _require(num_points, "num_points_per_cloud", torch.int64, dev)
+    _require(idx, "idx", torch.int32, dev)
+    _require(zbuf, "zbuf", torch.float32, dev)
+    _require(dists, "dists", torch.float32, dev)
+    _require(workspace, "workspace", torch.uint8, dev)
+    N = _cloud_shapes(points, first_idx, num_points)
+    _same_shape("N,H,W,K", (N, int(H), int(W), int(K)), (idx, "idx"), (zbuf, "zbuf"), (dists, "dists"))
+    rc = lib().rasterize_points_fwd(_p(points), points.shape[0], _p(first_idx), _p(num_points), int(N), int(H),
+                                    int(W), float(radius), int(K), _p(idx), _p(zbuf), _p(dists), _p(workspace),
+                                    workspace.numel(), _stream(dev))
+    _check("rasterize_points_fwd", rc)
+
+
+def rasterize_points_bwd(points, first_idx, num_points, H, W, radius, K, flags, idx, grad_zbuf, grad_dists,
+                         grad_points, workspace):
+    dev = points.device
+    _require(points, "points", torch.float32, dev)
+    _require(first_idx, "cloud_to_first_idx", torch.int64, dev)
+    _require(num_points, "num_points_per_cloud", torch.int64, dev)
+    _require(idx, "idx", torch.int32, dev)
+    for t, n in ((grad_zbuf, "grad_zbuf"), (grad_dists, "grad_dists"), (grad_points, "grad_points")):
+        _require(t, n, torch.float32, dev)
+    _require(workspace, "workspace", torch.uint8, dev)
+    N = _cloud_shapes(points, first_idx, num_points)
+    _same_shape("N,H,W,K", (N, int(H), int(W), int(K)), (idx, "idx"), (grad_zbuf, "grad_zbuf"),
+                (grad_dists, "grad_dists"))
+    _same_shape("points", points.shape, (grad_points, "grad_points"))
+    rc = lib().rasterize_points_bwd(_p(points), points.shape[0], _p(first_idx), _p(num_points), int(N), int(H),
+                                    int(W), float(radius), int(K), int(flags), _p(idx), _p(grad_zbuf),
+                                    _p(grad_dists), _p(grad_points), _p(workspace), workspace.numel(), _stream(dev))
+    _check("rasterize_points_bwd", rc)
+
+
+def _composite_shapes(idx, weights, features, image):
+    _same_shape("idx", idx.shape, (weights, "weights"))
+    if features.dim() != 2:
+        raise ValueError(f"features must be (P,D), got {tuple(features.shape)}")
+    _same_shape("idx", tuple(idx.shape[:-1]) + (features.shape[1],), (image, "image"))
+    K = idx.shape[-1]
+    return idx.numel() // K if K else 0, K, features.shape[0], features.shape[1]
+
+
+def points_composite_fwd(idx, weights, features, mode, radius, image):
+    dev = idx.device
+    _require(idx, "idx", torch.int32, dev)
+    for t, n in ((weights, "weights"), (features, "features"), (image, "image")):
+        _require(t, n, torch.float32, dev)
+    npix, K, P, D = _composite_shapes(idx, weights, features, image)
+    _check("points_composite_fwd",
+           lib().points_composite_fwd(_p(idx), _p(weights), _p(features), P, npix, K, D, int(mode), float(radius),
+                                      _p(image), _stream(dev)))
+
+
+def points_composite_bwd(idx, weights, features, mode, radius, grad_image, grad_weights, grad_features):
+    dev = idx.device
+    _require(idx, "idx", torch.int32, dev)
+    for t, n in ((weights, "weights"), (features, "features"), (grad_image, "grad_image"),
+                 (grad_weights, "grad_weights"), (grad_features, "grad_features")):
+        _require(t, n, torch.float32, dev)
+    npix, K, P, D = _composite_shapes(idx, weights, features, grad_image)
+    _same_shape("idx", idx.shape, (grad_weights, "grad_weights"))
+    _same_shape("features", features.shape, (grad_features, "grad_features"))
+    _check("points_composite_bwd",
+           lib().points_composite_bwd(_p(idx), _p(weights), _p(features), P, npix, K, D, int(mode), float(radius),
+                                      _p(grad_image), _p(grad_weights), _p(grad_features), _stream(dev)))

@@ -19,7 +19,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librast.so")
-SOURCES = ["api.hip", "kernels_fwd.hip", "kernels_bwd.hip", "kernels_blend.hip"]
+SOURCES = ["api.hip", "kernels_fwd.hip", "kernels_bwd.hip", "kernels_blend.hip", "kernels_points.hip"]
 ARCH = "gfx950"
 
 

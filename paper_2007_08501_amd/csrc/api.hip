@@ -94,8 +94,8 @@ inline int hip_rc(hipError_t e) { return e == hipSuccess ? RAST_OK : RAST_EHIP; 
 
 // Instrumentation events of the calling host thread (rast_set_kernel_events).
 struct KernelEvents {
-    hipEvent_t begin[2] = {nullptr, nullptr};
-    hipEvent_t end[2] = {nullptr, nullptr};
+    hipEvent_t begin[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t end[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 thread_local KernelEvents tl_events;
 
@@ -203,7 +203,7 @@ int rasterize_meshes_bwd(const float* verts_packed, int64_t V, const int32_t* fa
 }
 
 int rast_set_kernel_events(int kernel, void* begin, void* end) {
-    if (kernel != RAST_KERNEL_FINE && kernel != RAST_KERNEL_BWD) return RAST_EINVAL;
+    if (kernel < RAST_KERNEL_FINE || kernel > RAST_KERNEL_POINTS_BWD) return RAST_EINVAL;
     if ((begin == nullptr) != (end == nullptr)) return RAST_EINVAL;
     tl_events.begin[kernel] = (hipEvent_t)begin;
     tl_events.end[kernel] = (hipEvent_t)end;
@@ -311,6 +311,140 @@ int softmax_blend_bwd(const int32_t* pix_to_face, const float* zbuf, const float
         return RAST_EINVAL;
     return hip_rc(rast::launch_softmax_bwd(pix_to_face, zbuf, dists, colors, P, K, C, sigma, gamma, znear, zfar,
                                            grad_image, grad_zbuf, grad_dists, grad_colors, (hipStream_t)stream));
+}
+
+// ---------------------------------------------------------------------------
+// Point clouds
+// ---------------------------------------------------------------------------
+namespace {
+
+struct PtLayout {
+    size_t hdr, start, bsum, home, rank, sorted, total;
+};
+
+bool make_pt_layout(int N, int H, int W, int64_t P, PtLayout* L) {
+    const int64_t T = (int64_t)N * ((H + rast::kTile - 1) / rast::kTile) * ((W + rast::kTile - 1) / rast::kTile);
+    if (T + 1 > INT32_MAX || P < 0 || P > RAST_POINTS_MAX) return false;
+    size_t off = 0;
+    L->hdr = off;
+    off += kAlign;
+    L->start = off;
+    off = align_up(off + (size_t)(T + 1) * 4);
+    L->bsum = off;
+    off = align_up(off + (size_t)(rast::pt_scan_blocks(T) + 1) * 4);
+    L->home = off;
+    off = align_up(off + (size_t)P * 4);
+    L->rank = off;
+    off = align_up(off + (size_t)P * 4);
+    L->sorted = off;
+    off = align_up(off + (size_t)P * 16);
+    L->total = off;
+    return true;
+}
+
+bool bad_points(int N, int H, int W, int K, int64_t P, float radius) {
+    if (bad_dims(N, H, W, K)) return true;
+    // pixel ranges of discs are conservative to well under 0.01 pixel up to this size
+    if (H > RAST_POINTS_MAX_SIDE || W > RAST_POINTS_MAX_SIDE) return true;
+    if (P < 0 || P > RAST_POINTS_MAX) return true;
+    if (!isfinite(radius) || !(radius >= 0.0f) || radius > RAST_POINTS_MAX_RADIUS) return true;
+    return false;
+}
+
+rast::BinSig pt_signature(int64_t P, int N, int H, int W, float radius) {
+    rast::BinSig g;
+    uint32_t rb;
+    memcpy(&rb, &radius, sizeof(rb));
+    const int w[rast::kSigWords] = {rast::kPtSigMarker, (int)P, N, H, W, (int)rb, 0, 0};
+    for (int i = 0; i < rast::kSigWords; ++i) g.w[i] = w[i];
+    return g;
+}
+
+}  // namespace
+
+int rast_points_workspace_size(int N, int H, int W, int64_t P, size_t* bytes_out) {
+    if (bytes_out == nullptr || N < 1 || H < 1 || W < 1) return RAST_EINVAL;
+    PtLayout L;
+    if (!make_pt_layout(N, H, W, P, &L)) return RAST_EINVAL;
+    *bytes_out = L.total;
+    return RAST_OK;
+}
+
+int rasterize_points_fwd(const float* points, int64_t P, const int64_t* cloud_to_first_idx,
+                         const int64_t* num_points_per_cloud, int N, int H, int W, float radius, int points_per_pixel,
+                         int32_t* idx, float* zbuf, float* dists, void* workspace, size_t workspace_bytes,
+                         void* stream) {
+    if (bad_points(N, H, W, points_per_pixel, P, radius)) return RAST_EINVAL;
+    if ((P > 0 && points == nullptr) || cloud_to_first_idx == nullptr || num_points_per_cloud == nullptr)
+        return RAST_EINVAL;
+    if (idx == nullptr || zbuf == nullptr || dists == nullptr) return RAST_EINVAL;
+    PtLayout L;
+    if (!make_pt_layout(N, H, W, P, &L)) return RAST_EINVAL;
+    if (workspace == nullptr || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < L.total)
+        return RAST_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    int* hdr = (int*)(ws + L.hdr);
+    if (rast::launch_header_init(hdr, pt_signature(P, N, H, W, radius), s) != hipSuccess) return RAST_EHIP;
+    return hip_rc(rast::launch_points_fwd(points, P, cloud_to_first_idx, num_points_per_cloud, N, H, W, radius,
+                                          points_per_pixel, hdr, (int*)(ws + L.start), (int*)(ws + L.bsum),
+                                          (int*)(ws + L.home), (int*)(ws + L.rank), (float4*)(ws + L.sorted), idx,
+                                          zbuf, dists, s, tl_events.begin[RAST_KERNEL_POINTS_FINE],
+                                          tl_events.end[RAST_KERNEL_POINTS_FINE]));
+}
+
+int rasterize_points_bwd(const float* points, int64_t P, const int64_t* cloud_to_first_idx,
+                         const int64_t* num_points_per_cloud, int N, int H, int W, float radius, int points_per_pixel,
+                         int flags, const int32_t* idx, const float* grad_zbuf, const float* grad_dists,
+                         float* grad_points, void* workspace, size_t workspace_bytes, void* stream) {
+    if (bad_points(N, H, W, points_per_pixel, P, radius)) return RAST_EINVAL;
+    if ((P > 0 && (points == nullptr || grad_points == nullptr)) || cloud_to_first_idx == nullptr ||
+        num_points_per_cloud == nullptr || idx == nullptr)
+        return RAST_EINVAL;
+    if ((flags & ~RAST_BWD_REUSE_FORWARD) != 0) return RAST_EINVAL;
+    PtLayout L;
+    if (!make_pt_layout(N, H, W, P, &L)) return RAST_EINVAL;
+    if (workspace == nullptr || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < L.total)
+        return RAST_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    return hip_rc(rast::launch_points_bwd(
+        points, P, cloud_to_first_idx, num_points_per_cloud, N, H, W, radius, points_per_pixel, idx, grad_zbuf,
+        grad_dists, grad_points, (int*)(ws + L.hdr), (int*)(ws + L.start), (int*)(ws + L.bsum), (int*)(ws + L.home),
+        (int*)(ws + L.rank), (float4*)(ws + L.sorted), (flags & RAST_BWD_REUSE_FORWARD) != 0,
+        pt_signature(P, N, H, W, radius), s, tl_events.begin[RAST_KERNEL_POINTS_BWD],
+        tl_events.end[RAST_KERNEL_POINTS_BWD]));
+}
+
+static bool bad_composite(int64_t P, int64_t npix, int K, int D, int mode, float radius) {
+    if (P < 0 || P > INT32_MAX || npix < 0 || K < 1 || K > RAST_KMAX || D < 1 || D > RAST_COMPOSITE_DMAX) return true;
+    if ((mode & ~(RAST_COMPOSITE_NORM | RAST_COMPOSITE_FROM_DISTS)) != 0) return true;
+    if (npix > ((int64_t)1 << 40) / K) return true;
+    if (mode & RAST_COMPOSITE_FROM_DISTS) {
+        if (!isfinite(radius) || !(radius > 0.0f)) return true;
+        if (!isfinite((float)(1.0 / ((double)radius * (double)radius)))) return true;
+    }
+    return false;
+}
+
+int points_composite_fwd(const int32_t* idx, const float* weights, const float* features, int64_t P, int64_t npix,
+                         int K, int D, int mode, float radius, float* image, void* stream) {
+    if (bad_composite(P, npix, K, D, mode, radius)) return RAST_EINVAL;
+    if (npix > 0 && (idx == nullptr || weights == nullptr || image == nullptr || (P > 0 && features == nullptr)))
+        return RAST_EINVAL;
+    return hip_rc(rast::launch_composite_fwd(idx, weights, features, P, npix, K, D, mode, radius, image,
+                                             (hipStream_t)stream));
+}
+
+int points_composite_bwd(const int32_t* idx, const float* weights, const float* features, int64_t P, int64_t npix,
+                         int K, int D, int mode, float radius, const float* grad_image, float* grad_weights,
+                         float* grad_features, void* stream) {
+    if (bad_composite(P, npix, K, D, mode, radius)) return RAST_EINVAL;
+    if (npix > 0 && (idx == nullptr || weights == nullptr || grad_image == nullptr || grad_weights == nullptr ||
+                     (P > 0 && features == nullptr)))
+        return RAST_EINVAL;
+    return hip_rc(rast::launch_composite_bwd(idx, weights, features, P, npix, K, D, mode, radius, grad_image,
+                                             grad_weights, grad_features, (hipStream_t)stream));
 }
 
 }  // extern "C"

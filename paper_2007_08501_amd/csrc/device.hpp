@@ -43,6 +43,7 @@ enum : int { kStatOverflow = 1, kStatMesh = 2, kStatReuse = 4 };
 // the bit pattern of the blur radius.
 constexpr int kSigWords = 8;
 constexpr int kSigMarker = 0x52535447;
+constexpr int kPtSigMarker = 0x50545347;  // point-cloud workspaces
 struct BinSig {
     int w[kSigWords];
 };
@@ -372,5 +373,35 @@ struct TopK {
         }
     }
 };
+
+// Largest value of v over the wave.
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+// element e of a pass that stages `per` values per pixel: pixel e / per
+__device__ __forceinline__ int stage_pixel(int e, float inv_per) { return (int)(((float)e + 0.5f) * inv_per); }
+
+// Pixels of the 8x8 tile (x0, y0) whose centres the box [bb.x, bb.y] x
+// [bb.z, bb.w] may contain, from the same conservative pixel ranges as the
+// binning (an empty box gives 0).
+__device__ __forceinline__ uint64_t tile_mask(const float4 bb, int H, int W, int x0, int y0, float tx_lo, float tx_hi,
+                                              float ty_lo, float ty_hi) {
+    // most faces of a single-pass tile miss it: reject those on the box alone
+    if (bb.y < tx_lo || bb.x > tx_hi || bb.w < ty_lo || bb.z > ty_hi) return 0ull;
+    int c0, c1, r0, r1;
+    pix_range(bb.x, bb.y, W, c0, c1);
+    pix_range(bb.z, bb.w, H, r0, r1);
+    c0 = max(c0 - x0, 0);
+    c1 = min(c1 - x0, kTile - 1);
+    r0 = max(r0 - y0, 0);
+    r1 = min(r1 - y0, kTile - 1);
+    if (c1 < c0 || r1 < r0) return 0ull;
+    const uint64_t cols = (uint64_t)((0xffu >> (kTile - 1 - (c1 - c0))) << c0) * 0x0101010101010101ull;
+    const uint64_t rows = (~0ull >> (8 * (kTile - 1 - r1))) & (~0ull << (8 * r0));
+    return cols & rows;
+}
 
 }  // namespace rast

@@ -221,33 +221,6 @@ struct TileLds {
     unsigned char lst[kChunk * 64];  // entry i of lane l at [i * 64 + l]
 };
 
-// Pixels of the 8x8 tile (x0, y0) whose centres the box [bb.x, bb.y] x
-// [bb.z, bb.w] may contain, from the same conservative pixel ranges as the
-// binning (an empty box gives 0).
-__device__ __forceinline__ uint64_t tile_mask(const float4 bb, int H, int W, int x0, int y0, float tx_lo, float tx_hi,
-                                              float ty_lo, float ty_hi) {
-    // most faces of a single-pass tile miss it: reject those on the box alone
-    if (bb.y < tx_lo || bb.x > tx_hi || bb.w < ty_lo || bb.z > ty_hi) return 0ull;
-    int c0, c1, r0, r1;
-    pix_range(bb.x, bb.y, W, c0, c1);
-    pix_range(bb.z, bb.w, H, r0, r1);
-    c0 = max(c0 - x0, 0);
-    c1 = min(c1 - x0, kTile - 1);
-    r0 = max(r0 - y0, 0);
-    r1 = min(r1 - y0, kTile - 1);
-    if (c1 < c0 || r1 < r0) return 0ull;
-    const uint64_t cols = (uint64_t)((0xffu >> (kTile - 1 - (c1 - c0))) << c0) * 0x0101010101010101ull;
-    const uint64_t rows = (~0ull >> (8 * (kTile - 1 - r1))) & (~0ull << (8 * r0));
-    return cols & rows;
-}
-
-// Largest value of v over the wave.
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return v;
-}
-
 // Writes the tile's fragments from the per-lane queues.  Values are staged in
 // LDS per pixel and then stored by consecutive lanes to consecutive
 // addresses, so every store instruction writes whole contiguous runs (one
@@ -258,9 +231,6 @@ __device__ __forceinline__ int wave_max(int v) {
 // distances are recomputed from the face records.
 constexpr int kStageG1 = 16;  // slots per pass for ids and depths
 constexpr int kStageG2 = 8;   // slots per pass for barycentrics and distances
-
-// element e of a pass that stages `per` values per pixel: pixel e / per
-__device__ __forceinline__ int stage_pixel(int e, float inv_per) { return (int)(((float)e + 0.5f) * inv_per); }
 
 // EXACT: K equals the bucket size KB, so every group width, stride and index
 // below is a compile-time constant (the common case); otherwise K < KB is a
@@ -430,7 +400,6 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
     const int lane = threadIdx.x & 63;
     const int r = ty * kTile + (lane >> 3);
     const int c = tx * kTile + (lane & 7);
-    const bool live = (r < a.H) && (c < a.W);
     const Pix p = make_pix(r, c, a.H, a.W);
     // extent of the tile's pixel centres (x decreases with c, y with r), less a
     // margin so that the float test never rejects what the pixel ranges keep

@@ -156,3 +156,73 @@ def test_softmax_blend_rejects_bad_arguments():
     bad = list(gb)
     bad[4], bad[11] = 10, None
     assert L.softmax_blend_bwd(*bad) == _lib.RAST_EINVAL
+
+
+def test_points_workspace_size():
+    L = _lib.lib()
+    out = ctypes.c_size_t(0)
+    assert L.rast_points_workspace_size(8, 256, 256, 1600000, ctypes.byref(out)) == _lib.RAST_OK
+    assert out.value >= 1600000 * 24 + 8 * 1024 * 4
+    small = out.value
+    assert L.rast_points_workspace_size(8, 256, 256, 100, ctypes.byref(out)) == _lib.RAST_OK
+    assert out.value < small
+    assert L.rast_points_workspace_size(0, 256, 256, 100, ctypes.byref(out)) == _lib.RAST_EINVAL
+    assert L.rast_points_workspace_size(1, 256, 256, -1, ctypes.byref(out)) == _lib.RAST_EINVAL
+    assert L.rast_points_workspace_size(1, 256, 256, (1 << 30) + 1, ctypes.byref(out)) == _lib.RAST_EINVAL
+    assert L.rast_points_workspace_size(1, 256, 256, 10, None) == _lib.RAST_EINVAL
+
+
+def pfwd(**kw):
+    a = dict(pts=FAKE, P=10, first=FAKE, num=FAKE, N=1, H=8, W=8, r=0.1, K=4, idx=FAKE, zbuf=FAKE, dists=FAKE,
+             ws=None, wsb=0, stream=None)
+    a.update(kw)
+    return _lib.lib().rasterize_points_fwd(a["pts"], a["P"], a["first"], a["num"], a["N"], a["H"], a["W"], a["r"],
+                                           a["K"], a["idx"], a["zbuf"], a["dists"], a["ws"], a["wsb"], a["stream"])
+
+
+@pytest.mark.parametrize("kw", [
+    dict(N=0), dict(H=0), dict(W=-1), dict(K=0), dict(K=65), dict(r=-0.1), dict(r=float("nan")),
+    dict(r=float("inf")), dict(r=2.5), dict(P=-1), dict(P=(1 << 30) + 1), dict(H=16385), dict(W=20000),
+    dict(pts=None), dict(first=None), dict(num=None), dict(idx=None), dict(zbuf=None), dict(dists=None),
+])
+def test_points_forward_rejects_bad_arguments(kw):
+    assert pfwd(**kw) == _lib.RAST_EINVAL
+
+
+def test_points_forward_and_backward_reject_bad_workspace():
+    assert pfwd() == _lib.RAST_EWORKSPACE
+    assert pfwd(ws=ctypes.c_void_p(0x1001), wsb=1 << 20) == _lib.RAST_EWORKSPACE
+    assert pfwd(ws=ctypes.c_void_p(0x1000), wsb=64) == _lib.RAST_EWORKSPACE
+    L = _lib.lib()
+    # points, P, first, num, N, H, W, r, K, flags, idx, gz, gd, grad, ws, wsb, stream
+    args = [FAKE, 10, FAKE, FAKE, 1, 8, 8, 0.1, 4, 0, FAKE, None, None, FAKE, None, 0, None]
+    assert L.rasterize_points_bwd(*args) == _lib.RAST_EWORKSPACE
+    for i, v in ((9, 2), (9, -1), (10, None), (13, None), (0, None), (7, -1.0), (8, 0), (2, None)):
+        bad = list(args)
+        bad[i] = v
+        assert L.rasterize_points_bwd(*bad) == _lib.RAST_EINVAL, i
+
+
+def test_points_composite_rejects_bad_arguments():
+    L = _lib.lib()
+    # idx, weights, features, P, npix, K, D, mode, radius, image, stream
+    good = [FAKE, FAKE, FAKE, 10, 0, 4, 3, 0, 0.0, FAKE, None]
+    assert L.points_composite_fwd(*good) == _lib.RAST_OK  # no pixels: nothing to launch
+    for i, v in ((5, 0), (5, 65), (6, 0), (6, 9), (7, 4), (7, -1), (3, -1), (4, -1)):
+        bad = list(good)
+        bad[i] = v
+        assert L.points_composite_fwd(*bad) == _lib.RAST_EINVAL, i
+    fd = list(good)
+    fd[7] = _lib.RAST_COMPOSITE_FROM_DISTS  # needs a positive radius
+    assert L.points_composite_fwd(*fd) == _lib.RAST_EINVAL
+    fd[8] = 0.01
+    assert L.points_composite_fwd(*fd) == _lib.RAST_OK
+    bad = list(good)
+    bad[4], bad[0] = 10, None
+    assert L.points_composite_fwd(*bad) == _lib.RAST_EINVAL
+    # bwd: ..., grad_image, grad_weights, grad_features (may be NULL), stream
+    gb = good[:9] + [FAKE, FAKE, None, None]
+    assert L.points_composite_bwd(*gb) == _lib.RAST_OK
+    bad = list(gb)
+    bad[4], bad[10] = 10, None
+    assert L.points_composite_bwd(*bad) == _lib.RAST_EINVAL

@@ -1,0 +1,372 @@
+"""GPU parity of the point-cloud renderer (paper, Section 3.3) against the
+FP64 oracle, through the C ABI.
+
+The coverage decision and the squared distance are evaluated in FP64 in the
+same operations on both sides, so idx and zbuf must match exactly and dists
+must equal the oracle's FP64 value rounded to float32.  Gradients and
+compositing are FP32/FP64 mixtures and are compared under the tolerances
+below.  Small cases are compared in full; the full-size workload (8 clouds x
+200,000 points, 256 x 256, K = 50) on seeded pixel and point samples, plus
+invariants.  The oracle never takes an input produced by the GPU.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2007_08501_amd import _lib, meshgen
+from paper_2007_08501_amd import points as pts_mod
+
+from _util import log, threads
+
+pytestmark = pytest.mark.gpu
+
+# compositing: sums of at most 64 FP32 terms, each bounded by the reference scale
+TOL_COMP = 2e-5
+# point gradients: FP64 sums of FP32 inputs, rounded once to FP32
+TOL_PGRAD = 1e-5
+
+
+def dev_cloud(b, dev="cuda"):
+    return (torch.from_numpy(b.points).to(dev), torch.from_numpy(b.first_idx).to(dev),
+            torch.from_numpy(b.num_points).to(dev))
+
+
+def run_pfwd(pts, first, num, H, W, radius, K, check=True):
+    N = first.shape[0]
+    dev = pts.device
+    idx = torch.empty((N, H, W, K), dtype=torch.int32, device=dev)
+    zbuf = torch.empty((N, H, W, K), dtype=torch.float32, device=dev)
+    dists = torch.empty_like(zbuf)
+    ws = _lib.alloc_workspace(_lib.rast_points_workspace_size(N, H, W, pts.shape[0]), dev)
+    _lib.rasterize_points_fwd(pts, first, num, H, W, radius, K, idx, zbuf, dists, ws)
+    if check:
+        st, _ = _lib.rast_query_status(ws)
+        assert st == _lib.RAST_OK, _lib.status_string(st)
+    return idx, zbuf, dists, ws
+
+
+def oracle_pfwd(points, first, num, H, W, radius, K, pixels=None):
+    return oracle.rasterize_points(points, first, num, (H, W), radius, K, pixels=pixels, nthreads=threads())
+
+
+def assert_frag_exact(idx, zbuf, dists, o, tag):
+    i = idx.cpu().numpy().astype(np.int64) if torch.is_tensor(idx) else idx
+    z = zbuf.cpu().numpy() if torch.is_tensor(zbuf) else zbuf
+    d = dists.cpu().numpy() if torch.is_tensor(dists) else dists
+    i = i.reshape(o["idx"].shape)
+    bad = np.argwhere(i != o["idx"])
+    assert bad.size == 0, f"{tag}: idx differs at {bad[:5].tolist()}: gpu {i[tuple(bad[0])]} oracle {o['idx'][tuple(bad[0])]}"
+    np.testing.assert_array_equal(z.reshape(o["zbuf"].shape), o["zbuf"].astype(np.float32), err_msg=tag + " zbuf")
+    np.testing.assert_array_equal(d.reshape(o["dists"].shape), o["dists"].astype(np.float32), err_msg=tag + " dists")
+
+
+def check_case(points, first, num, H, W, radius, K, tag):
+    p = torch.from_numpy(np.ascontiguousarray(points, np.float32)).cuda()
+    f = torch.from_numpy(np.asarray(first, np.int64)).cuda()
+    n = torch.from_numpy(np.asarray(num, np.int64)).cuda()
+    radius = float(np.float32(radius))
+    log(tag, "P", p.shape[0], "HW", H, W, "r", radius, "K", K)
+    idx, zbuf, dists, _ = run_pfwd(p, f, n, H, W, radius, K)
+    o = oracle_pfwd(np.asarray(points, np.float32), first, num, H, W, radius, K)
+    assert_frag_exact(idx, zbuf, dists, o, tag)
+    return o
+
+
+# ----------------------------------------------------------------- forward
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_points_small_configs_exact(cfg):
+    b = meshgen.make_points_config(cfg)
+    o = check_case(b.points, b.first_idx, b.num_points, *b.image_size, b.radius, b.points_per_pixel, f"pts{cfg}")
+    assert (o["idx"] >= 0).sum() > 1000
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 4, 5, 8, 13, 16, 31, 32, 50, 64])
+def test_points_K_sweep_ragged_image(K):
+    b = meshgen.make_points_config(2, image_override=40)
+    # a ragged image: neither side a multiple of the 8x8 tile
+    check_case(b.points, b.first_idx, b.num_points, 37, 53, b.radius * 2, K, f"K{K}")
+
+
+def test_points_unaligned_outputs_match_aligned():
+    b = meshgen.make_points_config(1)
+    p, f, n = dev_cloud(b)
+    H, W = b.image_size
+    K = 8
+    idx, zbuf, dists, _ = run_pfwd(p, f, n, H, W, b.radius, K)
+    shp = (1, H, W, K)
+    big_i = torch.empty(idx.numel() + 1, dtype=torch.int32, device="cuda")
+    big_z = torch.empty(idx.numel() + 1, dtype=torch.float32, device="cuda")
+    big_d = torch.empty(idx.numel() + 1, dtype=torch.float32, device="cuda")
+    ui, uz, ud = big_i[1:].view(shp), big_z[1:].view(shp), big_d[1:].view(shp)
+    ws = _lib.alloc_workspace(_lib.rast_points_workspace_size(1, H, W, p.shape[0]), "cuda")
+    _lib.rasterize_points_fwd(p, f, n, H, W, b.radius, K, ui, uz, ud, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(ui, idx) and torch.equal(uz, zbuf) and torch.equal(ud, dists)
+
+
+def test_points_edge_cases():
+    rng = np.random.default_rng(11)
+    H = W = 16
+    # empty cloud between two clouds, points behind the camera, off-image points
+    a = np.c_[rng.uniform(-0.9, 0.9, (50, 2)), rng.uniform(0.5, 2.0, 50)]
+    behind = np.c_[rng.uniform(-0.9, 0.9, (20, 2)), -rng.uniform(0.1, 1.0, 20)]
+    off = np.c_[rng.uniform(1.2, 3.0, (20, 2)), rng.uniform(0.5, 2.0, 20)]
+    pts = np.concatenate([a, behind, off]).astype(np.float32)
+    check_case(pts, [0, 50, 50], [50, 0, 40], H, W, 0.2, 6, "empty/behind/off")
+    # radius 0 covers nothing
+    o = check_case(pts, [0], [90], H, W, 0.0, 4, "radius0")
+    assert (o["idx"] < 0).all()
+    # coincident points at equal depth: ties by index; z exactly 0 counts
+    c = np.array([[1 - 7 / 16, 1 - 5 / 16, 1.0]] * 5 + [[1 - 7 / 16, 1 - 5 / 16, 0.0]], np.float32)
+    o = check_case(c, [0], [6], H, W, 0.1, 8, "ties")
+    assert list(o["idx"][0, 2, 3, :7]) == [5, 0, 1, 2, 3, 4, -1]
+    # a very large radius: every point covers most pixels (many batches per tile)
+    check_case(pts[:50], [0], [50], 24, 24, 1.9, 64, "radius1.9")
+    # points outside every cloud are ignored
+    check_case(pts, [10], [30], H, W, 0.2, 4, "partial cloud")
+
+
+def test_points_zero_points():
+    p = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
+    f = torch.zeros(2, dtype=torch.int64, device="cuda")
+    n = torch.zeros(2, dtype=torch.int64, device="cuda")
+    idx, zbuf, dists, _ = run_pfwd(p, f, n, 9, 11, 0.1, 3)
+    assert (idx == -1).all() and (zbuf == -1).all() and (dists == -1).all()
+
+
+def test_points_bad_cloud_ranges_flagged():
+    b = meshgen.make_points_config(1)
+    p, _, _ = dev_cloud(b)
+    f = torch.tensor([0, 100], dtype=torch.int64, device="cuda")
+    n = torch.tensor([200, 10], dtype=torch.int64, device="cuda")  # overlapping ranges
+    _, _, _, ws = run_pfwd(p, f, n, 16, 16, 0.05, 2, check=False)
+    assert _lib.rast_query_status(ws)[0] == _lib.RAST_EMESH
+    n = torch.tensor([10, 10 ** 6], dtype=torch.int64, device="cuda")  # past the end
+    _, _, _, ws = run_pfwd(p, f, n, 16, 16, 0.05, 2, check=False)
+    assert _lib.rast_query_status(ws)[0] == _lib.RAST_EMESH
+
+
+def full_size_points(batch=0):
+    return meshgen.make_points_config(3, batch=batch)
+
+
+def test_points_full_size_sampled_and_invariants():
+    b = full_size_points()
+    H, W = b.image_size
+    K = b.points_per_pixel
+    p, f, n = dev_cloud(b)
+    log("pts3 full size", p.shape[0], H, W, K)
+    idx, zbuf, dists, _ = run_pfwd(p, f, n, H, W, b.radius, K)
+    torch.cuda.synchronize()
+    # invariants over every pixel
+    valid = idx >= 0
+    assert not (valid[..., 1:] & ~valid[..., :-1]).any()
+    both = valid[..., 1:] & valid[..., :-1]
+    assert (zbuf[..., 1:] >= zbuf[..., :-1])[both].all()
+    assert (dists[valid] < b.radius ** 2 * (1 + 1e-6)).all() and (dists[valid] >= 0).all()
+    lo = f.view(-1, 1, 1, 1)
+    hi = lo + n.view(-1, 1, 1, 1)
+    i64 = idx.long()
+    assert (((i64 >= lo) & (i64 < hi)) | ~valid).all()
+    filled = valid.sum(-1).float()
+    log("pts3 filled slots per covered pixel", float(filled[filled > 0].mean()), "full pixels",
+        int((filled == K).sum()))
+    # seeded pixel sample plus two whole tiles, exact against the oracle
+    rng = np.random.default_rng(b.seed + 1)
+    npx = b.N * H * W
+    pix = np.unique(np.concatenate([rng.integers(0, npx, 3000),
+                                    [3 * H * W + (128 + r) * W + 120 + c for r in range(8) for c in range(8)],
+                                    [6 * H * W + (64 + r) * W + 200 + c for r in range(8) for c in range(8)]]))
+    o = oracle_pfwd(b.points, b.first_idx, b.num_points, H, W, b.radius, K, pixels=pix)
+    sel = torch.from_numpy(pix).cuda()
+    assert_frag_exact(idx.view(-1, K)[sel], zbuf.view(-1, K)[sel], dists.view(-1, K)[sel], o, "pts3 sample")
+    assert (o["idx"] >= 0).sum() > 10000
+
+
+# ----------------------------------------------------------------- backward
+
+def run_pbwd(pts, first, num, H, W, radius, K, idx, gz, gd, ws, flags=0):
+    grad = torch.empty_like(pts)
+    _lib.rasterize_points_bwd(pts, first, num, H, W, radius, K, flags, idx, gz, gd, grad, ws)
+    return grad
+
+
+def assert_grad_close(g, ref, tag):
+    g = g.cpu().numpy().astype(np.float64) if torch.is_tensor(g) else g
+    scale = max(float(np.abs(ref).max()), 1e-30)
+    err = np.abs(g - ref)
+    bound = TOL_PGRAD * scale + 1e-6 * np.abs(ref)
+    assert (err <= bound).all(), f"{tag}: max err {err.max():.3g} scale {scale:.3g}"
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_points_backward_full(cfg):
+    b = meshgen.make_points_config(cfg)
+    H, W = b.image_size
+    K = b.points_per_pixel
+    p, f, n = dev_cloud(b)
+    idx, _, _, ws = run_pfwd(p, f, n, H, W, b.radius, K)
+    gz, gd, _, _ = meshgen.point_grads(b)
+    gz_t, gd_t = torch.from_numpy(gz).cuda(), torch.from_numpy(gd).cuda()
+    g_reuse = run_pbwd(p, f, n, H, W, b.radius, K, idx, gz_t, gd_t, ws, _lib.RAST_BWD_REUSE_FORWARD)
+    st, _ = _lib.rast_query_status(ws)
+    assert st == _lib.RAST_OK
+    ws2 = _lib.alloc_workspace(_lib.rast_points_workspace_size(b.N, H, W, p.shape[0]), "cuda")
+    g_fresh = run_pbwd(p, f, n, H, W, b.radius, K, idx, gz_t, gd_t, ws2, 0)
+    torch.cuda.synchronize()
+    # every point's gradient is one thread's fixed-order sum: bitwise reproducible
+    assert torch.equal(g_reuse, g_fresh)
+    o = oracle_pfwd(b.points, b.first_idx, b.num_points, H, W, b.radius, K)
+    ref = oracle.points_backward(b.points, (H, W), o["idx"], gz, gd, nthreads=threads())
+    log(f"pts{cfg} bwd |ref| max", float(np.abs(ref).max()))
+    assert_grad_close(g_reuse, ref, f"pts{cfg} bwd")
+    # each upstream gradient alone
+    g_z = run_pbwd(p, f, n, H, W, b.radius, K, idx, gz_t, None, ws2)
+    g_d = run_pbwd(p, f, n, H, W, b.radius, K, idx, None, gd_t, ws2)
+    assert_grad_close(g_z, oracle.points_backward(b.points, (H, W), o["idx"], gz, None, nthreads=threads()), "gz")
+    assert_grad_close(g_d, oracle.points_backward(b.points, (H, W), o["idx"], None, gd, nthreads=threads()), "gd")
+    assert (g_z[:, :2] == 0).all() and (g_d[:, 2] == 0).all()
+
+
+def test_points_backward_reuse_mismatch_flagged():
+    b = meshgen.make_points_config(1)
+    H, W = b.image_size
+    p, f, n = dev_cloud(b)
+    idx, _, _, ws = run_pfwd(p, f, n, H, W, b.radius, 4)
+    gz = torch.ones((1, H, W, 4), dtype=torch.float32, device="cuda")
+    # a different radius than the forward that filled the workspace
+    g = run_pbwd(p, f, n, H, W, b.radius * 2, 4, idx, gz, None, ws, _lib.RAST_BWD_REUSE_FORWARD)
+    assert _lib.rast_query_status(ws)[0] == _lib.RAST_EREUSE
+    assert (g == 0).all()
+
+
+def test_points_backward_full_size_sampled():
+    b = full_size_points(batch=1)
+    H, W = b.image_size
+    K = b.points_per_pixel
+    p, f, n = dev_cloud(b)
+    idx, _, _, ws = run_pfwd(p, f, n, H, W, b.radius, K)
+    gz, gd, _, _ = meshgen.point_grads(b)
+    g = run_pbwd(p, f, n, H, W, b.radius, K, idx, torch.from_numpy(gz).cuda(), torch.from_numpy(gd).cuda(), ws,
+                 _lib.RAST_BWD_REUSE_FORWARD).cpu().numpy().astype(np.float64)
+    # sampled points: the oracle rasterizes every pixel of their discs' boxes,
+    # which holds every slot they can occupy, and differentiates those rows
+    rng = np.random.default_rng(b.seed + 2)
+    sample = rng.choice(b.points.shape[0], 300, replace=False)
+    rpix = 1.0 / W
+    pix = set()
+    for q in sample:
+        x, y = float(b.points[q, 0]), float(b.points[q, 1])
+        cloud = int(np.searchsorted(b.first_idx, q, side="right") - 1)
+        c_lo = int(np.floor(((1 - x - b.radius) * W - 1) / 2)) - 1
+        c_hi = int(np.ceil(((1 - x + b.radius) * W - 1) / 2)) + 1
+        r_lo = int(np.floor(((1 - y - b.radius) * H - 1) / 2)) - 1
+        r_hi = int(np.ceil(((1 - y + b.radius) * H - 1) / 2)) + 1
+        for r in range(max(r_lo, 0), min(r_hi, H - 1) + 1):
+            for c in range(max(c_lo, 0), min(c_hi, W - 1) + 1):
+                pix.add(cloud * H * W + r * W + c)
+    del rpix
+    pix = np.array(sorted(pix), np.int64)
+    o = oracle_pfwd(b.points, b.first_idx, b.num_points, H, W, b.radius, K, pixels=pix)
+    ref = oracle.points_backward(b.points, (H, W), o["idx"], gz.reshape(-1, K)[pix], gd.reshape(-1, K)[pix],
+                                 pixels=pix, N=b.N, nthreads=threads())
+    assert np.abs(ref[sample]).max() > 0
+    assert_grad_close(g[sample], ref[sample], "pts3 sampled bwd")
+
+
+# ----------------------------------------------------------------- compositing
+
+def composite_inputs(D, from_dists):
+    b = meshgen.make_points_config(2, image_override=48)
+    H, W = b.image_size
+    K = b.points_per_pixel
+    o = oracle_pfwd(b.points, b.first_idx, b.num_points, H, W, b.radius, K)
+    rng = np.random.default_rng(b.seed + 3)
+    feat = rng.uniform(size=(b.points.shape[0], D)).astype(np.float32)
+    gimg = rng.standard_normal((b.N, H, W, D)).astype(np.float32)
+    idx = o["idx"]
+    d32 = o["dists"].astype(np.float32)
+    if from_dists:
+        w = d32
+        alpha = oracle.splat_alpha(idx, d32, b.radius)
+    else:
+        w = np.where(idx >= 0, rng.uniform(size=idx.shape), 0.0).astype(np.float32)
+        w[..., 0] = np.where(idx[..., 0] >= 0, 1.0, 0.0)  # some fully opaque first slots
+        w[::2, ::3, ::5, 0] = 0.5
+        alpha = w.astype(np.float64)
+    return b, idx, w, alpha, feat, gimg
+
+
+@pytest.mark.parametrize("norm", [False, True])
+@pytest.mark.parametrize("from_dists", [False, True])
+@pytest.mark.parametrize("D", [1, 3, 8])
+def test_composite_parity(norm, from_dists, D):
+    b, idx, w, alpha, feat, gimg = composite_inputs(D, from_dists)
+    mode = (_lib.RAST_COMPOSITE_NORM if norm else 0) | (_lib.RAST_COMPOSITE_FROM_DISTS if from_dists else 0)
+    log("composite", "norm" if norm else "alpha", "dists" if from_dists else "alphas", "D", D)
+    t_idx = torch.from_numpy(idx.astype(np.int32)).cuda()
+    t_w = torch.from_numpy(w).cuda()
+    t_f = torch.from_numpy(feat).cuda()
+    t_g = torch.from_numpy(gimg).cuda()
+    img = torch.empty(idx.shape[:-1] + (D,), dtype=torch.float32, device="cuda")
+    _lib.points_composite_fwd(t_idx, t_w, t_f, mode, b.radius, img)
+    gw = torch.empty_like(t_w)
+    gf = torch.empty_like(t_f)
+    _lib.points_composite_bwd(t_idx, t_w, t_f, mode, b.radius, t_g, gw, gf)
+    if norm:
+        ref = oracle.norm_composite(idx, alpha, feat)
+        ga, gfr = oracle.norm_composite_backward(idx, alpha, feat, gimg)
+    else:
+        ref = oracle.alpha_composite(idx, alpha, feat)
+        ga, gfr = oracle.alpha_composite_backward(idx, alpha, feat, gimg)
+    gwr = -ga / (float(b.radius) ** 2) if from_dists else ga
+    for got, want, tag in ((img, ref, "image"), (gw, gwr, "grad_weights"), (gf, gfr, "grad_features")):
+        g = got.cpu().numpy().astype(np.float64)
+        scale = max(1.0, float(np.abs(want).max())) if not (from_dists and tag == "grad_weights") else \
+            float(np.abs(want).max())
+        err = float(np.abs(g - want).max())
+        log(" ", tag, "max err", err, "scale", scale)
+        assert err <= TOL_COMP * scale * (4 if tag == "grad_features" else 1), tag
+
+
+def test_composite_without_feature_grad():
+    b, idx, w, alpha, feat, gimg = composite_inputs(3, False)
+    t_idx = torch.from_numpy(idx.astype(np.int32)).cuda()
+    t_w, t_f, t_g = (torch.from_numpy(a).cuda() for a in (w, feat, gimg))
+    gw = torch.empty_like(t_w)
+    _lib.points_composite_bwd(t_idx, t_w, t_f, 0, 0.0, t_g, gw, None)
+    ga, _ = oracle.alpha_composite_backward(idx, alpha, feat, gimg)
+    assert float(np.abs(gw.cpu().numpy() - ga).max()) <= TOL_COMP * max(1.0, float(np.abs(ga).max()))
+
+
+# ----------------------------------------------------------------- autograd
+
+@pytest.mark.parametrize("norm", [False, True])
+def test_points_render_autograd_chain(norm):
+    b = meshgen.make_points_config(1)
+    H, W = b.image_size
+    K = b.points_per_pixel
+    p, f, n = dev_cloud(b)
+    p.requires_grad_(True)
+    _, _, feat, gimg = meshgen.point_grads(b)
+    t_f = torch.from_numpy(feat).cuda().requires_grad_(True)
+    s = pts_mod.PointsRasterSettings(image_size=(H, W), radius=b.radius, points_per_pixel=K)
+    frags = pts_mod.rasterize_points(p, f, n, s)
+    img = pts_mod.splat_composite(frags.idx, frags.dists, t_f, b.radius, norm=norm)
+    (img * torch.from_numpy(gimg).cuda()).sum().backward()
+    # oracle chain: compositing backward -> dL/dd = -dL/dalpha / r^2 -> rasterizer backward
+    o = oracle_pfwd(b.points, b.first_idx, b.num_points, H, W, b.radius, K)
+    d32 = o["dists"].astype(np.float32)
+    alpha = oracle.splat_alpha(o["idx"], d32, b.radius)
+    bwd = oracle.norm_composite_backward if norm else oracle.alpha_composite_backward
+    ga, gfr = bwd(o["idx"], alpha, feat, gimg)
+    gd = np.where(o["idx"] >= 0, -ga / float(b.radius) ** 2, 0.0)
+    gpr = oracle.points_backward(b.points, (H, W), o["idx"], None, gd, nthreads=threads())
+    gp = p.grad.cpu().numpy().astype(np.float64)
+    err = np.abs(gp - gpr).max()
+    log("autograd chain grad_points max err", float(err), "scale", float(np.abs(gpr).max()))
+    # the FP32 dL/dd (scale 1/r^2) dominates the error
+    assert err <= 1e-4 * float(np.abs(gpr).max())
+    assert float(np.abs(t_f.grad.cpu().numpy() - gfr).max()) <= 4 * TOL_COMP * max(1.0, float(np.abs(gfr).max()))

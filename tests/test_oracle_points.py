@@ -173,3 +173,16 @@ def test_compositing_backward_fd(mode):
         fm[i] -= h
         fd = ((fwd(idx, a, fp) - fwd(idx, a, fm)) * g).sum() / (2 * h)
         assert abs(fd - gf[i]) < 1e-6 * max(1.0, abs(fd)), (i, fd, gf[i])
+
+
+def test_splat_alpha_closed_form():
+    idx = np.array([[3, 7, -1]])
+    r = 0.25
+    d = np.array([[0.0, r * r / 4, 0.5]])
+    a = oracle.splat_alpha(idx, d, r)
+    # opaque at the point, 3/4 at half the radius (d = r^2 / 4), nothing for an empty slot
+    np.testing.assert_allclose(a, [[1.0, 0.75, 0.0]], rtol=0, atol=1e-15)
+    # zero at the rim and linear in d in between
+    np.testing.assert_allclose(oracle.splat_alpha([[0]], [[r * r]], r), [[0.0]], atol=1e-15)
+    ds = np.linspace(0, r * r, 9)[None, :]
+    assert np.allclose(np.diff(oracle.splat_alpha(np.zeros_like(ds, int), ds, r)), -1 / 8)
