@@ -202,6 +202,167 @@ def cpu_baseline_leg(b, cpu_seconds, v, f, fi, nf, out, gz_np, gb_np, gd_np, bs,
     return cpu, parity
 
 
+POINTS_METRIC = "point-cloud render fwd+bwd ms/batch (rasterize + Alpha/Norm silhouette compositing)"
+POINTS_PAPER_MS = 75.0  # the paper's figure for this workload (V100); context, not a target
+
+
+def points_cpu_leg(b, cpu_seconds, idx, zbuf, dists, gd_np):
+    """The FP64 point oracle on a bounded seeded pixel sample, timed on the
+    host cores (brute-force forward over every point of the pixel's cloud and
+    the analytic backward of those slots), with the GPU fragments checked
+    against it, exactly, on the sample."""
+    import numpy as np
+    import torch
+
+    import oracle
+
+    N, (H, W), K = b.N, b.image_size, b.points_per_pixel
+    nthr = min(16, oracle.default_threads())
+    rng = np.random.default_rng(4321)
+    probe = np.sort(rng.choice(N * H * W, size=64, replace=False))
+    tq = time.perf_counter()
+    oracle.rasterize_points(b.points, b.first_idx, b.num_points, (H, W), b.radius, K, pixels=probe, nthreads=nthr)
+    per_px = (time.perf_counter() - tq) / probe.size
+    P = int(min(N * H * W, max(256, cpu_seconds / max(per_px, 1e-9))))
+    pix = np.sort(rng.choice(N * H * W, size=P, replace=False))
+    tq = time.perf_counter()
+    o = oracle.rasterize_points(b.points, b.first_idx, b.num_points, (H, W), b.radius, K, pixels=pix,
+                                nthreads=nthr)
+    t_f = time.perf_counter() - tq
+    tq = time.perf_counter()
+    oracle.points_backward(b.points, (H, W), o["idx"], None, gd_np.reshape(-1, K)[pix], pixels=pix, N=N,
+                           nthreads=nthr)
+    t_b = time.perf_counter() - tq
+    cpu = {"value": round(P * K / (t_f + t_b) / 1e6, 6), "unit": UNIT, "cores": nthr, "kind": "oracle",
+           "sample": f"{P} of {N * H * W} pixels (seeded uniform), FP64 brute force over every point of the "
+                     f"pixel's cloud + analytic backward of their slots; fwd {t_f:.2f}s, bwd {t_b:.2f}s"}
+    sel = torch.from_numpy(pix).to(idx.device)
+    gi = idx.view(-1, K)[sel].cpu().numpy().astype(np.int64)
+    gz = zbuf.view(-1, K)[sel].cpu().numpy()
+    gdd = dists.view(-1, K)[sel].cpu().numpy()
+    ok = bool((gi == o["idx"]).all() and (gz == o["zbuf"].astype(np.float32)).all()
+              and (gdd == o["dists"].astype(np.float32)).all())
+    return cpu, {"pixels": int(pix.size), "fragments_exact": ok}
+
+
+def points_main(args):
+    """--points: the point-cloud renderer at the paper's benchmark shape."""
+    import numpy as np
+    import torch
+
+    from paper_2007_08501_amd import _lib, meshgen
+    from paper_2007_08501_amd.graph import PointsGraphRunner
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ev = HipEvents()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    per_batch = []
+    keep = None
+    for batch in range(args.batch, args.batch + args.batches):
+        b = meshgen.make_points_config(3, batch=batch)
+        N, (H, W), K = b.N, b.image_size, b.points_per_pixel
+        t = lambda a: torch.from_numpy(a).to(dev)
+        gr = PointsGraphRunner(t(b.points), t(b.first_idx), t(b.num_points), H, W, b.radius, K, D=1,
+                               norm=args.norm)
+        _, gd_np, _, _ = meshgen.point_grads(b, channels=1)
+        rng = np.random.default_rng(b.seed + 9)
+        gr.set_grad_image(t(rng.standard_normal((N, H, W, 1)).astype(np.float32)))
+        gr.capture(warmup=2)
+        for _ in range(args.warmup):
+            gr.replay()
+        n = args.steps
+        e0, e1 = ev.create(), ev.create()
+        torch.cuda.synchronize()
+        ev.record(e0, stream)
+        for _ in range(n):
+            gr.replay()
+        ev.record(e1, stream)
+        torch.cuda.synchronize()
+        graph_ms = ev.elapsed(e0, e1) / n
+        st, _ = gr.status()
+        if st != _lib.RAST_OK:
+            log(f"[bench] device status: {_lib.status_string(st)}")
+            sys.exit(1)
+        # eager steps with the library's events around the per-tile and per-point kernels
+        kev = [[ev.create() for _ in range(8)] for _ in range(n)]
+        torch.cuda.synchronize()
+        for i in range(n):
+            k = kev[i]
+            _lib.rast_set_kernel_events(_lib.RAST_KERNEL_POINTS_FINE, k[0], k[1])
+            _lib.rast_set_kernel_events(_lib.RAST_KERNEL_POINTS_BWD, k[2], k[3])
+            ev.record(k[4], stream)
+            gr.forward_eager()
+            ev.record(k[5], stream)
+            gr.backward_eager()
+            ev.record(k[6], stream)
+        torch.cuda.synchronize()
+        _lib.rast_set_kernel_events(_lib.RAST_KERNEL_POINTS_FINE, None, None)
+        _lib.rast_set_kernel_events(_lib.RAST_KERNEL_POINTS_BWD, None, None)
+        r = dict(batch=batch, graph_ms=graph_ms,
+                 fine_ms=sum(ev.elapsed(k[0], k[1]) for k in kev) / n,
+                 bwd_ms=sum(ev.elapsed(k[2], k[3]) for k in kev) / n,
+                 fwd_call_ms=sum(ev.elapsed(k[4], k[5]) for k in kev) / n,
+                 bwd_call_ms=sum(ev.elapsed(k[5], k[6]) for k in kev) / n,
+                 valid=int((gr.idx >= 0).sum().item()))
+        for e in [e0, e1] + [x for k in kev for x in k]:
+            ev.destroy(e)
+        log(f"[bench] points batch {batch}: {graph_ms:.4f} ms/step graph-replayed; fine {r['fine_ms']:.4f}, "
+            f"point bwd {r['bwd_ms']:.4f}, fwd calls {r['fwd_call_ms']:.4f}, bwd calls {r['bwd_call_ms']:.4f} ms")
+        per_batch.append(r)
+        if keep is None:
+            keep = (b, gr, gd_np)
+        else:
+            del gr
+    b, gr, gd_np = keep
+    N, (H, W), K = b.N, b.image_size, b.points_per_pixel
+    P = b.points.shape[0]
+    S = N * H * W * K
+    ms_step = float(np.median([r["graph_ms"] for r in per_batch]))
+    med = lambda k: float(np.median([r[k] for r in per_batch]))
+    fine_ms, bwd_ms = med("fine_ms"), med("bwd_ms")
+    S_valid = per_batch[0]["valid"]
+    # algorithmic bytes: the fine pass writes three 4-byte outputs per slot and
+    # reads each sorted 16-byte point once; the point backward reads the id
+    # of every slot, the upstream gradient of each filled slot, each sorted
+    # point, and writes 12 bytes per point
+    fine_bytes = 12 * S + 16 * P
+    bwd_bytes = 4 * S + 4 * S_valid + 16 * P + 12 * P
+    kernels = {"points_fine": (fine_ms, fine_bytes), "points_backward": (bwd_ms, bwd_bytes)}
+    dom = max(kernels, key=lambda k: kernels[k][0])
+    dom_ms, dom_bytes = kernels[dom]
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel_ms": round(dom_ms, 5),
+                "algorithmic_bytes": dom_bytes}
+    cpu, parity = None, None
+    if not args.no_cpu_baseline:
+        cpu, parity = points_cpu_leg(b, args.cpu_seconds, gr.idx, gr.zbuf, gr.dists, gd_np)
+        log(f"[bench] cpu baseline {cpu}")
+        log(f"[bench] parity {parity}")
+    res = {
+        "metric": POINTS_METRIC, "value": round(ms_step, 5), "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": round(ms_step / POINTS_PAPER_MS, 6), "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"pts3: {meshgen.POINT_CONFIG_NAMES[3]}", "clouds": N, "points": P, "image": [H, W],
+                   "points_per_pixel": K, "radius": b.radius,
+                   "compositing": "Norm" if args.norm else "Alpha", "features": "silhouette (D=1, ones)",
+                   "parallelism": "single GPU"},
+        "throughput_mpixk_per_s": round(S / (ms_step * 1e-3) / 1e6, 2), "slots": S, "slots_valid": S_valid,
+        "kernels_ms": {"points_fine": round(fine_ms, 5), "points_backward": round(bwd_ms, 5),
+                       "forward_calls": round(med("fwd_call_ms"), 5), "backward_calls": round(med("bwd_call_ms"), 5)},
+        "timing": {"form": "fwd (rasterize + composite) and bwd (composite + rasterize) captured in one HIP graph "
+                           "and replayed; value is the median over seeded batches",
+                   "batches": [r["batch"] for r in per_batch],
+                   "ms_per_step_graph": [round(r["graph_ms"], 5) for r in per_batch]},
+        "paper_ms_v100": POINTS_PAPER_MS,
+        "roofline": roofline, "cpu_baseline": cpu, "parity": parity,
+    }
+    print(json.dumps(res), flush=True)
+    if parity is not None and not parity["fragments_exact"]:
+        sys.exit(3)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,12 +378,19 @@ def main():
     ap.add_argument("--no-per-mesh", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain streaming kernel of known size")
+    ap.add_argument("--points", action="store_true",
+                    help="benchmark the point-cloud renderer instead (8 clouds x 200k points, 256x256, K=50)")
+    ap.add_argument("--norm", action="store_true", help="--points: Norm compositing instead of Alpha")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: this rasterizer runs on one GPU; the batch would "
               "shard by image across GPUs but no multi-GPU path is built", file=sys.stderr)
         sys.exit(2)
+
+    if args.points:
+        points_main(args)
+        return
 
     import numpy as np
     import torch

@@ -1,14 +1,17 @@
 // kernels_points.hip -- point-cloud rasterizer and compositing for gfx950.
 //
-//   pt_count      one thread per point: cloud id, home tile, rank in that tile
+//   pt_count      cloud id, home tile and rank in that tile of every point
+//                 (counts gathered per block in LDS when the tiles fit)
 //   pt_scan_*     exclusive scan of the per-tile counts into tile starts
 //   pt_scatter    one thread per point: 16-byte record at its sorted slot
 //   pt_raster     one wave per 8x8 tile: candidates from the home lists of
 //                 the tiles that can reach it, cull, exact FP64 test per
 //                 pixel, K nearest along z in registers, write the fragments
-//   pt_bwd        one thread per sorted point: gathers the gradient of its
-//                 own slots from the pixels its disc covers (no atomics)
-//   composite     one thread per pixel: Alpha / Norm compositing, backward
+//   pt_bwd        one thread per sorted point, one workgroup per home tile:
+//                 gathers the gradient of the point's own slots from the
+//                 pixels its disc covers, staged in LDS (no atomics)
+//   composite     a pixel's slots over the lanes of a wave segment, four per
+//                 lane: Alpha / Norm compositing and its backward
 //
 // Paper, Section 3.3: every point is splatted to a disc of radius r in screen
 // space; each pixel keeps the K points nearest along z whose discs cover it,
@@ -44,6 +47,7 @@ struct PtArgs {
     float r;                // radius
     double r2;              // radius^2, FP64
     int tiles_x, tiles_y, rx, ry;
+    int span_x, span_y;     // pixel columns / rows a disc reaches past its first
     int64_t T;              // tiles in the batch
     int* hdr;
     int* start;             // T+1: counts, then tile starts
@@ -56,26 +60,72 @@ struct PtArgs {
     float* dists;
 };
 
-__global__ __launch_bounds__(256) void pt_count_kernel(PtArgs a) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < a.N) {
-        // cloud range check: inside [0, P] and ascending without overlap
-        const int64_t f = a.first[p], c = a.np[p];
-        bool bad = f < 0 || c < 0 || f + c > a.P;
-        if (p > 0) bad = bad || f < a.first[p - 1] + a.np[p - 1];
-        if (bad) atomicOr(&a.hdr[kHdrStatus], kStatMesh);
-    }
-    if (p >= a.P) return;
+// Home tile of point p, or -1 when it takes no part (outside every cloud,
+// behind the camera, or covering no pixel).
+__device__ __forceinline__ int pt_home(const PtArgs& a, int64_t p) {
     const int n = find_mesh(a.first, a.np, a.N, p);
     const float x = a.pts[3 * p], y = a.pts[3 * p + 1], z = a.pts[3 * p + 2];
-    int h = -1, rk = 0, c0, c1, r0, r1;
-    // points behind the camera or covering no pixel take no part
-    if (n >= 0 && z >= 0.0f && disc_pixels(x, y, a.r, a.H, a.W, c0, c1, r0, r1)) {
-        h = (int)(((int64_t)n * a.tiles_y + r0 / kTile) * a.tiles_x + c0 / kTile);
-        rk = atomicAdd(&a.start[h], 1);
-    }
+    int c0, c1, r0, r1;
+    if (n < 0 || !(z >= 0.0f) || !disc_pixels(x, y, a.r, a.H, a.W, c0, c1, r0, r1)) return -1;
+    return (int)(((int64_t)n * a.tiles_y + r0 / kTile) * a.tiles_x + c0 / kTile);
+}
+
+// cloud range check: inside [0, P] and ascending without overlap
+__device__ __forceinline__ void pt_check_cloud(const PtArgs& a, int64_t i) {
+    const int64_t f = a.first[i], c = a.np[i];
+    bool bad = f < 0 || c < 0 || f + c > a.P;
+    if (i > 0) bad = bad || f < a.first[i - 1] + a.np[i - 1];
+    if (bad) atomicOr(&a.hdr[kHdrStatus], kStatMesh);
+}
+
+// Counting, one thread per point: the rank of a point within its home tile is
+// the count before its own increment.
+__global__ __launch_bounds__(256) void pt_count_kernel(PtArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < a.N) pt_check_cloud(a, p);
+    if (p >= a.P) return;
+    const int h = pt_home(a, p);
     a.home[p] = h;
-    a.rank[p] = rk;
+    a.rank[p] = h >= 0 ? atomicAdd(&a.start[h], 1) : 0;
+}
+
+// The same with the counts of a block's points first gathered in an LDS
+// histogram of every tile of the batch (when they fit): one global atomic per
+// tile a block touches instead of one per point.  A point's rank is the
+// block's base for its tile plus its rank within the block.
+constexpr int kCountThreads = 1024;
+constexpr int kCountPer = 8;                  // points per thread
+constexpr int kCountLdsTiles = 16384;         // tiles the LDS histogram holds
+
+__global__ __launch_bounds__(kCountThreads) void pt_count_lds_kernel(PtArgs a) {
+    __shared__ int hist[kCountLdsTiles];
+    const int T = (int)a.T;
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < a.N; i += kCountThreads) pt_check_cloud(a, i);
+    for (int i = threadIdx.x; i < T; i += kCountThreads) hist[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kCountThreads * kCountPer + threadIdx.x;
+    int h[kCountPer], lr[kCountPer];
+#pragma unroll
+    for (int j = 0; j < kCountPer; ++j) {
+        const int64_t p = base + (int64_t)j * kCountThreads;
+        h[j] = p < a.P ? pt_home(a, p) : -1;
+        lr[j] = h[j] >= 0 ? atomicAdd(&hist[h[j]], 1) : 0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < T; i += kCountThreads) {
+        const int c = hist[i];
+        if (c > 0) hist[i] = atomicAdd(&a.start[i], c);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kCountPer; ++j) {
+        const int64_t p = base + (int64_t)j * kCountThreads;
+        if (p < a.P) {
+            a.home[p] = h[j];
+            a.rank[p] = h[j] >= 0 ? hist[h[j]] + lr[j] : 0;
+        }
+    }
 }
 
 // Exclusive scan of start[0, T) in place, start[T] = total, in three passes:
@@ -176,12 +226,21 @@ __global__ __launch_bounds__(256) void pt_scatter_kernel(PtArgs a) {
 // lists go through the register top-K eight keys at a time.
 // ---------------------------------------------------------------------------
 constexpr int kPtBatch = 128;
+constexpr int kPtLoads = 4;  // candidate chunks loaded at once
 static_assert(kPtBatch <= 256, "per-lane lists hold byte indices");
 
-struct PtLds {
+struct PtBatchLds {
     double2 xy[kPtBatch];
     uint64_t key[kPtBatch];                 // (z, id) sort key
     unsigned char lst[kPtBatch * 64];       // entry i of lane l at [i * 64 + l]
+};
+
+// The tile's LDS: the candidate batch, reused at the end to stage one output
+// array of the tile (64 pixels x K slots, pixel-major) for the row stores.
+template <int KB>
+union PtLds {
+    PtBatchLds b;
+    uint32_t stage[64 * KB];
 };
 
 __device__ __forceinline__ double pt_d2(double x, double y, double px, double py) {
@@ -190,7 +249,7 @@ __device__ __forceinline__ double pt_d2(double x, double y, double px, double py
 }
 
 template <int KB>
-__device__ __forceinline__ void pt_batch(const PtArgs& a, PtLds& L, TopK<KB>& top, int m, bool live, double px,
+__device__ __forceinline__ void pt_batch(const PtArgs& a, PtBatchLds& L, TopK<KB>& top, int m, bool live, double px,
                                          double py) {
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -210,92 +269,72 @@ __device__ __forceinline__ void pt_batch(const PtArgs& a, PtLds& L, TopK<KB>& to
     __syncthreads();
 }
 
-// Stores slots [g0, g0 + gw) of the tile's pixels from an LDS stage (pixel
-// major, stride G + 1) so that consecutive lanes write consecutive words.
-template <int G, bool V4, bool EXACT>
-__device__ __forceinline__ void pt_store(uint32_t* __restrict__ out, const uint32_t* st, int K, int rowK, int g0,
-                                         int gw, int rows, int cols) {
-    constexpr int S = G + 1;
+// Stores one staged output array of the tile: tile row r is the contiguous
+// run of cols * K words at out + r * W * K, staged at stage + r * 8 * K, and
+// is written by consecutive lanes, 16 bytes each when `vec` (full-width tile,
+// W * K a multiple of four, 16-byte aligned outputs).
+__device__ __forceinline__ void pt_store_rows(uint32_t* __restrict__ out, const uint32_t* stage, int K, int rowK,
+                                              int rows, int cols, bool vec) {
     const int lane = threadIdx.x & 63;
-    if constexpr (V4) {
-        constexpr int Q = G / 4;
-#pragma unroll
-        for (int e0 = 0; e0 < 64 * Q; e0 += 64) {
-            const int e = e0 + lane;
-            const int px = e / Q, q = e - px * Q;
-            const int r = px >> 3, c = px & 7;
-            if (r < rows && c < cols) {
-                const uint32_t* si = st + px * S + 4 * q;
-                *reinterpret_cast<uint4*>(out + r * rowK + c * K + g0 + 4 * q) = make_uint4(si[0], si[1], si[2], si[3]);
-            }
-        }
-    } else {
-        const float inv = 1.0f / (float)gw;
-#pragma unroll
-        for (int e0 = 0; e0 < 64 * G; e0 += 64) {
-            const int e = e0 + lane;
-            if (e >= 64 * gw) break;
-            const int px = EXACT ? e / gw : stage_pixel(e, inv);
-            const int k = e - px * gw;
-            const int r = px >> 3, c = px & 7;
-            if (r < rows && c < cols) out[r * rowK + c * K + g0 + k] = st[px * S + k];
+    const int nrow = cols * K;
+    for (int r = 0; r < rows; ++r) {
+        const uint32_t* src = stage + r * kTile * K;
+        uint32_t* dst = out + r * rowK;
+        if (vec) {
+            for (int e = 4 * lane; e < nrow; e += 256)
+                *reinterpret_cast<uint4*>(dst + e) = *reinterpret_cast<const uint4*>(src + e);
+        } else {
+            for (int e = lane; e < nrow; e += 64) dst[e] = src[e];
         }
     }
 }
 
+// Writes the tile's fragments: ids and depths from the keys, squared
+// distances recomputed in FP64 exactly as the test evaluated them.
 template <int KB, bool EXACT>
-__device__ __forceinline__ void pt_write(const PtArgs& a, PtLds& L, const TopK<KB>& top, double px, double py, int n,
-                                         int tx, int ty) {
+__device__ __forceinline__ void pt_write(const PtArgs& a, PtLds<KB>& L, const TopK<KB>& top, double px, double py,
+                                         int n, int tx, int ty, bool aligned) {
     const int lane = threadIdx.x & 63;
     const int K = EXACT ? KB : a.K;
     const int rows = min(kTile, a.H - ty * kTile), cols = min(kTile, a.W - tx * kTile);
     const int64_t pix0 = ((int64_t)n * a.H + ty * kTile) * a.W + tx * kTile;
     const int rowK = a.W * K;
-    constexpr bool V4 = EXACT && (KB % 4 == 0);
-    constexpr int G = KB < 16 ? KB : 16;
-    constexpr int S = G + 1;
-    static_assert(sizeof(PtLds) >= sizeof(uint32_t) * 64 * S * 2, "staging exceeds the tile LDS");
-    uint32_t* const idx_t = reinterpret_cast<uint32_t*>(a.idx + pix0 * K);
-    uint32_t* const z_t = reinterpret_cast<uint32_t*>(a.zbuf + pix0 * K);
-    uint32_t* const d_t = reinterpret_cast<uint32_t*>(a.dists + pix0 * K);
-    uint32_t* sid = reinterpret_cast<uint32_t*>(&L);
-    uint32_t* sz = sid + 64 * S;
+    const bool vec = aligned && cols == kTile && (rowK & 3) == 0;
+    uint32_t* st = L.stage + lane * K;
+    // ids
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+        if (EXACT || k < K) st[k] = top.q[k] == kEmptyKey ? 0xffffffffu : (uint32_t)top.q[k];
+    __syncthreads();
+    pt_store_rows(reinterpret_cast<uint32_t*>(a.idx + pix0 * K), L.stage, K, rowK, rows, cols, vec);
+    __syncthreads();
+    // depths
     const uint32_t neg1 = __float_as_uint(-1.0f);
 #pragma unroll
-    for (int g0 = 0; g0 < KB; g0 += G) {
-        if (g0 >= K) continue;  // K is uniform: the whole wave skips
-        const int gw = EXACT ? G : min(G, K - g0);
+    for (int k = 0; k < KB; ++k)
+        if (EXACT || k < K) st[k] = top.q[k] == kEmptyKey ? neg1 : (uint32_t)(top.q[k] >> 32);
+    __syncthreads();
+    pt_store_rows(reinterpret_cast<uint32_t*>(a.zbuf + pix0 * K), L.stage, K, rowK, rows, cols, vec);
+    __syncthreads();
+    // squared distances
 #pragma unroll
-        for (int k = 0; k < G; ++k) {
-            const uint64_t key = top.q[g0 + k];
-            const bool empty = key == kEmptyKey;
-            sid[lane * S + k] = empty ? 0xffffffffu : (uint32_t)key;
-            sz[lane * S + k] = empty ? neg1 : (uint32_t)(key >> 32);
-        }
-        __syncthreads();
-        pt_store<G, V4, EXACT>(idx_t, sid, K, rowK, g0, gw, rows, cols);
-        pt_store<G, V4, EXACT>(z_t, sz, K, rowK, g0, gw, rows, cols);
-        __syncthreads();
-        // squared distances, recomputed in FP64 exactly as the test did
-#pragma unroll
-        for (int k = 0; k < G; ++k) {
-            const uint64_t key = top.q[g0 + k];
+    for (int k = 0; k < KB; ++k) {
+        if (EXACT || k < K) {
             float d = -1.0f;
-            if (key != kEmptyKey) {
-                const int64_t id = (int64_t)(uint32_t)key;
+            if (top.q[k] != kEmptyKey) {
+                const int64_t id = (int64_t)(uint32_t)top.q[k];
                 d = (float)pt_d2((double)a.pts[3 * id], (double)a.pts[3 * id + 1], px, py);
             }
-            sid[lane * S + k] = __float_as_uint(d);
+            st[k] = __float_as_uint(d);
         }
-        __syncthreads();
-        pt_store<G, V4, EXACT>(d_t, sid, K, rowK, g0, gw, rows, cols);
-        __syncthreads();
     }
+    __syncthreads();
+    pt_store_rows(reinterpret_cast<uint32_t*>(a.dists + pix0 * K), L.stage, K, rowK, rows, cols, vec);
 }
 
 template <int KB, bool EXACT>
-__global__ __launch_bounds__(64) void pt_raster_kernel(PtArgs a) {
-    __shared__ PtLds L;
+__global__ __launch_bounds__(64) void pt_raster_kernel(PtArgs a, bool aligned) {
+    __shared__ PtLds<KB> L;
     const int tx = blockIdx.x, ty = blockIdx.y, n = blockIdx.z;
     const int lane = threadIdx.x & 63;
     const int r = ty * kTile + (lane >> 3), c = tx * kTile + (lane & 7);
@@ -313,32 +352,43 @@ __global__ __launch_bounds__(64) void pt_raster_kernel(PtArgs a) {
         const int64_t row = ((int64_t)n * a.tiles_y + yy) * a.tiles_x;
         const int lo = a.start[row + max(tx - a.rx, 0)];
         const int hi = a.start[row + tx + 1];
-        for (int e0 = lo; e0 < hi; e0 += 64) {
-            const int e = e0 + lane;
-            bool keep = false;
-            float4 rec = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (e < hi) {
-                rec = a.sorted[e];
-                int c0, c1, r0, r1;
-                keep = disc_pixels(rec.x, rec.y, a.r, a.H, a.W, c0, c1, r0, r1) && c1 >= x0 && c0 <= x1 &&
-                       r1 >= y0 && r0 <= y1;
+        // kPtLoads chunks of candidates are loaded before any is culled, so
+        // their loads overlap
+        for (int e0 = lo; e0 < hi; e0 += 64 * kPtLoads) {
+            float4 recs[kPtLoads];
+#pragma unroll
+            for (int u = 0; u < kPtLoads; ++u) {
+                const int e = e0 + 64 * u + lane;
+                recs[u] = e < hi ? a.sorted[e] : make_float4(0.0f, 0.0f, -1.0f, 0.0f);
             }
-            const uint64_t kept = __ballot(keep);
-            const int cnt = __popcll(kept);
-            if (m + cnt > kPtBatch) {
-                pt_batch<KB>(a, L, top, m, live, px, py);
-                m = 0;
+#pragma unroll
+            for (int u = 0; u < kPtLoads; ++u) {
+                if (e0 + 64 * u >= hi) break;  // uniform
+                const float4 rec = recs[u];
+                bool keep = false;
+                if (e0 + 64 * u + lane < hi) {
+                    int c0, c1, r0, r1;
+                    keep = disc_pixels(rec.x, rec.y, a.r, a.H, a.W, c0, c1, r0, r1) && c1 >= x0 && c0 <= x1 &&
+                           r1 >= y0 && r0 <= y1;
+                }
+                const uint64_t kept = __ballot(keep);
+                const int cnt = __popcll(kept);
+                if (m + cnt > kPtBatch) {
+                    pt_batch<KB>(a, L.b, top, m, live, px, py);
+                    m = 0;
+                }
+                if (keep) {
+                    const int d = m + __popcll(kept & lt_mask);
+                    L.b.xy[d] = make_double2((double)rec.x, (double)rec.y);
+                    L.b.key[d] = make_key(rec.z, __float_as_int(rec.w));
+                }
+                m += cnt;
             }
-            if (keep) {
-                const int d = m + __popcll(kept & lt_mask);
-                L.xy[d] = make_double2((double)rec.x, (double)rec.y);
-                L.key[d] = make_key(rec.z, __float_as_int(rec.w));
-            }
-            m += cnt;
         }
     }
-    if (m > 0) pt_batch<KB>(a, L, top, m, live, px, py);
-    pt_write<KB, EXACT>(a, L, top, px, py, n, tx, ty);
+    if (m > 0) pt_batch<KB>(a, L.b, top, m, live, px, py);
+    __syncthreads();
+    pt_write<KB, EXACT>(a, L, top, px, py, n, tx, ty, aligned);
 }
 
 static PtArgs pt_args(const float* pts, int64_t P, const int64_t* first, const int64_t* np, int N, int H, int W,
@@ -358,10 +408,10 @@ static PtArgs pt_args(const float* pts, int64_t P, const int64_t* first, const i
     a.tiles_y = (H + kTile - 1) / kTile;
     // pixel-range spans of a disc: at most floor(r W + 0.03) columns past its
     // first (the ranges are widened by 0.01 pixel at each end)
-    const int span_x = (int)fmin(floor((double)radius * W + 0.05), (double)W);
-    const int span_y = (int)fmin(floor((double)radius * H + 0.05), (double)H);
-    a.rx = min((kTile - 1 + span_x) / kTile, a.tiles_x - 1);
-    a.ry = min((kTile - 1 + span_y) / kTile, a.tiles_y - 1);
+    a.span_x = (int)fmin(floor((double)radius * W + 0.05), (double)W);
+    a.span_y = (int)fmin(floor((double)radius * H + 0.05), (double)H);
+    a.rx = min((kTile - 1 + a.span_x) / kTile, a.tiles_x - 1);
+    a.ry = min((kTile - 1 + a.span_y) / kTile, a.tiles_y - 1);
     a.T = (int64_t)N * a.tiles_x * a.tiles_y;
     a.hdr = hdr;
     a.start = start;
@@ -380,9 +430,15 @@ int64_t pt_scan_blocks(int64_t T) { return (T + kScanTile - 1) / kScanTile; }
 static hipError_t pt_sort(const PtArgs& a, hipStream_t s) {
     hipError_t e = launch_fill_i32(a.start, a.T + 1, 0, s);
     if (e != hipSuccess) return e;
-    const int64_t nthreads = a.P > a.N ? a.P : a.N;
-    const unsigned g = (unsigned)((nthreads + 255) / 256);
-    hipLaunchKernelGGL(pt_count_kernel, dim3(g), dim3(256), 0, s, a);
+    if (a.T <= kCountLdsTiles) {
+        const int64_t per_block = (int64_t)kCountThreads * kCountPer;
+        const unsigned g = (unsigned)((a.P + per_block - 1) / per_block);
+        hipLaunchKernelGGL(pt_count_lds_kernel, dim3(g > 0 ? g : 1), dim3(kCountThreads), 0, s, a);
+    } else {
+        const int64_t nthreads = a.P > a.N ? a.P : a.N;
+        const unsigned g = (unsigned)((nthreads + 255) / 256);
+        hipLaunchKernelGGL(pt_count_kernel, dim3(g), dim3(256), 0, s, a);
+    }
     const int64_t nb = pt_scan_blocks(a.T);
     hipLaunchKernelGGL(pt_scan_sums_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a.start, a.T, a.bsum);
     hipLaunchKernelGGL(pt_scan_top_kernel, dim3(1), dim3(kScanThreads), 0, s, a.bsum, nb);
@@ -392,10 +448,10 @@ static hipError_t pt_sort(const PtArgs& a, hipStream_t s) {
 }
 
 template <int KB, bool EXACT>
-static hipError_t pt_fine_k(const PtArgs& a, hipStream_t s, hipEvent_t eb, hipEvent_t ee) {
+static hipError_t pt_fine_k(const PtArgs& a, bool aligned, hipStream_t s, hipEvent_t eb, hipEvent_t ee) {
     const dim3 grid(a.tiles_x, a.tiles_y, a.N);
     if (eb) (void)hipEventRecord(eb, s);
-    hipLaunchKernelGGL((pt_raster_kernel<KB, EXACT>), grid, dim3(64), 0, s, a);
+    hipLaunchKernelGGL((pt_raster_kernel<KB, EXACT>), grid, dim3(64), 0, s, a, aligned);
     if (ee) (void)hipEventRecord(ee, s);
     return hipGetLastError();
 }
@@ -411,13 +467,13 @@ hipError_t launch_points_fwd(const float* pts, int64_t P, const int64_t* first, 
     hipError_t e = pt_sort(a, s);
     if (e != hipSuccess) return e;
     const bool aligned = (((uintptr_t)idx | (uintptr_t)zbuf | (uintptr_t)dists) & 15) == 0;
-#define PT_FINE_BUCKET(KB)                                          \
-    if (K <= KB) {                                                  \
-        if (K == KB && aligned) return pt_fine_k<KB, true>(a, s, eb, ee); \
-        return pt_fine_k<KB, false>(a, s, eb, ee);                  \
+#define PT_FINE_BUCKET(KB)                                                     \
+    if (K <= KB) {                                                             \
+        if (K == KB) return pt_fine_k<KB, true>(a, aligned, s, eb, ee);        \
+        return pt_fine_k<KB, false>(a, aligned, s, eb, ee);                    \
     }
-    if (K <= 1) return pt_fine_k<1, true>(a, s, eb, ee);
-    if (K <= 2) return pt_fine_k<2, true>(a, s, eb, ee);
+    if (K <= 1) return pt_fine_k<1, true>(a, aligned, s, eb, ee);
+    if (K <= 2) return pt_fine_k<2, true>(a, aligned, s, eb, ee);
     PT_FINE_BUCKET(4)
     PT_FINE_BUCKET(8)
     PT_FINE_BUCKET(16)
@@ -430,12 +486,18 @@ hipError_t launch_points_fwd(const float* pts, int64_t P, const int64_t* first, 
 // ---------------------------------------------------------------------------
 // Backward.  zbuf_k = z_p and dists_k = (x_p - px)^2 + (y_p - py)^2 for the
 // point p held in slot k, so dL/dz_p collects grad_zbuf and dL/d(x_p, y_p)
-// collects 2 grad_dists (x_p - px, y_p - py) over p's slots.  One thread per
-// point, in home-tile order so that the threads of a wave read neighbouring
-// pixels: it visits the pixels its disc covers (the forward's exact test),
-// finds itself in each pixel's id list and sums its own terms, then writes
-// its gradient once.  A point is listed only at pixels its disc covers, so
-// no slot is missed, and every gradient is a plain store.
+// collects 2 grad_dists (x_p - px, y_p - py) over p's slots.  Every point
+// gathers its own terms and writes its gradient once (no atomics, the same
+// sum order on every run): it visits the pixels its disc covers (the
+// forward's exact test) and finds itself in each pixel's id list.  A point is
+// listed only at pixels its disc covers, so no slot is missed.
+//
+// One workgroup per home tile: the points of the tile are contiguous in the
+// sorted array, and every pixel they can cover lies in the tile grown by the
+// disc reach (span_x columns to the right, span_y rows down), so the ids and
+// upstream gradients of that pixel box are staged in LDS first (rows padded
+// to a multiple of four slots for 16-byte reads).  When the box does not fit
+// in LDS, a one-thread-per-point form reads the lists from global memory.
 // ---------------------------------------------------------------------------
 struct PtBwdArgs {
     const float4* sorted;
@@ -451,20 +513,30 @@ struct PtBwdArgs {
     int N, H, W, K;
     float r;
     double r2;
+    int tiles_x, tiles_y, span_x, span_y;
+    int Kp;  // slots per pixel in LDS (K rounded up to a multiple of 4)
     int reuse;
     BinSig sig;
 };
 
-__global__ __launch_bounds__(256) void pt_bwd_kernel(PtBwdArgs b) {
-    if (b.reuse) {
-        bool same = true;
+__device__ __forceinline__ bool pt_bwd_usable(const PtBwdArgs& b) {
+    if (!b.reuse) return true;
+    bool same = true;
 #pragma unroll
-        for (int i = 0; i < kSigWords; ++i) same = same && (b.hdr[kHdrSig + i] == b.sig.w[i]);
-        if (!same) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&b.hdr[kHdrStatus], kStatReuse);
-            return;
-        }
-    }
+    for (int i = 0; i < kSigWords; ++i) same = same && (b.hdr[kHdrSig + i] == b.sig.w[i]);
+    if (!same && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&b.hdr[kHdrStatus], kStatReuse);
+    return same;
+}
+
+__device__ __forceinline__ void pt_write_grad(const PtBwdArgs& b, int id, double gx, double gy, double gzs) {
+    b.grad[3 * (int64_t)id + 0] = (float)gx;
+    b.grad[3 * (int64_t)id + 1] = (float)gy;
+    b.grad[3 * (int64_t)id + 2] = (float)gzs;
+}
+
+// One thread per sorted point, id lists read from global memory.
+__global__ __launch_bounds__(256) void pt_bwd_kernel(PtBwdArgs b) {
+    if (!pt_bwd_usable(b)) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= b.start[b.T]) return;
     const float4 rec = b.sorted[i];
@@ -493,9 +565,117 @@ __global__ __launch_bounds__(256) void pt_bwd_kernel(PtBwdArgs b) {
             }
         }
     }
-    b.grad[3 * (int64_t)id + 0] = (float)gx;
-    b.grad[3 * (int64_t)id + 1] = (float)gy;
-    b.grad[3 * (int64_t)id + 2] = (float)gzs;
+    pt_write_grad(b, id, gx, gy, gzs);
+}
+
+constexpr int kBwdTileThreads = 256;
+
+// e / d for 0 <= e < 2^22 and d > 0: the float estimate is off by at most one.
+__device__ __forceinline__ int small_div(int e, int d, float inv_d) {
+    int q = (int)((float)e * inv_d);
+    if (q * d > e) --q;
+    else if ((q + 1) * d <= e) ++q;
+    return q;
+}
+extern __shared__ uint32_t bwd_lds[];
+
+__global__ __launch_bounds__(kBwdTileThreads) void pt_bwd_tile_kernel(PtBwdArgs b) {
+    if (!pt_bwd_usable(b)) return;
+    const int t = blockIdx.x;
+    const int lo = b.start[t], hi = b.start[t + 1];
+    if (lo == hi) return;  // uniform: no point has this home tile
+    const int per_img = b.tiles_x * b.tiles_y;
+    const int n = t / per_img;
+    const int rem = t - n * per_img;
+    const int ty = rem / b.tiles_x, tx = rem - (rem / b.tiles_x) * b.tiles_x;
+    const int x0 = tx * kTile, y0 = ty * kTile;
+    const int bw = min(x0 + kTile + b.span_x, b.W) - x0;
+    const int bh = min(y0 + kTile + b.span_y, b.H) - y0;
+    const int K = b.K, Kp = b.Kp;
+    const int box = bw * bh * Kp;
+    int* sidx = reinterpret_cast<int*>(bwd_lds);
+    float* sgz = reinterpret_cast<float*>(bwd_lds + box);
+    float* sgd = reinterpret_cast<float*>(bwd_lds + (b.gz ? 2 : 1) * box);
+    // stage the box: LDS word e = (row * bw + pixel) * Kp + slot; padding
+    // slots hold -1.  Eight words per thread are loaded before any is stored.
+    const int rowl = bw * Kp, nbox = bh * rowl;
+    const float inv_rowl = 1.0f / (float)rowl, inv_kp = 1.0f / (float)Kp;
+    for (int e0 = 0; e0 < nbox; e0 += 8 * kBwdTileThreads) {
+        int vi[8];
+        float vz[8], vd[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int e = e0 + j * kBwdTileThreads + (int)threadIdx.x;
+            vi[j] = -1;
+            vz[j] = vd[j] = 0.0f;
+            if (e < nbox) {
+                const int r = small_div(e, rowl, inv_rowl);
+                const int rem = e - r * rowl;
+                const int px = small_div(rem, Kp, inv_kp);
+                const int k = rem - px * Kp;
+                if (k < K) {
+                    const int64_t g = (((int64_t)n * b.H + y0 + r) * b.W + x0 + px) * K + k;
+                    vi[j] = b.idx[g];
+                    if (b.gz) vz[j] = b.gz[g];
+                    if (b.gd) vd[j] = b.gd[g];
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int e = e0 + j * kBwdTileThreads + (int)threadIdx.x;
+            if (e < nbox) {
+                sidx[e] = vi[j];
+                if (b.gz) sgz[e] = vz[j];
+                if (b.gd) sgd[e] = vd[j];
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = lo + (int)threadIdx.x; i < hi; i += kBwdTileThreads) {
+        const float4 rec = b.sorted[i];
+        const int id = __float_as_int(rec.w);
+        int c0, c1, r0, r1;
+        disc_pixels(rec.x, rec.y, b.r, b.H, b.W, c0, c1, r0, r1);
+        // the ranges lie in the box by construction of the home tile and the
+        // reach; clamping only keeps every LDS index in bounds
+        r0 = max(r0, y0);
+        c0 = max(c0, x0);
+        r1 = min(r1, y0 + bh - 1);
+        c1 = min(c1, x0 + bw - 1);
+        const double x = rec.x, y = rec.y;
+        double gx = 0.0, gy = 0.0, gzs = 0.0;
+        for (int r = r0; r <= r1; ++r) {
+            const double py = 1.0 - (double)(2 * r + 1) / (double)b.H;
+            for (int c = c0; c <= c1; ++c) {
+                const double px = 1.0 - (double)(2 * c + 1) / (double)b.W;
+                if (!(pt_d2(x, y, px, py) < b.r2)) continue;
+                const int l0 = ((r - y0) * bw + (c - x0)) * Kp;
+                int s = -1;
+                for (int k4 = 0; k4 < K && s < 0; k4 += 4) {
+                    const int4 v = *reinterpret_cast<const int4*>(sidx + l0 + k4);
+                    s = v.x == id ? l0 + k4 : v.y == id ? l0 + k4 + 1 : v.z == id ? l0 + k4 + 2
+                        : v.w == id ? l0 + k4 + 3 : -1;
+                }
+                if (s < 0) continue;
+                if (b.gz) gzs += (double)sgz[s];
+                if (b.gd) {
+                    const double g = 2.0 * (double)sgd[s];
+                    gx += g * (x - px);
+                    gy += g * (y - py);
+                }
+            }
+        }
+        pt_write_grad(b, id, gx, gy, gzs);
+    }
+}
+
+// LDS bytes of the box-staged backward, or 0 when it does not fit.
+static size_t pt_bwd_lds_bytes(const PtArgs& a, int span_x, int span_y, bool gz, bool gd) {
+    const int64_t bw = min(kTile + span_x, a.W), bh = min(kTile + span_y, a.H);
+    const int64_t Kp = (a.K + 3) & ~3;
+    const int64_t bytes = bw * bh * Kp * 4 * (1 + (gz ? 1 : 0) + (gd ? 1 : 0));
+    return bytes <= 65536 ? (size_t)bytes : 0;
 }
 
 hipError_t launch_points_bwd(const float* pts, int64_t P, const int64_t* first, const int64_t* np, int N, int H,
@@ -529,29 +709,44 @@ hipError_t launch_points_bwd(const float* pts, int64_t P, const int64_t* first, 
     b.K = K;
     b.r = radius;
     b.r2 = a.r2;
+    b.tiles_x = a.tiles_x;
+    b.tiles_y = a.tiles_y;
+    b.span_x = a.span_x;
+    b.span_y = a.span_y;
+    b.Kp = (K + 3) & ~3;
     b.reuse = reuse ? 1 : 0;
     b.sig = sig;
+    const size_t lds = pt_bwd_lds_bytes(a, a.span_x, a.span_y, gz != nullptr, gd != nullptr);
     if (eb) (void)hipEventRecord(eb, s);
-    hipLaunchKernelGGL(pt_bwd_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, b);
+    if (lds > 0)
+        hipLaunchKernelGGL(pt_bwd_tile_kernel, dim3((unsigned)a.T), dim3(kBwdTileThreads), lds, s, b);
+    else
+        hipLaunchKernelGGL(pt_bwd_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, b);
     if (ee) (void)hipEventRecord(ee, s);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Compositing (paper, Section 3.3).  One thread per pixel over its K slots;
-// slots whose id is negative (or not below P) take no part.  Opacities come
-// either as given or, for splats, from the squared distance: alpha = 1 - d/r^2.
+// Compositing (paper, Section 3.3).  A pixel's K slots are spread over L
+// lanes of a wave, four consecutive slots per lane (L the power of two with
+// 4 L >= K, 64 / L pixels per wave): each lane combines its own four slots in
+// order and only the per-lane aggregates cross lanes, in segmented scans of
+// log2(L) steps.  Slots whose id is negative (or not below P) take no part.
+// Opacities come either as given or, for splats, from the squared distance:
+// alpha = 1 - d/r^2.
 //   Alpha:  out = sum_k alpha_k T_k f_k,  T_k = prod_{j<k} (1 - alpha_j)
 //   Norm:   out = sum_k alpha_k f_k / S,   S = sum_k alpha_k (0 where S <= 0)
 // Backward (g = upstream gradient of the pixel, g_k = <g, f_k>):
 //   Alpha:  dL/dalpha_k = T_k (g_k - R_k),  R_k = sum_{i>k} alpha_i g_i
-//           prod_{k<j<i} (1 - alpha_j), which runs backwards as
-//           R_{k-1} = alpha_k g_k + (1 - alpha_k) R_k -- no division by
-//           1 - alpha_k, so a fully opaque slot is no special case;
-//           dL/df_k = alpha_k T_k g.
+//           prod_{k<j<i} (1 - alpha_j).  R_k is the composition of the affine
+//           maps x -> (1 - alpha_i) x + alpha_i g_i over the slots after k,
+//           applied to 0 -- a suffix scan with no division by 1 - alpha_k, so
+//           a fully opaque slot is no special case;  dL/df_k = alpha_k T_k g.
 //   Norm:   dL/dalpha_k = (g_k - <g, out>) / S,  dL/df_k = alpha_k g / S.
 // Feature gradients are scattered to the point rows with float atomics.
 // ---------------------------------------------------------------------------
+constexpr int kCompQ = 4;  // consecutive slots per lane
+
 struct CompArgs {
     const int32_t* idx;
     const float* w;
@@ -562,119 +757,177 @@ struct CompArgs {
     float inv_r2;
 };
 
-__device__ __forceinline__ float comp_alpha(const CompArgs& a, int64_t o) {
-    const float w = a.w[o];
-    return a.from_d ? 1.0f - w * a.inv_r2 : w;
+// The lane's slots of pixel p: point ids (-1 if a slot takes no part) and opacities (0 then).
+__device__ __forceinline__ void comp_slots(const CompArgs& a, int64_t p, int sub, int (&id)[kCompQ],
+                                           float (&al)[kCompQ]) {
+    int32_t iv[kCompQ];
+    float wv[kCompQ];
+    const int64_t o = p * a.K + kCompQ * sub;
+#pragma unroll
+    for (int i = 0; i < kCompQ; ++i) {
+        const bool in = p < a.npix && kCompQ * sub + i < a.K;
+        iv[i] = in ? a.idx[o + i] : -1;
+        wv[i] = in ? a.w[o + i] : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < kCompQ; ++i) {
+        const bool ok = iv[i] >= 0 && iv[i] < a.P;
+        id[i] = ok ? iv[i] : -1;
+        al[i] = ok ? (a.from_d ? 1.0f - wv[i] * a.inv_r2 : wv[i]) : 0.0f;
+    }
 }
 
-template <int CB>
-__global__ __launch_bounds__(256) void composite_fwd_kernel(CompArgs a, float* __restrict__ img) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.npix) return;
-    float out[CB];
+// exclusive product over the lower lanes of the segment
+template <int L>
+__device__ __forceinline__ float seg_exclusive_prod(float t, int sub) {
 #pragma unroll
-    for (int c = 0; c < CB; ++c) out[c] = 0.0f;
-    float T = 1.0f, S = 0.0f;
-    for (int k = 0; k < a.K; ++k) {
-        const int64_t o = p * a.K + k;
-        const int id = a.idx[o];
-        if (id < 0 || id >= a.P) continue;
-        const float al = comp_alpha(a, o);
-        const float wk = a.norm ? al : al * T;
-        const float* fr = a.f + (int64_t)id * a.D;
+    for (int d = 1; d < L; d <<= 1) {
+        const float u = __shfl_up(t, d, L);
+        if (sub >= d) t *= u;
+    }
+    const float e = __shfl_up(t, 1, L);
+    return sub == 0 ? 1.0f : e;
+}
+
+template <int L>
+__device__ __forceinline__ float seg_sum(float v) {
+#pragma unroll
+    for (int d = L / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, L);
+    return v;
+}
+
+template <int L, int CB>
+__global__ __launch_bounds__(256) void composite_fwd_kernel(CompArgs a, float* __restrict__ img) {
+    constexpr int PPW = 64 / L;
+    const int lane = threadIdx.x & 63, sub = lane & (L - 1), grp = lane / L;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t p0 = wave * PPW; p0 < a.npix; p0 += nwaves * PPW) {
+        const int64_t p = p0 + grp;
+        int id[kCompQ];
+        float al[kCompQ];
+        comp_slots(a, p, sub, id, al);
+        float t = 1.0f, S = 0.0f;
+#pragma unroll
+        for (int i = 0; i < kCompQ; ++i) {
+            t *= 1.0f - al[i];
+            S += al[i];
+        }
+        float T = a.norm ? 1.0f : seg_exclusive_prod<L>(t, sub);
+        float acc[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) acc[c] = 0.0f;
+#pragma unroll
+        for (int i = 0; i < kCompQ; ++i) {
+            if (id[i] >= 0) {
+                const float wk = a.norm ? al[i] : al[i] * T;
+                const float* fr = a.f + (int64_t)id[i] * a.D;
+#pragma unroll
+                for (int c = 0; c < CB; ++c)
+                    if (c < a.D) acc[c] = fmaf(wk, fr[c], acc[c]);
+            }
+            T *= 1.0f - al[i];
+        }
 #pragma unroll
         for (int c = 0; c < CB; ++c)
-            if (c < a.D) out[c] = fmaf(wk, fr[c], out[c]);
-        T *= 1.0f - al;
-        S += al;
-    }
-    const float sc = a.norm ? (S > 0.0f ? 1.0f / S : 0.0f) : 1.0f;
+            if (c < a.D) acc[c] = seg_sum<L>(acc[c]);
+        if (a.norm) S = seg_sum<L>(S);
+        const float sc = a.norm ? (S > 0.0f ? 1.0f / S : 0.0f) : 1.0f;
+        if (sub == 0 && p < a.npix) {
 #pragma unroll
-    for (int c = 0; c < CB; ++c)
-        if (c < a.D) img[p * a.D + c] = out[c] * sc;
+            for (int c = 0; c < CB; ++c)
+                if (c < a.D) img[p * a.D + c] = acc[c] * sc;
+        }
+    }
 }
 
-template <int CB>
+template <int L, int CB>
 __global__ __launch_bounds__(256) void composite_bwd_kernel(CompArgs a, const float* __restrict__ gimg,
                                                             float* __restrict__ gw, float* __restrict__ gf) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.npix) return;
-    float g[CB];
-#pragma unroll
-    for (int c = 0; c < CB; ++c) g[c] = c < a.D ? gimg[p * a.D + c] : 0.0f;
+    constexpr int PPW = 64 / L;
+    const int lane = threadIdx.x & 63, sub = lane & (L - 1), grp = lane / L;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const float chain = a.from_d ? -a.inv_r2 : 1.0f;
-    if (!a.norm) {
-        // forward sweep: T_k (kept in gw) and the feature gradients
-        float T = 1.0f;
-        for (int k = 0; k < a.K; ++k) {
-            const int64_t o = p * a.K + k;
-            const int id = a.idx[o];
-            if (id < 0 || id >= a.P) {
-                gw[o] = 0.0f;
-                continue;
-            }
-            const float al = comp_alpha(a, o);
-            gw[o] = T;
-            if (gf) {
-                const float wk = al * T;
+    for (int64_t p0 = wave * PPW; p0 < a.npix; p0 += nwaves * PPW) {
+        const int64_t p = p0 + grp;
+        int id[kCompQ];
+        float al[kCompQ];
+        comp_slots(a, p, sub, id, al);
+        float g[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) g[c] = (p < a.npix && c < a.D) ? gimg[p * a.D + c] : 0.0f;
+        float gk[kCompQ];
+#pragma unroll
+        for (int i = 0; i < kCompQ; ++i) {
+            gk[i] = 0.0f;
+            if (id[i] >= 0) {
+                const float* fr = a.f + (int64_t)id[i] * a.D;
 #pragma unroll
                 for (int c = 0; c < CB; ++c)
-                    if (c < a.D) atomicAdd(gf + (int64_t)id * a.D + c, wk * g[c]);
+                    if (c < a.D) gk[i] = fmaf(g[c], fr[c], gk[i]);
             }
-            T *= 1.0f - al;
         }
-        // backward sweep: R_k and dL/dalpha_k = T_k (g_k - R_k)
-        float R = 0.0f;
-        for (int k = a.K - 1; k >= 0; --k) {
-            const int64_t o = p * a.K + k;
-            const int id = a.idx[o];
-            if (id < 0 || id >= a.P) continue;
-            const float al = comp_alpha(a, o);
-            const float* fr = a.f + (int64_t)id * a.D;
-            float gk = 0.0f;
+        float dal[kCompQ], wf[kCompQ];
+        if (!a.norm) {
+            float t = 1.0f;
 #pragma unroll
-            for (int c = 0; c < CB; ++c)
-                if (c < a.D) gk = fmaf(g[c], fr[c], gk);
-            gw[o] = gw[o] * (gk - R) * chain;
-            R = fmaf(1.0f - al, R, al * gk);
-        }
-    } else {
-        // first sweep: S, sum alpha_k g_k, and g_k kept in gw
-        float S = 0.0f, A = 0.0f;
-        for (int k = 0; k < a.K; ++k) {
-            const int64_t o = p * a.K + k;
-            const int id = a.idx[o];
-            if (id < 0 || id >= a.P) {
-                gw[o] = 0.0f;
-                continue;
-            }
-            const float al = comp_alpha(a, o);
-            const float* fr = a.f + (int64_t)id * a.D;
-            float gk = 0.0f;
+            for (int i = 0; i < kCompQ; ++i) t *= 1.0f - al[i];
+            float T = seg_exclusive_prod<L>(t, sub);
+            // the lane's four maps composed (slot 4 sub outermost), then the
+            // composition of every later lane's maps: a suffix scan
+            float A = 1.0f, B = 0.0f;
 #pragma unroll
-            for (int c = 0; c < CB; ++c)
-                if (c < a.D) gk = fmaf(g[c], fr[c], gk);
-            gw[o] = gk;
-            S += al;
-            A = fmaf(al, gk, A);
-        }
-        const bool lit = S > 0.0f;
-        const float invS = lit ? 1.0f / S : 0.0f;
-        const float gout = A * invS;
-        for (int k = 0; k < a.K; ++k) {
-            const int64_t o = p * a.K + k;
-            const int id = a.idx[o];
-            if (id < 0 || id >= a.P) continue;
-            if (!lit) {
-                gw[o] = 0.0f;
-                continue;
+            for (int i = kCompQ - 1; i >= 0; --i) {
+                B = fmaf(1.0f - al[i], B, al[i] * gk[i]);
+                A *= 1.0f - al[i];
             }
-            gw[o] = (gw[o] - gout) * invS * chain;
-            if (gf) {
-                const float wk = comp_alpha(a, o) * invS;
+#pragma unroll
+            for (int d = 1; d < L; d <<= 1) {
+                const float A2 = __shfl_down(A, d, L), B2 = __shfl_down(B, d, L);
+                if (sub + d < L) {
+                    B = fmaf(A, B2, B);
+                    A *= A2;
+                }
+            }
+            const float Bn = __shfl_down(B, 1, L);
+            float V = sub == L - 1 ? 0.0f : Bn;  // R after the lane's last slot
+            float R[kCompQ];
+#pragma unroll
+            for (int i = kCompQ - 1; i >= 0; --i) {
+                R[i] = V;
+                V = fmaf(1.0f - al[i], V, al[i] * gk[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < kCompQ; ++i) {
+                dal[i] = T * (gk[i] - R[i]);
+                wf[i] = al[i] * T;
+                T *= 1.0f - al[i];
+            }
+        } else {
+            float S = 0.0f, Ag = 0.0f;
+#pragma unroll
+            for (int i = 0; i < kCompQ; ++i) {
+                S += al[i];
+                Ag = fmaf(al[i], gk[i], Ag);
+            }
+            S = seg_sum<L>(S);
+            Ag = seg_sum<L>(Ag);
+            const float invS = S > 0.0f ? 1.0f / S : 0.0f;
+#pragma unroll
+            for (int i = 0; i < kCompQ; ++i) {
+                dal[i] = (gk[i] - Ag * invS) * invS;
+                wf[i] = al[i] * invS;
+            }
+        }
+        const int64_t o = p * a.K + kCompQ * sub;
+#pragma unroll
+        for (int i = 0; i < kCompQ; ++i) {
+            if (p < a.npix && kCompQ * sub + i < a.K) gw[o + i] = id[i] >= 0 ? dal[i] * chain : 0.0f;
+            if (gf && id[i] >= 0 && wf[i] != 0.0f) {
 #pragma unroll
                 for (int c = 0; c < CB; ++c)
-                    if (c < a.D) atomicAdd(gf + (int64_t)id * a.D + c, wk * g[c]);
+                    if (c < a.D) atomicAdd(gf + (int64_t)id[i] * a.D + c, wf[i] * g[c]);
             }
         }
     }
@@ -696,16 +949,41 @@ static CompArgs comp_args(const int32_t* idx, const float* w, const float* f, in
     return a;
 }
 
+// Workgroups of a grid-stride launch: one wave per 64 / L pixels, at most
+// 2048 workgroups of four waves.
+static unsigned comp_blocks(int64_t npix, int L) {
+    const int64_t waves = (npix + 64 / L - 1) / (64 / L);
+    const int64_t blocks = (waves + 3) / 4;
+    return (unsigned)(blocks < 1 ? 1 : (blocks > 2048 ? 2048 : blocks));
+}
+
+template <int CB>
+static hipError_t comp_launch(const CompArgs& a, bool bwd, const float* gimg, float* gw, float* gf, float* img,
+                              hipStream_t s) {
+#define COMP_L(L)                                                                                      \
+    if (a.K <= kCompQ * L) {                                                                           \
+        const dim3 grid(comp_blocks(a.npix, L));                                                       \
+        if (bwd)                                                                                       \
+            hipLaunchKernelGGL((composite_bwd_kernel<L, CB>), grid, dim3(256), 0, s, a, gimg, gw, gf); \
+        else                                                                                           \
+            hipLaunchKernelGGL((composite_fwd_kernel<L, CB>), grid, dim3(256), 0, s, a, img);          \
+        return hipGetLastError();                                                                      \
+    }
+    COMP_L(1)
+    COMP_L(2)
+    COMP_L(4)
+    COMP_L(8)
+    COMP_L(16)
+#undef COMP_L
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_composite_fwd(const int32_t* idx, const float* w, const float* f, int64_t P, int64_t npix, int K,
                                 int D, int mode, float radius, float* img, hipStream_t s) {
     if (npix == 0) return hipSuccess;
     const CompArgs a = comp_args(idx, w, f, P, npix, K, D, mode, radius);
-    const dim3 grid((unsigned)((npix + 255) / 256));
-    if (D <= 4)
-        hipLaunchKernelGGL(composite_fwd_kernel<4>, grid, dim3(256), 0, s, a, img);
-    else
-        hipLaunchKernelGGL(composite_fwd_kernel<8>, grid, dim3(256), 0, s, a, img);
-    return hipGetLastError();
+    if (D <= 4) return comp_launch<4>(a, false, nullptr, nullptr, nullptr, img, s);
+    return comp_launch<8>(a, false, nullptr, nullptr, nullptr, img, s);
 }
 
 hipError_t launch_composite_bwd(const int32_t* idx, const float* w, const float* f, int64_t P, int64_t npix, int K,
@@ -717,12 +995,8 @@ hipError_t launch_composite_bwd(const int32_t* idx, const float* w, const float*
     }
     if (npix == 0) return hipSuccess;
     const CompArgs a = comp_args(idx, w, f, P, npix, K, D, mode, radius);
-    const dim3 grid((unsigned)((npix + 255) / 256));
-    if (D <= 4)
-        hipLaunchKernelGGL(composite_bwd_kernel<4>, grid, dim3(256), 0, s, a, gimg, gw, gf);
-    else
-        hipLaunchKernelGGL(composite_bwd_kernel<8>, grid, dim3(256), 0, s, a, gimg, gw, gf);
-    return hipGetLastError();
+    if (D <= 4) return comp_launch<4>(a, true, gimg, gw, gf, nullptr, s);
+    return comp_launch<8>(a, true, gimg, gw, gf, nullptr, s);
 }
 
 }  // namespace rast

@@ -81,3 +81,80 @@ class GraphRunner:
     def status(self):
         """(status, max_bin_count) of the last forward; synchronises."""
         return _lib.rast_query_status(self.ws)
+
+
+class PointsGraphRunner:
+    """hipGraph of one point-cloud render step: rasterize, composite the
+    splats (Alpha or Norm, opacity 1 - d / r^2), composite backward, rasterize
+    backward reusing the forward's sorted points.  Static buffers as for
+    GraphRunner; ``features`` (P,D) and the upstream image gradient are set
+    with ``set_features`` / ``set_grad_image``."""
+
+    def __init__(self, points, first_idx, num_points, H, W, radius, K, D=1, norm=False, feature_grad=False):
+        dev = points.device
+        self.device = dev
+        N, P = first_idx.shape[0], points.shape[0]
+        self.dims = (N, H, W, K, D)
+        self.radius = float(radius)
+        self.mode = ((_lib.RAST_COMPOSITE_NORM if norm else _lib.RAST_COMPOSITE_ALPHA)
+                     | _lib.RAST_COMPOSITE_FROM_DISTS)
+        self.points = points.detach().clone().contiguous()
+        self.first_idx = first_idx.contiguous()
+        self.num_points = num_points.contiguous()
+        self.idx = torch.empty((N, H, W, K), dtype=torch.int32, device=dev)
+        self.zbuf = torch.empty((N, H, W, K), dtype=torch.float32, device=dev)
+        self.dists = torch.empty_like(self.zbuf)
+        self.features = torch.ones((P, D), dtype=torch.float32, device=dev)
+        self.image = torch.empty((N, H, W, D), dtype=torch.float32, device=dev)
+        self.grad_image = torch.zeros_like(self.image)
+        self.grad_dists = torch.empty_like(self.zbuf)
+        self.grad_features = torch.empty_like(self.features) if feature_grad else None
+        self.grad_points = torch.empty_like(self.points)
+        self.ws = torch.empty(_lib.rast_points_workspace_size(N, H, W, P), dtype=torch.uint8, device=dev)
+        self.graph = None
+
+    def set_features(self, f):
+        self.features.copy_(f)
+
+    def set_grad_image(self, g):
+        self.grad_image.copy_(g)
+
+    def forward_eager(self):
+        N, H, W, K, D = self.dims
+        _lib.rasterize_points_fwd(self.points, self.first_idx, self.num_points, H, W, self.radius, K, self.idx,
+                                  self.zbuf, self.dists, self.ws)
+        _lib.points_composite_fwd(self.idx, self.dists, self.features, self.mode, self.radius, self.image)
+
+    def backward_eager(self):
+        N, H, W, K, D = self.dims
+        _lib.points_composite_bwd(self.idx, self.dists, self.features, self.mode, self.radius, self.grad_image,
+                                  self.grad_dists, self.grad_features)
+        _lib.rasterize_points_bwd(self.points, self.first_idx, self.num_points, H, W, self.radius, K,
+                                  _lib.RAST_BWD_REUSE_FORWARD, self.idx, None, self.grad_dists, self.grad_points,
+                                  self.ws)
+
+    def step_eager(self):
+        self.forward_eager()
+        self.backward_eager()
+
+    def capture(self, warmup: int = 2):
+        s = torch.cuda.Stream(device=self.device)
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(s):
+            for _ in range(warmup):
+                self.step_eager()
+        torch.cuda.current_stream(self.device).wait_stream(s)
+        torch.cuda.synchronize(self.device)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.step_eager()
+        torch.cuda.synchronize(self.device)
+        return self
+
+    def replay(self):
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()
+
+    def status(self):
+        return _lib.rast_query_status(self.ws)

@@ -370,3 +370,57 @@ def test_points_render_autograd_chain(norm):
     # the FP32 dL/dd (scale 1/r^2) dominates the error
     assert err <= 1e-4 * float(np.abs(gpr).max())
     assert float(np.abs(t_f.grad.cpu().numpy() - gfr).max()) <= 4 * TOL_COMP * max(1.0, float(np.abs(gfr).max()))
+
+
+def test_points_graph_replays_match_eager():
+    from paper_2007_08501_amd.graph import PointsGraphRunner
+    b = meshgen.make_points_config(2)
+    H, W = b.image_size
+    K = b.points_per_pixel
+    p, f, n = dev_cloud(b)
+    _, _, feat, gimg = meshgen.point_grads(b, channels=3)
+    gr = PointsGraphRunner(p, f, n, H, W, b.radius, K, D=3, feature_grad=True)
+    gr.set_features(torch.from_numpy(feat).cuda())
+    gr.set_grad_image(torch.from_numpy(gimg).cuda())
+    gr.step_eager()
+    torch.cuda.synchronize()
+    names = ("idx", "zbuf", "dists", "image", "grad_dists", "grad_points")
+    ref = {k: getattr(gr, k).clone() for k in names}
+    ref_gf = gr.grad_features.clone()
+    gr.capture()
+    for rep in range(3):
+        for k in names:
+            getattr(gr, k).fill_(7)
+        gr.grad_features.fill_(7)
+        gr.replay()
+        torch.cuda.synchronize()
+        for k in names:
+            assert torch.equal(getattr(gr, k), ref[k]), (rep, k)
+        # feature gradients are float-atomic sums: equal up to rounding order
+        torch.testing.assert_close(gr.grad_features, ref_gf, rtol=1e-5, atol=1e-5)
+        torch.randn(1000, device="cuda").sum().item()  # unrelated eager work between replays
+    assert gr.status()[0] == _lib.RAST_OK
+
+
+def test_points_many_tiles_global_count_path():
+    # more tiles than the counting pass's LDS histogram holds (2 x 100 x 101)
+    rng = np.random.default_rng(17)
+    pts = np.c_[rng.uniform(-1.0, 1.0, (400, 2)), rng.uniform(0.0, 3.0, 400)].astype(np.float32)
+    check_case(pts, [0, 150], [150, 250], 800, 808, 0.01, 3, "many tiles")
+
+
+def test_points_backward_large_radius_global_form():
+    # a disc reach whose pixel box does not fit in LDS takes the one-thread-per-point form
+    b = meshgen.make_points_config(1, points_override=600)
+    H, W = b.image_size
+    K = 32
+    radius = float(np.float32(0.3))
+    p, f, n = dev_cloud(b)
+    idx, _, _, ws = run_pfwd(p, f, n, H, W, radius, K)
+    rng = np.random.default_rng(5)
+    gz = rng.standard_normal((1, H, W, K)).astype(np.float32)
+    gd = rng.standard_normal((1, H, W, K)).astype(np.float32)
+    g = run_pbwd(p, f, n, H, W, radius, K, idx, torch.from_numpy(gz).cuda(), torch.from_numpy(gd).cuda(), ws,
+                 _lib.RAST_BWD_REUSE_FORWARD)
+    o = oracle_pfwd(b.points, b.first_idx, b.num_points, H, W, radius, K)
+    assert_grad_close(g, oracle.points_backward(b.points, (H, W), o["idx"], gz, gd, nthreads=threads()), "r0.3")
