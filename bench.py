@@ -80,6 +80,7 @@ class HipEvents:
 KERNEL_SOURCES = {
     "fine": ["paper_2007_08501_amd/csrc/kernels_fwd.hip", "paper_2007_08501_amd/csrc/device.hpp"],
     "backward": ["paper_2007_08501_amd/csrc/kernels_bwd.hip", "paper_2007_08501_amd/csrc/device.hpp"],
+    "points_fine": ["paper_2007_08501_amd/csrc/kernels_points.hip", "paper_2007_08501_amd/csrc/device.hpp"],
 }
 
 
@@ -113,12 +114,12 @@ def measured_traffic(kernel, config, K, bs):
         return None
 
 
-def measured_valu(kernel, config, K, bs):
+def measured_valu(kernel, config, K, bs, path=None):
     """VALU wave instructions per launch of `kernel` from the committed
     kernel-trace summary (SQ_INSTS_VALU), or None when there is none for this
     workload or the kernel changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"kernels_cfg{config}_K{K}_bs{bs}.txt")
-    if kernel != "fine" or not os.path.exists(path):
+    path = path or os.path.join(ROOT, "profiles", f"kernels_cfg{config}_K{K}_bs{bs}.txt")
+    if kernel not in ("fine", "points_fine") or not os.path.exists(path):
         return None
     vals = {}
     with open(path) as fh:
@@ -335,6 +336,11 @@ def points_main(args):
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel_ms": round(dom_ms, 5),
                 "algorithmic_bytes": dom_bytes}
+    valu = measured_valu(dom, 0, K, 0, path=os.path.join(ROOT, "profiles", f"kernels_pts3_K{K}.txt"))
+    if valu is not None:
+        lane_ops = valu * 64 / (dom_ms * 1e-3)
+        roofline["valu"] = {"lane_ops_per_s": float(f"{lane_ops:.4g}"), "peak": VALU_PEAK_LANE_OPS,
+                            "frac": round(lane_ops / VALU_PEAK_LANE_OPS, 4), "wave_instructions": int(valu)}
     cpu, parity = None, None
     if not args.no_cpu_baseline:
         cpu, parity = points_cpu_leg(b, args.cpu_seconds, gr.idx, gr.zbuf, gr.dists, gd_np)
