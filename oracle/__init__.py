@@ -54,11 +54,11 @@ def _load():
     i64 = ctypes.c_int64
     ci = ctypes.c_int
     lib.oracle_rasterize.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, ctypes.c_double, ci, P, i64,
-                                     P, P, P, P, P, P, ci]
+                                     P, P, P, P, P, P, ci, ci]
     lib.oracle_rasterize.restype = ci
-    lib.oracle_fragments_fixed.argtypes = [P, P, ci, ci, ci, ci, P, ctypes.c_int64, P, P, P, P, P, ci]
+    lib.oracle_fragments_fixed.argtypes = [P, P, ci, ci, ci, ci, P, ctypes.c_int64, P, P, P, P, P, ci, ci]
     lib.oracle_fragments_fixed.restype = ci
-    lib.oracle_backward.argtypes = [P, i64, P, ci, ci, ci, ci, P, i64, P, P, P, P, P, ci]
+    lib.oracle_backward.argtypes = [P, i64, P, ci, ci, ci, ci, P, i64, P, P, P, P, P, ci, ci]
     lib.oracle_backward.restype = ci
     lib.oracle_points_rasterize.argtypes = [P, i64, P, P, ci, ci, ci, ctypes.c_double, ci, P, i64, P, P, P, P, ci]
     lib.oracle_points_rasterize.restype = ci
@@ -89,8 +89,14 @@ def _i64(a):
     return np.ascontiguousarray(a, dtype=np.int64)
 
 
+# Rasterizer options (bits; see oracle_rast.c for their definitions)
+PERSPECTIVE_CORRECT = 0x100
+CLIP_BARYCENTRIC = 0x200
+CULL_BACKFACES = 0x400
+
+
 def rasterize(verts, faces, first_idx, num_faces, image_size, blur_radius, faces_per_pixel,
-              pixels=None, nthreads: Optional[int] = None):
+              pixels=None, nthreads: Optional[int] = None, options: int = 0):
     """Brute-force FP64 rasterization.
 
     verts (V,3) (float32 inputs are promoted exactly), faces (F,3) global ids,
@@ -117,7 +123,7 @@ def rasterize(verts, faces, first_idx, num_faces, image_size, blur_radius, faces
     nh = np.empty((npix,), np.int64)
     rc = lib.oracle_rasterize(_ptr(v), v.shape[0], _ptr(f), f.shape[0], _ptr(fi), _ptr(nf), N, H, W,
                               float(blur_radius), K, _ptr(pix), npix, _ptr(p2f), _ptr(zbuf), _ptr(bary),
-                              _ptr(dists), _ptr(amb), _ptr(nh), nthreads or default_threads())
+                              _ptr(dists), _ptr(amb), _ptr(nh), int(options), nthreads or default_threads())
     if rc != 0:
         raise ValueError("oracle_rasterize rejected its arguments")
     out = dict(p2f=p2f, zbuf=zbuf, bary=bary, dists=dists, amb=amb, nhits=nh)
@@ -126,7 +132,7 @@ def rasterize(verts, faces, first_idx, num_faces, image_size, blur_radius, faces
     return out
 
 
-def fragments_fixed(verts, faces, image_size, p2f, nthreads: Optional[int] = None, pixels=None):
+def fragments_fixed(verts, faces, image_size, p2f, nthreads: Optional[int] = None, pixels=None, options: int = 0):
     """zbuf, bary, dists (float64) and the per-slot edge-tie mask for a given
     face choice p2f (N,H,W,K); the forward map with the selection frozen.
     With ``pixels`` (linear pixel ids), p2f is (npix,K) rows of those pixels."""
@@ -144,12 +150,13 @@ def fragments_fixed(verts, faces, image_size, p2f, nthreads: Optional[int] = Non
     dists = np.empty(p.shape, np.float64)
     tie = np.empty(p.shape, np.uint8)
     lib.oracle_fragments_fixed(_ptr(v), _ptr(f), N, H, W, K, _ptr(pix), 0 if pix is None else pix.shape[0],
-                               _ptr(p), _ptr(zbuf), _ptr(bary), _ptr(dists), _ptr(tie), nthreads or default_threads())
+                               _ptr(p), _ptr(zbuf), _ptr(bary), _ptr(dists), _ptr(tie), int(options),
+                               nthreads or default_threads())
     return zbuf, bary, dists, tie
 
 
 def backward(verts, faces, image_size, p2f, grad_zbuf=None, grad_bary=None, grad_dists=None,
-             nthreads: Optional[int] = None, pixels=None, N: Optional[int] = None):
+             nthreads: Optional[int] = None, pixels=None, N: Optional[int] = None, options: int = 0):
     """Analytic FP64 dL/dverts (V,3) for L = <gz,zbuf> + <gb,bary> + <gd,dists>
     over the slots of p2f (N,H,W,K).  With ``pixels`` (linear pixel ids),
     p2f and the grads are (npix,K[,3]) rows of those pixels instead; N is
@@ -170,7 +177,8 @@ def backward(verts, faces, image_size, p2f, grad_zbuf=None, grad_bary=None, grad
     gd = None if grad_dists is None else _f64(grad_dists)
     out = np.empty(v.shape, np.float64)
     rc = lib.oracle_backward(_ptr(v), v.shape[0], _ptr(f), N, H, W, K, _ptr(pix), 0 if pix is None else pix.shape[0],
-                             _ptr(p), _ptr(gz), _ptr(gb), _ptr(gd), _ptr(out), nthreads or default_threads())
+                             _ptr(p), _ptr(gz), _ptr(gb), _ptr(gd), _ptr(out), int(options),
+                             nthreads or default_threads())
     if rc != 0:
         raise MemoryError("oracle_backward failed")
     return out

@@ -32,6 +32,21 @@
  *  - empty slots: face id -1 and -1 in zbuf, all three bary and dists
  *  - face ids are packed global ids (indices into the packed face array)
  *
+ * Rasterizer options (bits of `opts`; the paper fixes none of them, these are
+ * the readings):
+ *  - ORC_CULL: a face whose doubled signed area E in the x-y NDC plane is
+ *    positive never counts (with +x to the left, E < 0 is anticlockwise as
+ *    the image is displayed, the usual front-facing order)
+ *  - ORC_PERSPECTIVE: the barycentrics are perspective-corrected,
+ *    w'_i = (w_i / z_i) / sum_j (w_j / z_j) with the vertex depths z_i; a face
+ *    with a vertex at z <= 0 never counts, nor does a pair whose
+ *    sum_j (w_j / z_j) is not positive
+ *  - ORC_CLIP: the barycentrics (after the correction) are clipped,
+ *    w''_i = max(w_i, 0) / sum_j max(w_j, 0)
+ *  - z is interpolated with the final barycentrics, and the z >= 0 test and
+ *    the order use it; "inside" and dists keep using the raw barycentrics
+ *    and the geometry
+ *
  * Ambiguity mask (decision margin tau = 1e-6 in linear NDC units): a pixel is
  * flagged when a rounding-level change of the inputs could change its face
  * selection; parity of the face ids is only claimed on unflagged pixels.
@@ -44,6 +59,8 @@
  *    M5 some face has abs(abs(E) - 1e-8) < 1e-3 * 1e-8
  *    M6 (per slot, gradients only) the two smallest edge distances of the
  *       slot's face differ by less than tau (in linear units)
+ *    M7 (perspective correction) a face that passes the coverage test has a
+ *       vertex depth within tau of 0, or sum_j (w_j / z_j) within tau of 0
  */
 #include <math.h>
 #include <stdint.h>
@@ -61,6 +78,11 @@
 #define AMB_M3 4
 #define AMB_M4 8
 #define AMB_M5 16
+#define AMB_M7 64
+
+#define ORC_PERSPECTIVE 0x100
+#define ORC_CLIP 0x200
+#define ORC_CULL 0x400
 
 typedef struct {
     double z;
@@ -95,7 +117,13 @@ static double seg_d2(double px, double py, double sx, double sy, double tx, doub
 
 typedef struct {
     double E;
-    double w[3];
+    double w[3];  /* raw screen-space barycentrics */
+    double wp[3]; /* after the perspective correction (= w without it) */
+    double wf[3]; /* final: after the correction and the clipping */
+    double D;     /* sum_j w_j / z_j (perspective correction) */
+    double M;     /* sum_j max(wp_j, 0) (clipping) */
+    double zf;    /* depth interpolated with wf */
+    int opts_ok;  /* the options admit the pair */
     double z;
     double d2;
     double de[3]; /* squared distance to each edge e0=(a,b), e1=(b,c), e2=(c,a) */
@@ -104,8 +132,41 @@ typedef struct {
     int argmin; /* lowest edge index among the minimal ones */
 } eval_t;
 
-/* Evaluate face (a, b, c) at pixel p.  Returns 0 if the face is degenerate. */
-static int eval_face(const double* a, const double* b, const double* c, double px, double py, eval_t* ev) {
+/* The options' barycentrics and depth from the raw ones (see the header). */
+static void apply_options(int opts, const double* a, const double* b, const double* c, eval_t* ev) {
+    const double Z[3] = {a[2], b[2], c[2]};
+    ev->opts_ok = 1;
+    ev->D = 1.0;
+    ev->M = 1.0;
+    for (int i = 0; i < 3; ++i) ev->wp[i] = ev->w[i];
+    if (opts & ORC_PERSPECTIVE) {
+        if (!(Z[0] > 0.0 && Z[1] > 0.0 && Z[2] > 0.0)) {
+            ev->opts_ok = 0;
+        } else {
+            double u[3];
+            for (int i = 0; i < 3; ++i) u[i] = ev->w[i] / Z[i];
+            ev->D = u[0] + u[1] + u[2];
+            if (!(ev->D > 0.0)) ev->opts_ok = 0;
+            else
+                for (int i = 0; i < 3; ++i) ev->wp[i] = u[i] / ev->D;
+        }
+    }
+    for (int i = 0; i < 3; ++i) ev->wf[i] = ev->wp[i];
+    if ((opts & ORC_CLIP) && ev->opts_ok) {
+        double m[3];
+        for (int i = 0; i < 3; ++i) m[i] = ev->wp[i] > 0.0 ? ev->wp[i] : 0.0;
+        ev->M = m[0] + m[1] + m[2];
+        if (!(ev->M > 0.0)) ev->opts_ok = 0;
+        else
+            for (int i = 0; i < 3; ++i) ev->wf[i] = m[i] / ev->M;
+    }
+    ev->zf = ev->wf[0] * Z[0] + ev->wf[1] * Z[1] + ev->wf[2] * Z[2];
+}
+
+/* Evaluate face (a, b, c) at pixel p under the options.  Returns 0 if the
+ * face is degenerate. */
+static int eval_face(const double* a, const double* b, const double* c, double px, double py, int opts,
+                          eval_t* ev) {
     double E = cross2(b[0] - a[0], b[1] - a[1], c[0] - a[0], c[1] - a[1]);
     ev->E = E;
     if (fabs(E) < ORC_EPS_AREA) return 0;
@@ -125,6 +186,7 @@ static int eval_face(const double* a, const double* b, const double* c, double p
     if (ev->de[2] < ev->de[am]) am = 2;
     ev->argmin = am;
     ev->d2 = ev->de[am];
+    apply_options(opts, a, b, c, ev);
     return 1;
 }
 
@@ -157,7 +219,7 @@ int oracle_rasterize(const double* verts, int64_t V, const int64_t* faces, int64
                      const int64_t* first, const int64_t* nfaces, int N, int H, int W,
                      double blur, int K, const int64_t* pix, int64_t npix,
                      int64_t* p2f, double* zbuf, double* bary, double* dists,
-                     uint8_t* amb, int64_t* nhits, int nthreads) {
+                     uint8_t* amb, int64_t* nhits, int opts, int nthreads) {
     if (N < 0 || H <= 0 || W <= 0 || K <= 0 || blur < 0.0) return -1;
     int64_t total = (int64_t)N * H * W;
     if (pix == NULL) npix = total;
@@ -192,9 +254,10 @@ int oracle_rasterize(const double* verts, int64_t V, const int64_t* faces, int64
                 load_vert(verts, faces[3 * f + 1], b);
                 load_vert(verts, faces[3 * f + 2], cc);
                 eval_t ev;
-                int ok = eval_face(a, b, cc, px, py, &ev);
+                int ok = eval_face(a, b, cc, px, py, opts, &ev);
                 if (fabs(fabs(ev.E) - ORC_EPS_AREA) < 1e-3 * ORC_EPS_AREA) am |= AMB_M5;
                 if (!ok) continue;
+                if ((opts & ORC_CULL) && ev.E > 0.0) continue;
                 double dist = sqrt(ev.d2);
                 if (blur == 0.0) {
                     if (dist < ORC_TAU) am |= AMB_M1;
@@ -203,8 +266,14 @@ int oracle_rasterize(const double* verts, int64_t V, const int64_t* faces, int64
                 }
                 int covers = ev.inside || (ev.d2 < blur);
                 if (!covers) continue;
-                if (fabs(ev.z) < ORC_TAU) am |= AMB_M4;
-                if (ev.z < 0.0) continue;
+                if (opts & ORC_PERSPECTIVE) {
+                    if (fabs(a[2]) < ORC_TAU || fabs(b[2]) < ORC_TAU || fabs(cc[2]) < ORC_TAU ||
+                        fabs(ev.D) < ORC_TAU)
+                        am |= AMB_M7;
+                }
+                if (!ev.opts_ok) continue;
+                if (fabs(ev.zf) < ORC_TAU) am |= AMB_M4;
+                if (ev.zf < 0.0) continue;
                 if (nh == cap) {
                     cap *= 2;
                     hit_t* nhp = (hit_t*)realloc(hits, sizeof(hit_t) * cap);
@@ -215,11 +284,11 @@ int oracle_rasterize(const double* verts, int64_t V, const int64_t* faces, int64
                     hits = nhp;
                 }
                 hit_t* h = &hits[nh++];
-                h->z = ev.z;
+                h->z = ev.zf;
                 h->f = f;
-                h->w[0] = ev.w[0];
-                h->w[1] = ev.w[1];
-                h->w[2] = ev.w[2];
+                h->w[0] = ev.wf[0];
+                h->w[1] = ev.wf[1];
+                h->w[2] = ev.wf[2];
                 h->sd = ev.inside ? -ev.d2 : ev.d2;
             }
             qsort(hits, (size_t)nh, sizeof(hit_t), hit_cmp);
@@ -263,7 +332,7 @@ int oracle_rasterize(const double* verts, int64_t V, const int64_t* faces, int64
  */
 int oracle_fragments_fixed(const double* verts, const int64_t* faces, int N, int H, int W, int K,
                            const int64_t* pix, int64_t npix, const int64_t* p2f, double* zbuf, double* bary,
-                           double* dists, uint8_t* tie, int nthreads) {
+                           double* dists, uint8_t* tie, int opts, int nthreads) {
     int64_t S = pix ? npix * K : (int64_t)N * H * W * K;
 #pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
     for (int64_t s = 0; s < S; ++s) {
@@ -284,18 +353,19 @@ int oracle_fragments_fixed(const double* verts, const int64_t* faces, int N, int
         load_vert(verts, faces[3 * f + 1], b);
         load_vert(verts, faces[3 * f + 2], c);
         eval_t ev;
-        if (!eval_face(a, b, c, px, py, &ev)) {
-            /* a degenerate face can only appear here if the caller's selection
-             * came from perturbed inputs; report NaN so it cannot go unnoticed */
+        if (!eval_face(a, b, c, px, py, opts, &ev) || !ev.opts_ok) {
+            /* a degenerate face (or one the options exclude) can only appear
+             * here if the caller's selection came from perturbed inputs;
+             * report NaN so it cannot go unnoticed */
             zbuf[s] = NAN;
             bary[3 * s] = bary[3 * s + 1] = bary[3 * s + 2] = NAN;
             dists[s] = NAN;
             continue;
         }
-        zbuf[s] = ev.z;
-        bary[3 * s + 0] = ev.w[0];
-        bary[3 * s + 1] = ev.w[1];
-        bary[3 * s + 2] = ev.w[2];
+        zbuf[s] = ev.zf;
+        bary[3 * s + 0] = ev.wf[0];
+        bary[3 * s + 1] = ev.wf[1];
+        bary[3 * s + 2] = ev.wf[2];
         dists[s] = ev.inside ? -ev.d2 : ev.d2;
         if (tie) {
             double d[3] = {sqrt(ev.de[0]), sqrt(ev.de[1]), sqrt(ev.de[2])};
@@ -324,11 +394,19 @@ int oracle_fragments_fixed(const double* verts, const int64_t* faces, int N, int
  *   dists = s * d2 with s = -1 inside, +1 outside (piecewise constant);
  *   on the nearest edge (s0, t) with closest point q = s0 + u (t - s0):
  *   d d2/d s0 = -2 (1-u) (p-q),  d d2/d t = -2 u (p-q)   (also at clamped u)
+ * With the options the outputs are the final barycentrics wf and
+ * zf = sum_i wf_i z_i; with G_i = dL/dwf_i = gb_i + gz z_i (and dL/dz_i += gz wf_i):
+ *   clipping wf_i = m_i / M, m_i = max(wp_i, 0):
+ *     dL/dwp_j = (G_j - sum_i G_i wf_i) / M where wp_j > 0, else 0
+ *   correction wp_i = u_i / D, u_i = w_i / z_i, D = sum_j u_j:
+ *     dL/du_j = (Gp_j - sum_i Gp_i wp_i) / D,
+ *     dL/dw_j = dL/du_j / z_j,  dL/dz_j += -dL/du_j w_j / z_j^2
+ *   and dL/dw (raw) enters the xy chain above.
  */
 int oracle_backward(const double* verts, int64_t V, const int64_t* faces, int N, int H, int W, int K,
                     const int64_t* pix, int64_t npix,
                     const int64_t* p2f, const double* gz, const double* gb, const double* gd,
-                    double* grad_verts, int nthreads) {
+                    double* grad_verts, int opts, int nthreads) {
     int nt = nthreads > 0 ? nthreads : 1;
     /* pix == NULL: slots cover every pixel in order, S = N*H*W*K; otherwise
      * slot s belongs to linear pixel pix[s / K] and S = npix*K */
@@ -359,7 +437,7 @@ int oracle_backward(const double* verts, int64_t V, const int64_t* faces, int N,
             double P[3][3];
             for (int j = 0; j < 3; ++j) load_vert(verts, vi[j], P[j]);
             eval_t ev;
-            if (!eval_face(P[0], P[1], P[2], px, py, &ev)) continue;
+            if (!eval_face(P[0], P[1], P[2], px, py, opts, &ev) || !ev.opts_ok) continue;
             double E = ev.E;
             /* relative positions r_j = P_j - p */
             double rx[3], ry[3];
@@ -383,6 +461,19 @@ int oracle_backward(const double* verts, int64_t V, const int64_t* faces, int N,
             G[0] = gb0 + gzs * Z[0];
             G[1] = gb1 + gzs * Z[1];
             G[2] = gb2 + gzs * Z[2];
+            for (int j = 0; j < 3; ++j) g[3 * vi[j] + 2] += gzs * ev.wf[j];
+            if (opts & ORC_CLIP) {
+                double S = G[0] * ev.wf[0] + G[1] * ev.wf[1] + G[2] * ev.wf[2];
+                for (int i = 0; i < 3; ++i) G[i] = ev.wp[i] > 0.0 ? (G[i] - S) / ev.M : 0.0;
+            }
+            if (opts & ORC_PERSPECTIVE) {
+                double S = G[0] * ev.wp[0] + G[1] * ev.wp[1] + G[2] * ev.wp[2];
+                for (int i = 0; i < 3; ++i) {
+                    double gu = (G[i] - S) / ev.D;
+                    G[i] = gu / Z[i];
+                    g[3 * vi[i] + 2] += -gu * ev.w[i] / (Z[i] * Z[i]);
+                }
+            }
             for (int j = 0; j < 3; ++j) {
                 for (int x = 0; x < 2; ++x) {
                     double dE = de[0][j][x] + de[1][j][x] + de[2][j][x];
@@ -393,7 +484,6 @@ int oracle_backward(const double* verts, int64_t V, const int64_t* faces, int N,
                     }
                     g[3 * vi[j] + x] += acc;
                 }
-                g[3 * vi[j] + 2] += gzs * ev.w[j];
             }
             if (gds != 0.0) {
                 double sgn = ev.inside ? -1.0 : 1.0;
