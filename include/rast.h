@@ -78,6 +78,29 @@ enum rast_status {
 #define RAST_SCHED_PERSISTENT 1 /* device-sized grid pulling tiles, most-loaded bins first */
 
 /*
+ * Rasterizer options: the `options` word of rasterize_meshes_fwd, or-ed into
+ * the `flags` word of rasterize_meshes_bwd (which must name the forward's).
+ * The paper leaves them to the camera and shader (Section 3.2); they are
+ * defined here as follows.
+ *  - RAST_PERSPECTIVE_CORRECT: barycentrics corrected for perspective,
+ *    w'_i = (w_i / z_i) / sum_j (w_j / z_j) with the vertex depths z_i; a face
+ *    with a vertex at z <= 0 never counts, nor does a (pixel, face) pair whose
+ *    sum_j (w_j / z_j) is not positive.
+ *  - RAST_CLIP_BARYCENTRIC: barycentrics (after the correction) clipped,
+ *    w''_i = max(w_i, 0) / sum_j max(w_j, 0): a pixel outside the face within
+ *    the blur radius takes the nearest point of the face.
+ *  - RAST_CULL_BACKFACES: a face whose doubled signed area E in the x-y NDC
+ *    plane is positive never counts (E < 0 is anticlockwise as the image is
+ *    displayed, +x pointing left).
+ * With the correction or the clipping, bary holds the final barycentrics,
+ * zbuf = sum_i w_i z_i with them, and the z >= 0 test and the slot order use
+ * that z; "inside" and dists stay geometric (raw barycentrics, xy distance).
+ */
+#define RAST_PERSPECTIVE_CORRECT 0x100
+#define RAST_CLIP_BARYCENTRIC 0x200
+#define RAST_CULL_BACKFACES 0x400
+
+/*
  * Bytes of workspace needed by rasterize_meshes_fwd / _bwd / rast_bin_count
  * for these sizes (one size serves all three).  bin_size 0 selects the single-pass form (every pixel
  * against every face of its mesh).  bin_size > 0 must be a multiple of
@@ -96,6 +119,8 @@ int rast_workspace_size(int N, int H, int W, int64_t F, int bin_size, int max_fa
  *   faces_per_pixel K in [1, RAST_KMAX];
  *   bin_size 0 or a multiple of RAST_TILE <= RAST_MAX_BIN; max_faces_per_bin > 0 if bin_size > 0;
  *   sched: RAST_SCHED_GRID or RAST_SCHED_PERSISTENT (ignored when bin_size == 0).
+ *   options: 0 or an or of RAST_PERSPECTIVE_CORRECT, RAST_CLIP_BARYCENTRIC,
+ *   RAST_CULL_BACKFACES (any other bit: RAST_EINVAL).
  *   Outputs, row-major, fully overwritten:
  *     pix_to_face (N,H,W,K) i32 packed face id or -1
  *     zbuf (N,H,W,K) f32, bary (N,H,W,K,3) f32, dists (N,H,W,K) f32
@@ -106,8 +131,8 @@ int rast_workspace_size(int N, int H, int W, int64_t F, int bin_size, int max_fa
 int rasterize_meshes_fwd(const float* verts_packed, int64_t V, const int32_t* faces_packed, int64_t F,
                          const int64_t* mesh_to_face_first_idx, const int64_t* num_faces_per_mesh,
                          int N, int H, int W, float blur_radius, int faces_per_pixel, int bin_size,
-                         int max_faces_per_bin, int sched, int32_t* pix_to_face, float* zbuf, float* bary,
-                         float* dists, void* workspace, size_t workspace_bytes, void* stream);
+                         int max_faces_per_bin, int sched, int options, int32_t* pix_to_face, float* zbuf,
+                         float* bary, float* dists, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * Backward (paper, Section 3.2: gradients with respect to the inputs, from the
@@ -123,12 +148,14 @@ int rasterize_meshes_fwd(const float* verts_packed, int64_t V, const int32_t* fa
  *   face's pixel box; > 0: it re-bins the faces and streams each bin's slots).
  *   A bin overflow sets RAST_EOVERFLOW in the workspace status and leaves
  *   grad_verts incomplete.
- *   flags: 0 or RAST_BWD_REUSE_FORWARD.  With RAST_BWD_REUSE_FORWARD and
+ *   flags: the forward's options, or-ed with RAST_BWD_REUSE_FORWARD or not;
+ *   the gradient then runs through the options' barycentrics and depth.
+ *   With RAST_BWD_REUSE_FORWARD and
  *   bin_size > 0, `workspace` must be the one the forward that produced
  *   pix_to_face used, not used by any call since, and the vertices must not
  *   have changed: the backward then takes the forward's face records and bins
  *   (and keeps its status) instead of rebuilding them.  The forward stamps its
- *   face count, image size, bin size, capacity and blur radius into the
+ *   face count, image size, bin size, capacity, blur radius and options into the
  *   workspace; if they differ from this call's, the status becomes RAST_EREUSE
  *   and grad_verts is left zero.  Changed vertex contents cannot be detected.
  *   With bin_size == 0 the flag has no effect.
@@ -146,7 +173,8 @@ int rasterize_meshes_bwd(const float* verts_packed, int64_t V, const int32_t* fa
 /*
  * Coarse pass only, counting: fills the workspace status with the largest
  * number of faces any bin of this bin_size receives (read it with
- * rast_query_status).  Used to size max_faces_per_bin exactly.  Needs
+ * rast_query_status).  Used to size max_faces_per_bin exactly (without
+ * culling; with RAST_CULL_BACKFACES it is an upper bound).  Needs
  * rast_workspace_size(N, H, W, F, bin_size, 1) bytes.
  */
 int rast_bin_count(const float* verts_packed, int64_t V, const int32_t* faces_packed, int64_t F,

@@ -28,6 +28,9 @@ RAST_TILE = 8
 RAST_MAX_BIN = 512
 RAST_SCHED_GRID = 0
 RAST_SCHED_PERSISTENT = 1
+RAST_PERSPECTIVE_CORRECT = 0x100
+RAST_CLIP_BARYCENTRIC = 0x200
+RAST_CULL_BACKFACES = 0x400
 
 _lock = threading.Lock()
 _lib = None
@@ -57,7 +60,7 @@ def lib() -> ctypes.CDLL:
         cf = ctypes.c_float
         sz = ctypes.c_size_t
         L.rast_workspace_size.argtypes = [ci, ci, ci, i64, ci, ci, ctypes.POINTER(sz)]
-        L.rasterize_meshes_fwd.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, cf, ci, ci, ci, ci, P, P, P, P, P, sz, P]
+        L.rasterize_meshes_fwd.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, cf, ci, ci, ci, ci, ci, P, P, P, P, P, sz, P]
         L.rasterize_meshes_bwd.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, cf, ci, ci, ci, ci, P, P, P, P, P, P, sz, P]
         L.rast_bin_count.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, cf, ci, P, sz, P]
         L.rast_query_status.argtypes = [P, ctypes.POINTER(ci), ctypes.POINTER(ci), P]
@@ -154,7 +157,7 @@ def _mesh_shapes(verts, faces, first_idx, num_faces):
 
 
 def rasterize_meshes_fwd(verts, faces, first_idx, num_faces, H, W, blur_radius, K, bin_size, max_faces_per_bin,
-                         sched, pix_to_face, zbuf, bary, dists, workspace):
+                         sched, pix_to_face, zbuf, bary, dists, workspace, options=0):
     dev = verts.device
     _require(verts, "verts", torch.float32, dev)
     _require(faces, "faces", torch.int32, dev)
@@ -169,8 +172,8 @@ def rasterize_meshes_fwd(verts, faces, first_idx, num_faces, H, W, blur_radius, 
     _same_shape("N,H,W,K", shp + (3,), (bary, "bary"))
     rc = lib().rasterize_meshes_fwd(_p(verts), verts.shape[0], _p(faces), faces.shape[0], _p(first_idx),
                                     _p(num_faces), int(N), int(H), int(W), float(blur_radius), int(K), int(bin_size),
-                                    int(max_faces_per_bin or 0), int(sched), _p(pix_to_face), _p(zbuf), _p(bary),
-                                    _p(dists), _p(workspace), workspace.numel(), _stream(dev))
+                                    int(max_faces_per_bin or 0), int(sched), int(options), _p(pix_to_face), _p(zbuf),
+                                    _p(bary), _p(dists), _p(workspace), workspace.numel(), _stream(dev))
     _check("rasterize_meshes_fwd", rc)
 
 

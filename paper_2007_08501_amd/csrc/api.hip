@@ -101,11 +101,12 @@ thread_local KernelEvents tl_events;
 
 }  // namespace
 
-static rast::BinSig bin_signature(int64_t F, int N, int H, int W, int bs, int M, float blur) {
+static rast::BinSig bin_signature(int64_t F, int N, int H, int W, int bs, int M, float blur, int opts) {
     rast::BinSig g;
     uint32_t bb;
     memcpy(&bb, &blur, sizeof(bb));
-    const int w[rast::kSigWords] = {rast::kSigMarker, (int)F, N, H, W, bs, M, (int)bb};
+    // the options change which faces count: they share the marker word
+    const int w[rast::kSigWords] = {rast::kSigMarker ^ opts, (int)F, N, H, W, bs, M, (int)bb};
     for (int i = 0; i < rast::kSigWords; ++i) g.w[i] = w[i];
     return g;
 }
@@ -126,9 +127,10 @@ int rast_workspace_size(int N, int H, int W, int64_t F, int bin_size, int max_fa
 int rasterize_meshes_fwd(const float* verts_packed, int64_t V, const int32_t* faces_packed, int64_t F,
                          const int64_t* mesh_to_face_first_idx, const int64_t* num_faces_per_mesh, int N, int H,
                          int W, float blur_radius, int faces_per_pixel, int bin_size, int max_faces_per_bin,
-                         int sched, int32_t* pix_to_face, float* zbuf, float* bary, float* dists, void* workspace,
-                         size_t workspace_bytes, void* stream) {
+                         int sched, int options, int32_t* pix_to_face, float* zbuf, float* bary, float* dists,
+                         void* workspace, size_t workspace_bytes, void* stream) {
     if (bad_dims(N, H, W, faces_per_pixel)) return RAST_EINVAL;
+    if ((options & ~rast::kOptMask) != 0) return RAST_EINVAL;
     if (V < 0 || V > INT32_MAX || F < 0 || F > INT32_MAX) return RAST_EINVAL;
     if ((V > 0 && verts_packed == nullptr) || (F > 0 && faces_packed == nullptr)) return RAST_EINVAL;
     if (mesh_to_face_first_idx == nullptr || num_faces_per_mesh == nullptr) return RAST_EINVAL;
@@ -150,10 +152,10 @@ int rasterize_meshes_fwd(const float* verts_packed, int64_t V, const int32_t* fa
 
     // the header carries this call's binning signature for a backward that reuses the bins
     hipError_t e = rast::launch_header_init(
-        hdr, bin_signature(F, N, H, W, bin_size, bin_size > 0 ? max_faces_per_bin : 0, blur_radius), s);
+        hdr, bin_signature(F, N, H, W, bin_size, bin_size > 0 ? max_faces_per_bin : 0, blur_radius, options), s);
     if (e != hipSuccess) return RAST_EHIP;
     e = rast::launch_face_setup(verts_packed, V, faces_packed, F, mesh_to_face_first_idx, num_faces_per_mesh, N,
-                                sqrtf(blur_radius), recs, hdr, s);
+                                sqrtf(blur_radius), options, recs, hdr, s);
     if (e != hipSuccess) return RAST_EHIP;
     int* counts = nullptr;
     int* lists = nullptr;
@@ -164,7 +166,8 @@ int rasterize_meshes_fwd(const float* verts_packed, int64_t V, const int32_t* fa
         if (e != hipSuccess) return RAST_EHIP;
     }
     e = rast::launch_fine(recs, mesh_to_face_first_idx, num_faces_per_mesh, counts, lists, F, N, H, W,
-                          faces_per_pixel, blur_radius, bin_size, max_faces_per_bin, sched, (int*)(ws + L.order),
+                          faces_per_pixel, blur_radius, options, bin_size, max_faces_per_bin, sched,
+                          (int*)(ws + L.order),
                           (int*)(ws + L.hist), hdr, n_workers, pix_to_face, zbuf, bary, dists, s,
                           tl_events.begin[RAST_KERNEL_FINE], tl_events.end[RAST_KERNEL_FINE]);
     return hip_rc(e);
@@ -182,7 +185,8 @@ int rasterize_meshes_bwd(const float* verts_packed, int64_t V, const int32_t* fa
         return RAST_EINVAL;
     if (mesh_to_face_first_idx == nullptr || num_faces_per_mesh == nullptr) return RAST_EINVAL;
     if (pix_to_face == nullptr) return RAST_EINVAL;
-    if ((flags & ~RAST_BWD_REUSE_FORWARD) != 0) return RAST_EINVAL;
+    if ((flags & ~(RAST_BWD_REUSE_FORWARD | rast::kOptMask)) != 0) return RAST_EINVAL;
+    const int options = flags & rast::kOptMask;
     if (!(blur_radius >= 0.0f) || !isfinite(blur_radius)) return RAST_EINVAL;
     if (bin_size < 0 || bin_size > RAST_MAX_BIN || (bin_size % RAST_TILE) != 0) return RAST_EINVAL;
     if (bin_size > 0 && max_faces_per_bin < 1) return RAST_EINVAL;
@@ -195,10 +199,10 @@ int rasterize_meshes_bwd(const float* verts_packed, int64_t V, const int32_t* fa
     char* ws = (char*)workspace;
     return hip_rc(rast::launch_backward(
         verts_packed, V, faces_packed, F, mesh_to_face_first_idx, num_faces_per_mesh, N, H, W, faces_per_pixel,
-        blur_radius, bin_size, max_faces_per_bin, pix_to_face, grad_zbuf, grad_bary, grad_dists, grad_verts,
+        blur_radius, options, bin_size, max_faces_per_bin, pix_to_face, grad_zbuf, grad_bary, grad_dists, grad_verts,
         (int*)(ws + L.hdr), (rast::FaceRec*)(ws + L.recs), (int*)(ws + L.counts), (int*)(ws + L.lists),
         (float*)(ws + L.partial), (int*)(ws + L.big), (flags & RAST_BWD_REUSE_FORWARD) != 0,
-        bin_signature(F, N, H, W, bin_size, bin_size > 0 ? max_faces_per_bin : 0, blur_radius), s,
+        bin_signature(F, N, H, W, bin_size, bin_size > 0 ? max_faces_per_bin : 0, blur_radius, options), s,
         tl_events.begin[RAST_KERNEL_BWD], tl_events.end[RAST_KERNEL_BWD]));
 }
 
@@ -230,7 +234,7 @@ int rast_bin_count(const float* verts_packed, int64_t V, const int32_t* faces_pa
     hipError_t e = rast::launch_fill_i32(hdr, rast::kHdrWords, 0, s);
     if (e != hipSuccess) return RAST_EHIP;
     e = rast::launch_face_setup(verts_packed, V, faces_packed, F, mesh_to_face_first_idx, num_faces_per_mesh, N,
-                                sqrtf(blur_radius), recs, hdr, s);
+                                sqrtf(blur_radius), 0, recs, hdr, s);
     if (e != hipSuccess) return RAST_EHIP;
     // M = 0: count only, no list writes
     return hip_rc(rast::launch_binning(recs, F, N, H, W, bin_size, 0, (int*)(ws + L.counts), nullptr, hdr, s));

@@ -25,6 +25,12 @@ namespace rast {
 constexpr double kEpsArea = 1e-8;  // faces with abs(2 * signed area) below this never count
 constexpr int kTile = 8;           // forward work unit: 8x8 pixels = one wave64
 
+// Rasterizer options (the bits of the ABI's options / flags words).
+constexpr int kOptPersp = 0x100;  // perspective-correct barycentrics
+constexpr int kOptClip = 0x200;   // barycentrics clipped to [0, 1] and renormalised
+constexpr int kOptCull = 0x400;   // back faces (E > 0) never count
+constexpr int kOptMask = kOptPersp | kOptClip | kOptCull;
+
 // Workspace header (int32 words); the header occupies the first 256 bytes.
 enum : int {
     kHdrStatus = 0,     // sticky status bits (kStatOverflow | kStatMesh)
@@ -91,8 +97,11 @@ __device__ __forceinline__ bool finite3(float a, float b, float c) {
 }
 
 // Builds the record of face (a, b, c).  rb = sqrt(blur_radius) in NDC units.
+// Under the options a back face (E > 0: clockwise as the image is displayed,
+// +x being to the left) or, with the perspective correction, a face with a
+// vertex at z <= 0 never counts.
 __device__ __forceinline__ FaceRec make_rec(float ax, float ay, float az, float bx, float by, float bz, float cx,
-                                            float cy, float cz, float rb, int mesh) {
+                                            float cy, float cz, float rb, int mesh, int opts = 0) {
     FaceRec R;
     R.pa = make_double2(ax, ay);
     R.ab = make_double2((double)bx - (double)ax, (double)by - (double)ay);
@@ -100,6 +109,8 @@ __device__ __forceinline__ FaceRec make_rec(float ax, float ay, float az, float 
     R.E = R.ab.x * R.ac.y - R.ab.y * R.ac.x;
     bool ok = mesh >= 0 && fabs(R.E) >= kEpsArea && finite3(ax, ay, az) && finite3(bx, by, bz) &&
               finite3(cx, cy, cz);
+    if ((opts & kOptCull) && R.E > 0.0) ok = false;
+    if ((opts & kOptPersp) && !(az > 0.0f && bz > 0.0f && cz > 0.0f)) ok = false;
     R.az = az;
     R.mesh_ = ok ? mesh : -1;
     R.dz1 = bz - az;
@@ -218,24 +229,50 @@ __device__ __forceinline__ bool in_bbox(const FaceRec& R, const Pix& p) {
     return p.xf >= R.bb.x && p.xf <= R.bb.y && p.yf >= R.bb.z && p.yf <= R.bb.w;
 }
 
+// The options' barycentrics and depth from the raw ones (az the depth of
+// vertex a, dz1 / dz2 those of b and c relative to it): with the
+// perspective correction w_i <- (w_i / z_i) / sum_j (w_j / z_j), then with
+// clipping w_i <- max(w_i, 0) / sum_j max(w_j, 0); z is interpolated with the
+// result.  False when the options exclude the pair (a correction whose
+// denominator is not positive).
+__device__ __forceinline__ bool apply_opts(int opts, float az, float dz1, float dz2, float& w0, float& w1, float& w2,
+                                           float& z) {
+    if (opts & kOptPersp) {
+        const float u0 = w0 / az, u1 = w1 / (az + dz1), u2 = w2 / (az + dz2);
+        const float D = u0 + u1 + u2;
+        if (!(D > 0.0f)) return false;
+        w0 = u0 / D;
+        w1 = u1 / D;
+        w2 = u2 / D;
+    }
+    if (opts & kOptClip) {
+        const float m0 = fmaxf(w0, 0.0f), m1 = fmaxf(w1, 0.0f), m2 = fmaxf(w2, 0.0f);
+        const float M = m0 + m1 + m2;
+        if (!(M > 0.0f)) return false;
+        w0 = m0 / M;
+        w1 = m1 / M;
+        w2 = m2 / M;
+    }
+    z = fmaf(w2, dz2, w1 * dz1) + az;
+    return true;
+}
+
 // Does face R count for pixel p, given that p lies in R's grown box?  On
-// success z is its depth.
+// success z is its depth (under the options, if any).
 template <class Rec>
-__device__ __forceinline__ bool face_counts_in_box(const Rec& R, const Pix& p, float blur, float& z) {
+__device__ __forceinline__ bool face_counts_in_box(const Rec& R, const Pix& p, float blur, float& z, int opts = 0) {
     Eval b;
     eval_bary(R, p, b);
     z = b.z;
-    if (!(b.z >= 0.0f)) return false;
+    if (opts & (kOptPersp | kOptClip)) {
+        float w0 = b.w0, w1 = b.w1, w2 = b.w2;
+        if (!apply_opts(opts, R.az, R.dz1, R.dz2, w0, w1, w2, z)) return false;
+    }
+    if (!(z >= 0.0f)) return false;
     if (b.inside) return true;
     EdgeD ed;
     eval_edges(R, b, ed);
     return fminf(ed.d[0], fminf(ed.d[1], ed.d[2])) < blur;
-}
-
-// Does face R count for pixel p?  On success z is its depth.
-__device__ __forceinline__ bool face_counts(const FaceRec& R, const Pix& p, float blur, float& z) {
-    if (!in_bbox(R, p)) return false;
-    return face_counts_in_box(R, p, blur, z);
 }
 
 // Mesh of face f: the last n with first[n] <= f, if f lies in its range.

@@ -44,6 +44,7 @@ struct BwdArgs {
     int64_t V, F;
     int N, H, W, K;
     float rb;      // sqrt(blur_radius)
+    int opts;      // rasterizer options (kOpt*)
     // binned form
     const FaceRec* recs;
     const int* counts;
@@ -85,9 +86,54 @@ __device__ __forceinline__ void slot_grad(const BwdArgs& a, const Rec& R, const 
         gb2 = a.gb[3 * s + 2];
     }
     float gds = a.gd ? a.gd[s] : 0.0f;
+    // dL/dw for the output barycentrics; z = sum_i w_i z_i adds gz z_i
     float G0 = gb0 + gzs * vz[0];
     float G1 = gb1 + gzs * vz[1];
     float G2 = gb2 + gzs * vz[2];
+    if (a.opts & (kOptPersp | kOptClip)) {
+        // the outputs are the options' barycentrics: carry dL/dw back through
+        // the clipping and the correction to the raw ones (and to the depths)
+        const float w[3] = {ev.w0, ev.w1, ev.w2};
+        float wp[3] = {w[0], w[1], w[2]}, D = 1.0f;
+        if (a.opts & kOptPersp) {
+            const float u0 = w[0] / vz[0], u1 = w[1] / vz[1], u2 = w[2] / vz[2];
+            D = u0 + u1 + u2;
+            wp[0] = u0 / D;
+            wp[1] = u1 / D;
+            wp[2] = u2 / D;
+        }
+        float wf[3] = {wp[0], wp[1], wp[2]}, M = 1.0f;
+        if (a.opts & kOptClip) {
+            const float m0 = fmaxf(wp[0], 0.0f), m1 = fmaxf(wp[1], 0.0f), m2 = fmaxf(wp[2], 0.0f);
+            M = m0 + m1 + m2;
+            wf[0] = m0 / M;
+            wf[1] = m1 / M;
+            wf[2] = m2 / M;
+        }
+        g.gzv[0] += gzs * wf[0];
+        g.gzv[1] += gzs * wf[1];
+        g.gzv[2] += gzs * wf[2];
+        if (a.opts & kOptClip) {
+            const float S = G0 * wf[0] + G1 * wf[1] + G2 * wf[2];
+            G0 = wp[0] > 0.0f ? (G0 - S) / M : 0.0f;
+            G1 = wp[1] > 0.0f ? (G1 - S) / M : 0.0f;
+            G2 = wp[2] > 0.0f ? (G2 - S) / M : 0.0f;
+        }
+        if (a.opts & kOptPersp) {
+            const float S = G0 * wp[0] + G1 * wp[1] + G2 * wp[2];
+            const float q0 = (G0 - S) / D, q1 = (G1 - S) / D, q2 = (G2 - S) / D;
+            G0 = q0 / vz[0];
+            G1 = q1 / vz[1];
+            G2 = q2 / vz[2];
+            g.gzv[0] -= q0 * w[0] / (vz[0] * vz[0]);
+            g.gzv[1] -= q1 * w[1] / (vz[1] * vz[1]);
+            g.gzv[2] -= q2 * w[2] / (vz[2] * vz[2]);
+        }
+    } else {
+        g.gzv[0] += gzs * ev.w0;
+        g.gzv[1] += gzs * ev.w1;
+        g.gzv[2] += gzs * ev.w2;
+    }
     float Gw = G0 * ev.w0 + G1 * ev.w1 + G2 * ev.w2;
     float invE = R.invE;
     float H0 = (G0 - Gw) * invE, H1 = (G1 - Gw) * invE, H2 = (G2 - Gw) * invE;
@@ -108,9 +154,6 @@ __device__ __forceinline__ void slot_grad(const BwdArgs& a, const Rec& R, const 
     g.gy[1] += H0 * (-Rx[2]) + H2 * Rx[0];
     g.gx[2] += H0 * (-Ry[1]) + H1 * Ry[0];
     g.gy[2] += H0 * Rx[1] + H1 * (-Rx[0]);
-    g.gzv[0] += gzs * ev.w0;
-    g.gzv[1] += gzs * ev.w1;
-    g.gzv[2] += gzs * ev.w2;
     if (gds != 0.0f) {
         int e = ev.edge;
         int js = e, jt = e == 2 ? 0 : e + 1;
@@ -184,7 +227,7 @@ __device__ __forceinline__ bool load_face(const BwdArgs& a, int64_t f, FaceRec& 
     const float* P0 = a.verts + 3 * (int64_t)vi[0];
     const float* P1 = a.verts + 3 * (int64_t)vi[1];
     const float* P2 = a.verts + 3 * (int64_t)vi[2];
-    R = make_rec(P0[0], P0[1], P0[2], P1[0], P1[1], P1[2], P2[0], P2[1], P2[2], a.rb, n);
+    R = make_rec(P0[0], P0[1], P0[2], P1[0], P1[1], P1[2], P2[0], P2[1], P2[2], a.rb, n, a.opts);
     vz[0] = P0[2];
     vz[1] = P1[2];
     vz[2] = P2[2];
@@ -545,7 +588,7 @@ __global__ __launch_bounds__(kBwdBlock) void bwd_face_sum_kernel(BwdArgs a) {
 }
 
 hipError_t launch_backward(const float* verts, int64_t V, const int32_t* faces, int64_t F, const int64_t* first,
-                           const int64_t* nf, int N, int H, int W, int K, float blur, int bs, int M,
+                           const int64_t* nf, int N, int H, int W, int K, float blur, int opts, int bs, int M,
                            const int32_t* p2f, const float* gz, const float* gb, const float* gd, float* grad,
                            int* hdr, FaceRec* recs, int* counts, int* lists, float* partial, int* big,
                            bool reuse, const BinSig& sig, hipStream_t s, hipEvent_t eb, hipEvent_t ee) {
@@ -576,6 +619,7 @@ hipError_t launch_backward(const float* verts, int64_t V, const int32_t* faces, 
     a.W = W;
     a.K = K;
     a.rb = sqrtf(blur);
+    a.opts = opts;
     a.recs = recs;
     a.counts = counts;
     a.lists = lists;
@@ -597,7 +641,7 @@ hipError_t launch_backward(const float* verts, int64_t V, const int32_t* faces, 
         // the same face setup and binning as the forward (unless the forward's
         // are reused), then the two passes
         if (!reuse) {
-            e = launch_face_setup(verts, V, faces, F, first, nf, N, a.rb, recs, hdr, s);
+            e = launch_face_setup(verts, V, faces, F, first, nf, N, a.rb, opts, recs, hdr, s);
             if (e != hipSuccess) return e;
             e = launch_binning(recs, F, N, H, W, bs, M, counts, lists, hdr, s);
             if (e != hipSuccess) return e;

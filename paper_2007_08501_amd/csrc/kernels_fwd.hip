@@ -61,7 +61,7 @@ hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
 
 __global__ void face_setup_kernel(const float* __restrict__ verts, int64_t V, const int32_t* __restrict__ faces,
                                   int64_t F, const int64_t* __restrict__ first, const int64_t* __restrict__ nf, int N,
-                                  float rb, FaceRec* __restrict__ recs, int* __restrict__ hdr) {
+                                  float rb, int opts, FaceRec* __restrict__ recs, int* __restrict__ hdr) {
     int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (first != nullptr && f < N) {
         // mesh range check: inside [0, F] and ascending without overlap
@@ -86,15 +86,15 @@ __global__ void face_setup_kernel(const float* __restrict__ verts, int64_t V, co
     const float* a = verts + 3 * (int64_t)i0;
     const float* b = verts + 3 * (int64_t)i1;
     const float* c = verts + 3 * (int64_t)i2;
-    recs[f] = make_rec(a[0], a[1], a[2], b[0], b[1], b[2], c[0], c[1], c[2], rb, mesh);
+    recs[f] = make_rec(a[0], a[1], a[2], b[0], b[1], b[2], c[0], c[1], c[2], rb, mesh, opts);
 }
 
 hipError_t launch_face_setup(const float* verts, int64_t V, const int32_t* faces, int64_t F, const int64_t* first,
-                             const int64_t* nf, int N, float rb, FaceRec* recs, int* hdr, hipStream_t s) {
+                             const int64_t* nf, int N, float rb, int opts, FaceRec* recs, int* hdr, hipStream_t s) {
     int64_t n = F > N ? F : N;
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(face_setup_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, verts, V, faces, F,
-                       first, nf, N, rb, recs, hdr);
+                       first, nf, N, rb, opts, recs, hdr);
     return hipGetLastError();
 }
 
@@ -186,6 +186,7 @@ struct FineArgs {
     int64_t F;
     int N, H, W, K;
     float blur;
+    int opts;  // rasterizer options (kOpt*)
     int bs, nby, nbx, M;
     int tiles_x, tiles_y;
     int32_t* p2f;
@@ -236,7 +237,9 @@ constexpr int kStageG2 = 8;   // slots per pass for barycentrics and distances
 // below is a compile-time constant (the common case); otherwise K < KB is a
 // run-time value.  Addresses are 32-bit offsets from the tile's first
 // fragment, a wave-uniform base.
-template <int KB, bool EXACT>
+// OPT: the rasterizer options that change barycentrics and depth are on
+// (a separate instantiation, so that the default path carries no test for them).
+template <int KB, bool EXACT, bool OPT>
 __device__ __forceinline__ void write_fragments(const FineArgs& a, TileLds& L, const TopK<KB>& top, const Pix& p,
                                                 int n, int tx, int ty) {
     const int lane = threadIdx.x & 63;
@@ -327,6 +330,10 @@ __device__ __forceinline__ void write_fragments(const FineArgs& a, TileLds& L, c
                     w0 = ev.w0;
                     w1 = ev.w1;
                     w2 = ev.w2;
+                    if (OPT) {
+                        float zf;
+                        apply_opts(a.opts, R.az, R.dz1, R.dz2, w0, w1, w2, zf);
+                    }
                     d = ev.inside ? -ev.d2 : ev.d2;
                 }
                 sb[lane * SB + 3 * k + 0] = w0;
@@ -395,7 +402,7 @@ __device__ __forceinline__ void write_fragments(const FineArgs& a, TileLds& L, c
 //     faces that count into its register top-K.
 // Step 3 is where the arithmetic is; compacting the (pixel, face) pairs first
 // keeps lanes from idling on faces that miss their pixel.
-template <int KB, bool BINNED, bool EXACT>
+template <int KB, bool BINNED, bool EXACT, bool OPT>
 __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n, int tx, int ty) {
     const int lane = threadIdx.x & 63;
     const int r = ty * kTile + (lane >> 3);
@@ -472,7 +479,7 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
                 if (i0 + u < nl) {
                     const int j = mylst[64 * (i0 + u)];
                     float z;
-                    if (face_counts_in_box(L.rec[j], p, a.blur, z)) key = make_key(z, L.rec[j].fid);
+                    if (face_counts_in_box(L.rec[j], p, a.blur, z, OPT ? a.opts : 0)) key = make_key(z, L.rec[j].fid);
                 }
                 b[u] = key;
             }
@@ -480,14 +487,14 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
         }
         __syncthreads();
     }
-    write_fragments<KB, EXACT>(a, L, top, p, n, tx, ty);
+    write_fragments<KB, EXACT, OPT>(a, L, top, p, n, tx, ty);
 }
 
 // EXACT: faces_per_pixel equals the queue size KB (chosen at launch).
-template <int KB, bool BINNED, bool EXACT>
+template <int KB, bool BINNED, bool EXACT, bool OPT>
 __global__ __launch_bounds__(64) void raster_tiles_kernel(FineArgs a) {
     __shared__ TileLds L;
-    raster_tile<KB, BINNED, EXACT>(a, L, blockIdx.z, blockIdx.x, blockIdx.y);
+    raster_tile<KB, BINNED, EXACT, OPT>(a, L, blockIdx.z, blockIdx.x, blockIdx.y);
 }
 
 // Persistent form: a device-sized grid; each wave pulls the next tile id from
@@ -497,12 +504,12 @@ __global__ __launch_bounds__(64) void raster_tiles_kernel(FineArgs a) {
 // One tile of the persistent form, kept out of line: inlined into the work
 // loop, the tile's loop-invariant address arithmetic is hoisted out of it and
 // held live across tiles, far beyond the register file.
-template <int KB, bool EXACT>
+template <int KB, bool EXACT, bool OPT>
 __device__ __noinline__ void raster_tile_persistent(const FineArgs& a, TileLds& L, int n, int tx, int ty) {
-    raster_tile<KB, true, EXACT>(a, L, n, tx, ty);
+    raster_tile<KB, true, EXACT, OPT>(a, L, n, tx, ty);
 }
 
-template <int KB, bool EXACT>
+template <int KB, bool EXACT, bool OPT>
 __global__ __launch_bounds__(64) void raster_persistent_kernel(FineArgs a, const int* __restrict__ order,
                                                                int* __restrict__ hdr, int total) {
     __shared__ TileLds L;
@@ -517,7 +524,7 @@ __global__ __launch_bounds__(64) void raster_persistent_kernel(FineArgs a, const
         int rem = t - n * per_img;
         int ty = rem / a.tiles_x;
         int tx = rem - ty * a.tiles_x;
-        raster_tile_persistent<KB, EXACT>(a, L, n, tx, ty);
+        raster_tile_persistent<KB, EXACT, OPT>(a, L, n, tx, ty);
     }
 }
 
@@ -570,7 +577,7 @@ __global__ void order_scan_kernel(int* __restrict__ hist, int* __restrict__ hdr,
     }
 }
 
-template <int KB, bool EXACT>
+template <int KB, bool EXACT, bool OPT>
 static hipError_t launch_fine_k(const FineArgs& a, bool binned, int sched, int* order, int* hist, int* hdr,
                                 int n_workers, hipStream_t s, hipEvent_t eb, hipEvent_t ee) {
     if (binned && sched == 1) {
@@ -585,22 +592,24 @@ static hipError_t launch_fine_k(const FineArgs& a, bool binned, int sched, int* 
                            a.nby, a.nbx, a.M, hist, order);
         int workers = n_workers < total ? n_workers : total;
         if (eb) (void)hipEventRecord(eb, s);
-        hipLaunchKernelGGL((raster_persistent_kernel<KB, EXACT>), dim3(workers), dim3(64), 0, s, a, order, hdr, total);
+        hipLaunchKernelGGL((raster_persistent_kernel<KB, EXACT, OPT>), dim3(workers), dim3(64), 0, s, a, order, hdr,
+                           total);
         if (ee) (void)hipEventRecord(ee, s);
         return hipGetLastError();
     }
     dim3 grid(a.tiles_x, a.tiles_y, a.N);
     if (eb) (void)hipEventRecord(eb, s);
     if (binned)
-        hipLaunchKernelGGL((raster_tiles_kernel<KB, true, EXACT>), grid, dim3(64), 0, s, a);
+        hipLaunchKernelGGL((raster_tiles_kernel<KB, true, EXACT, OPT>), grid, dim3(64), 0, s, a);
     else
-        hipLaunchKernelGGL((raster_tiles_kernel<KB, false, EXACT>), grid, dim3(64), 0, s, a);
+        hipLaunchKernelGGL((raster_tiles_kernel<KB, false, EXACT, OPT>), grid, dim3(64), 0, s, a);
     if (ee) (void)hipEventRecord(ee, s);
     return hipGetLastError();
 }
 
 hipError_t launch_fine(const FaceRec* recs, const int64_t* first, const int64_t* nf, const int* counts,
-                       const int* lists, int64_t F, int N, int H, int W, int K, float blur, int bs, int M, int sched,
+                       const int* lists, int64_t F, int N, int H, int W, int K, float blur, int opts, int bs, int M,
+                       int sched,
                        int* order, int* hist, int* hdr, int n_workers, int32_t* p2f, float* zbuf, float* bary,
                        float* dists, hipStream_t s, hipEvent_t eb, hipEvent_t ee) {
     FineArgs a;
@@ -615,6 +624,7 @@ hipError_t launch_fine(const FaceRec* recs, const int64_t* first, const int64_t*
     a.W = W;
     a.K = K;
     a.blur = blur;
+    a.opts = opts;
     a.bs = bs > 0 ? bs : kTile;
     a.nby = bs > 0 ? (H + bs - 1) / bs : 0;
     a.nbx = bs > 0 ? (W + bs - 1) / bs : 0;
@@ -632,11 +642,17 @@ hipError_t launch_fine(const FaceRec* recs, const int64_t* first, const int64_t*
     const bool aligned = (((uintptr_t)p2f | (uintptr_t)zbuf | (uintptr_t)bary | (uintptr_t)dists) & 15) == 0;
 #define RAST_FINE_BUCKET(KB)                                                                          \
     if (K <= KB) {                                                                                    \
-        if (K == KB && aligned) return launch_fine_k<KB, true>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee); \
-        return launch_fine_k<KB, false>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);     \
+        if (opt) return launch_fine_k<KB, false, true>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee); \
+        if (K == KB && aligned)                                                                         \
+            return launch_fine_k<KB, true, false>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee); \
+        return launch_fine_k<KB, false, false>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee); \
     }
-    if (K <= 1) return launch_fine_k<1, true>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
-    if (K <= 2) return launch_fine_k<2, true>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
+    // options that change barycentrics and depth take the runtime-K form with their per-pixel work
+    const bool opt = (opts & (kOptPersp | kOptClip)) != 0;
+    if (K <= 1 && opt) return launch_fine_k<1, true, true>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
+    if (K <= 2 && opt) return launch_fine_k<2, true, true>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
+    if (K <= 1) return launch_fine_k<1, true, false>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
+    if (K <= 2) return launch_fine_k<2, true, false>(a, binned, sched, order, hist, hdr, n_workers, s, eb, ee);
     RAST_FINE_BUCKET(4)
     RAST_FINE_BUCKET(8)
     RAST_FINE_BUCKET(16)

@@ -13,18 +13,19 @@ hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_header_init(int* hdr, const BinSig& sig, hipStream_t s);
 
 hipError_t launch_face_setup(const float* verts, int64_t V, const int32_t* faces, int64_t F, const int64_t* first,
-                             const int64_t* nf, int N, float rb, FaceRec* recs, int* hdr, hipStream_t s);
+                             const int64_t* nf, int N, float rb, int opts, FaceRec* recs, int* hdr, hipStream_t s);
 
 hipError_t launch_binning(const FaceRec* recs, int64_t F, int N, int H, int W, int bs, int M, int* counts, int* lists,
                           int* hdr, hipStream_t s);
 
 hipError_t launch_fine(const FaceRec* recs, const int64_t* first, const int64_t* nf, const int* counts,
-                       const int* lists, int64_t F, int N, int H, int W, int K, float blur, int bs, int M, int sched,
+                       const int* lists, int64_t F, int N, int H, int W, int K, float blur, int opts, int bs, int M,
+                       int sched,
                        int* order, int* hist, int* hdr, int n_workers, int32_t* p2f, float* zbuf, float* bary,
                        float* dists, hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end);
 
 hipError_t launch_backward(const float* verts, int64_t V, const int32_t* faces, int64_t F, const int64_t* first,
-                           const int64_t* nf, int N, int H, int W, int K, float blur, int bs, int M,
+                           const int64_t* nf, int N, int H, int W, int K, float blur, int opts, int bs, int M,
                            const int32_t* p2f, const float* gz, const float* gb, const float* gd, float* grad,
                            int* hdr, FaceRec* recs, int* counts, int* lists, float* partial, int* big,
                            bool reuse, const BinSig& sig, hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end);

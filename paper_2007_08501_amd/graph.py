@@ -18,9 +18,10 @@ from .raster import empty_fragments
 
 class GraphRunner:
     def __init__(self, verts, faces, first_idx, num_faces, H, W, blur, K, bin_size, max_faces_per_bin,
-                 sched=_lib.RAST_SCHED_GRID, backward=True):
+                 sched=_lib.RAST_SCHED_GRID, backward=True, options=0):
         dev = verts.device
         self.device = dev
+        self.options = int(options)
         self.dims = (first_idx.shape[0], H, W, K)
         self.args = (float(blur), int(bin_size), int(max_faces_per_bin or 0), int(sched))
         self.verts = verts.detach().clone().contiguous()
@@ -51,11 +52,12 @@ class GraphRunner:
         N, H, W, K = self.dims
         blur, bs, M, sched = self.args
         _lib.rasterize_meshes_fwd(self.verts, self.faces, self.first_idx, self.num_faces, H, W, blur, K, bs, M, sched,
-                                  self.out.pix_to_face, self.out.zbuf, self.out.bary, self.out.dists, self.ws)
+                                  self.out.pix_to_face, self.out.zbuf, self.out.bary, self.out.dists, self.ws,
+                                  self.options)
         if self.backward:
             # the backward reuses the forward's face records and bins in the same workspace
             _lib.rasterize_meshes_bwd(self.verts, self.faces, self.first_idx, self.num_faces, H, W, blur, K, bs, M,
-                                      _lib.RAST_BWD_REUSE_FORWARD,
+                                      _lib.RAST_BWD_REUSE_FORWARD | self.options,
                                       self.out.pix_to_face, self.grad_zbuf, self.grad_bary, self.grad_dists,
                                       self.grad_verts, self.ws)
 

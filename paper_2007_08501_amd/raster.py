@@ -25,6 +25,8 @@ class RasterSettings:
     sched: 0 = grid launch, 1 = persistent most-loaded-first scheduler.
     check: read the device status after the forward (synchronises) and
     recover from a bin overflow by recounting when max_faces_per_bin is None.
+    perspective_correct / clip_barycentric_coords / cull_backfaces: the
+    rasterizer options (see RAST_PERSPECTIVE_CORRECT etc. in rast.h).
     """
 
     image_size: Union[int, Tuple[int, int]]
@@ -34,6 +36,15 @@ class RasterSettings:
     max_faces_per_bin: Optional[int] = None
     sched: int = _lib.RAST_SCHED_GRID
     check: bool = True
+    perspective_correct: bool = False
+    clip_barycentric_coords: bool = False
+    cull_backfaces: bool = False
+
+    @property
+    def options(self) -> int:
+        return ((_lib.RAST_PERSPECTIVE_CORRECT if self.perspective_correct else 0)
+                | (_lib.RAST_CLIP_BARYCENTRIC if self.clip_barycentric_coords else 0)
+                | (_lib.RAST_CULL_BACKFACES if self.cull_backfaces else 0))
 
     @property
     def hw(self):
@@ -81,10 +92,10 @@ def round_up(x: int, m: int) -> int:
     return max(m, (x + m - 1) // m * m)
 
 
-def forward_into(verts, faces, first_idx, num_faces, H, W, blur_radius, K, bin_size, M, sched, out, ws):
+def forward_into(verts, faces, first_idx, num_faces, H, W, blur_radius, K, bin_size, M, sched, out, ws, options=0):
     """Raw forward into preallocated outputs (no status read)."""
     _lib.rasterize_meshes_fwd(verts, faces, first_idx, num_faces, H, W, blur_radius, K, bin_size, M, sched,
-                              out.pix_to_face, out.zbuf, out.bary, out.dists, ws)
+                              out.pix_to_face, out.zbuf, out.bary, out.dists, ws, options)
 
 
 def empty_fragments(N, H, W, K, device) -> Fragments:
@@ -98,13 +109,13 @@ def empty_fragments(N, H, W, K, device) -> Fragments:
 
 class _RasterizeMeshes(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, verts, faces, first_idx, num_faces, H, W, blur, K, bs, M, sched, check):
+    def forward(ctx, verts, faces, first_idx, num_faces, H, W, blur, K, bs, M, sched, check, options):
         N = first_idx.shape[0]
         out = empty_fragments(N, H, W, K, verts.device)
         vd = verts.detach().contiguous()
         # a workspace of this call's own: its backward reuses the face records and bins
         ws = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, faces.shape[0], bs, M), verts.device)
-        forward_into(vd, faces, first_idx, num_faces, H, W, blur, K, bs, M, sched, out, ws)
+        forward_into(vd, faces, first_idx, num_faces, H, W, blur, K, bs, M, sched, out, ws, options)
         if check:
             st, mx = _lib.rast_query_status(ws)
             if st == _lib.RAST_EOVERFLOW:
@@ -116,6 +127,7 @@ class _RasterizeMeshes(torch.autograd.Function):
         ctx.dims = (N, H, W, K)
         ctx.blur = blur
         ctx.bins = (bs, M)
+        ctx.options = options
         ctx.ws = ws
         return out.pix_to_face, out.zbuf, out.bary, out.dists
 
@@ -132,10 +144,10 @@ class _RasterizeMeshes(torch.autograd.Function):
         # the saved vertices cannot have changed (autograd checks their version),
         # so the forward's face records and bins are still valid
         _lib.rasterize_meshes_bwd(verts, faces, first_idx, num_faces, H, W, ctx.blur, K, bs, M,
-                                  _lib.RAST_BWD_REUSE_FORWARD, p2f, prep(g_zbuf), prep(g_bary), prep(g_dists),
-                                  grad_verts, ctx.ws)
+                                  _lib.RAST_BWD_REUSE_FORWARD | ctx.options, p2f, prep(g_zbuf), prep(g_bary),
+                                  prep(g_dists), grad_verts, ctx.ws)
         ctx.ws = None
-        return (grad_verts,) + (None,) * 11
+        return (grad_verts,) + (None,) * 12
 
 
 def rasterize_meshes(verts, faces, first_idx, num_faces, settings: RasterSettings) -> Fragments:
@@ -166,14 +178,14 @@ def rasterize_meshes(verts, faces, first_idx, num_faces, settings: RasterSetting
                                              settings.blur_radius, bs), 32)
     try:
         res = _RasterizeMeshes.apply(verts, faces, first_idx, num_faces, H, W, float(settings.blur_radius), K,
-                                     int(bs), int(M or 0), int(sched), bool(settings.check))
+                                     int(bs), int(M or 0), int(sched), bool(settings.check), settings.options)
     except BinOverflow:
         if not auto_M:
             raise
         M = round_up(count_max_faces_per_bin(verts.detach(), faces, first_idx, num_faces, H, W,
                                              settings.blur_radius, bs), 32)
         res = _RasterizeMeshes.apply(verts, faces, first_idx, num_faces, H, W, float(settings.blur_radius), K,
-                                     int(bs), int(M), int(sched), bool(settings.check))
+                                     int(bs), int(M), int(sched), bool(settings.check), settings.options)
     return Fragments(*res)
 
 

@@ -39,7 +39,7 @@ def to_dev(b, dev="cuda"):
             torch.from_numpy(b.first_idx).to(dev), torch.from_numpy(b.num_faces).to(dev))
 
 
-def run_fwd(b, bs, M=None, sched=0, K=None, dev_inputs=None, check=True):
+def run_fwd(b, bs, M=None, sched=0, K=None, dev_inputs=None, check=True, options=0):
     v, f, fi, nf = dev_inputs or to_dev(b)
     H, W = b.image_size
     K = K or b.faces_per_pixel
@@ -49,7 +49,7 @@ def run_fwd(b, bs, M=None, sched=0, K=None, dev_inputs=None, check=True):
     out = empty_fragments(N, H, W, K, v.device)
     ws = _lib.alloc_workspace(_lib.rast_workspace_size(N, H, W, f.shape[0], bs, M or 0), v.device)
     _lib.rasterize_meshes_fwd(v, f, fi, nf, H, W, b.blur_radius, K, bs, M or 0, sched, out.pix_to_face, out.zbuf,
-                              out.bary, out.dists, ws)
+                              out.bary, out.dists, ws, options)
     if check:
         st, _ = _lib.rast_query_status(ws)
         assert st == _lib.RAST_OK, _lib.status_string(st)

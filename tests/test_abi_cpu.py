@@ -67,11 +67,11 @@ FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every case fails validatio
 
 def fwd(**kw):
     a = dict(verts=FAKE, V=3, faces=FAKE, F=1, first=FAKE, nf=FAKE, N=1, H=8, W=8, blur=0.0, K=1, bs=0, M=0,
-             sched=0, p2f=FAKE, zbuf=FAKE, bary=FAKE, dists=FAKE, ws=None, wsb=0, stream=None)
+             sched=0, opts=0, p2f=FAKE, zbuf=FAKE, bary=FAKE, dists=FAKE, ws=None, wsb=0, stream=None)
     a.update(kw)
     return _lib.lib().rasterize_meshes_fwd(a["verts"], a["V"], a["faces"], a["F"], a["first"], a["nf"], a["N"],
                                            a["H"], a["W"], a["blur"], a["K"], a["bs"], a["M"], a["sched"],
-                                           a["p2f"], a["zbuf"], a["bary"], a["dists"], a["ws"], a["wsb"],
+                                           a["opts"], a["p2f"], a["zbuf"], a["bary"], a["dists"], a["ws"], a["wsb"],
                                            a["stream"])
 
 
@@ -79,7 +79,8 @@ def fwd(**kw):
     dict(N=0), dict(H=0), dict(W=-3), dict(K=0), dict(K=65), dict(blur=-1.0), dict(blur=float("nan")),
     dict(blur=float("inf")), dict(bs=4), dict(bs=8, M=0), dict(bs=520, M=4), dict(sched=2), dict(V=-1),
     dict(F=-1), dict(F=1 << 31), dict(H=1, W=1 << 22, K=64), dict(verts=None), dict(faces=None), dict(first=None), dict(nf=None),
-    dict(p2f=None), dict(zbuf=None), dict(bary=None), dict(dists=None),
+    dict(p2f=None), dict(zbuf=None), dict(bary=None), dict(dists=None), dict(opts=1), dict(opts=0x800),
+    dict(opts=-1),
 ])
 def test_forward_rejects_bad_arguments(kw):
     assert fwd(**kw) == _lib.RAST_EINVAL
@@ -87,6 +88,9 @@ def test_forward_rejects_bad_arguments(kw):
 
 def test_forward_rejects_bad_workspace():
     assert fwd(ws=None, wsb=1 << 20) == _lib.RAST_EWORKSPACE
+    # every option combination passes validation (and then needs a workspace)
+    for o in (0x100, 0x200, 0x400, 0x700):
+        assert fwd(opts=o) == _lib.RAST_EWORKSPACE
     assert fwd(ws=ctypes.c_void_p(0x1001), wsb=1 << 20) == _lib.RAST_EWORKSPACE  # misaligned
     assert fwd(ws=ctypes.c_void_p(0x1000), wsb=16) == _lib.RAST_EWORKSPACE      # too small
 
@@ -98,8 +102,10 @@ def test_backward_rejects_bad_arguments():
     reuse = list(args)
     reuse[13] = _lib.RAST_BWD_REUSE_FORWARD
     assert L.rasterize_meshes_bwd(*reuse) == _lib.RAST_EWORKSPACE
+    reuse[13] = _lib.RAST_BWD_REUSE_FORWARD | 0x700  # the forward's options ride along
+    assert L.rasterize_meshes_bwd(*reuse) == _lib.RAST_EWORKSPACE
     for i, v in ((14, None), (18, None), (10, 100), (9, -1.0), (4, None), (5, None), (6, 0), (11, 12), (11, -8),
-                 (13, 2), (13, -1)):
+                 (13, 2), (13, -1), (13, 0x800)):
         bad = list(args)
         bad[i] = v
         assert L.rasterize_meshes_bwd(*bad) == _lib.RAST_EINVAL, i
