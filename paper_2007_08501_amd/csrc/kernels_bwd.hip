@@ -429,6 +429,19 @@ __device__ __forceinline__ void store_bin_rec(BinRec& d, const FaceRec& R) {
 // kP1Chunk faces -- most of them -- is one chunk and reads its slots once.
 constexpr double kFixScale = 4294967296.0;  // 2^32
 
+// v * 2^32 as a two's-complement 64-bit fixed-point integer, for abs(v) <
+// 2^30, rounded toward zero.  The magnitude's integer part and fraction are
+// split exactly in FP32 (m - floor(m) is exact for m >= 0) and the fraction
+// scaled by 2^32 (exact), so only fractions below 2^-32 are lost; far
+// cheaper than a conversion through FP64.
+__device__ __forceinline__ unsigned long long to_fix32(float v) {
+    const float m = fabsf(v);
+    const float fm = floorf(m);
+    const unsigned long long q =
+        ((unsigned long long)(unsigned)fm << 32) | (unsigned long long)(unsigned)((m - fm) * 4294967296.0f);
+    return v < 0.0f ? (unsigned long long)(-(long long)q) : q;
+}
+
 __global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a) {
     __shared__ BinRec srec[kP1Chunk];
     __shared__ unsigned long long acci[kP1Chunk * 9];
@@ -508,7 +521,7 @@ __global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a) {
                 for (int x = 0; x < 9; ++x) {
                     const float v = g9[x];
                     if (fabsf(v) < a.fix_limit) {
-                        atomicAdd(&acci[9 * j + x], (unsigned long long)__double2ll_rn((double)v * kFixScale));
+                        atomicAdd(&acci[9 * j + x], to_fix32(v));
                     } else {
                         // too large for the fixed-point sums (never for sane inputs): straight to the vertex
                         const int vtx = a.faces[3 * (int64_t)list[base + j] + x / 3];
