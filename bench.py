@@ -265,7 +265,7 @@ def points_main(args):
         N, (H, W), K = b.N, b.image_size, b.points_per_pixel
         t = lambda a: torch.from_numpy(a).to(dev)
         gr = PointsGraphRunner(t(b.points), t(b.first_idx), t(b.num_points), H, W, b.radius, K, D=1,
-                               norm=args.norm)
+                               norm=args.norm, silhouette=True)
         _, gd_np, _, _ = meshgen.point_grads(b, channels=1)
         rng = np.random.default_rng(b.seed + 9)
         gr.set_grad_image(t(rng.standard_normal((N, H, W, 1)).astype(np.float32)))
@@ -352,7 +352,7 @@ def points_main(args):
         "vs_baseline": round(ms_step / POINTS_PAPER_MS, 6), "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"pts3: {meshgen.POINT_CONFIG_NAMES[3]}", "clouds": N, "points": P, "image": [H, W],
                    "points_per_pixel": K, "radius": b.radius,
-                   "compositing": "Norm" if args.norm else "Alpha", "features": "silhouette (D=1, ones)",
+                   "compositing": "Norm" if args.norm else "Alpha", "features": "silhouette (every feature 1, no feature table)",
                    "parallelism": "single GPU"},
         "throughput_mpixk_per_s": round(S / (ms_step * 1e-3) / 1e6, 2), "slots": S, "slots_valid": S_valid,
         "kernels_ms": {"points_fine": round(fine_ms, 5), "points_backward": round(bwd_ms, 5),

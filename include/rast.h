@@ -339,6 +339,9 @@ int rasterize_points_bwd(const float* points, int64_t P, const int64_t* cloud_to
  * holds the opacities, or, with RAST_COMPOSITE_FROM_DISTS or-ed into mode,
  * the rasterizer's squared distances d, the opacity being
  * alpha = 1 - d / radius^2 (radius > 0).  image (npix,D) is overwritten.
+ * features may be NULL: every feature of every point is then 1 (silhouette
+ * compositing, the paper's boolean features), and no table is read; P still
+ * bounds the valid ids.
  */
 #define RAST_COMPOSITE_ALPHA 0
 #define RAST_COMPOSITE_NORM 1
@@ -356,8 +359,9 @@ int points_composite_fwd(const int32_t* idx, const float* weights, const float* 
  *          dL/df_{idx_k} += alpha_k grad_image / S   (nothing where S <= 0)
  * grad_weights (npix,K) is overwritten with dL/dalpha_k, or dL/dd_k =
  * -dL/dalpha_k / radius^2 in RAST_COMPOSITE_FROM_DISTS mode; 0 for slots that
- * take no part.  grad_features (P,D) is overwritten, or NULL (not computed);
- * its sums are formed with float atomics, so their rounding order varies.
+ * take no part.  grad_features (P,D) is overwritten, or NULL (not computed;
+ * it must be NULL when features is); its sums are formed with float atomics,
+ * so their rounding order varies.
  */
 int points_composite_bwd(const int32_t* idx, const float* weights, const float* features, int64_t P, int64_t npix,
                          int K, int D, int mode, float radius, const float* grad_image, float* grad_weights,

@@ -359,35 +359,45 @@ def rasterize_points_bwd(points, first_idx, num_points, H, W, radius, K, flags, 
     _check("rasterize_points_bwd", rc)
 
 
-def _composite_shapes(idx, weights, features, image):
+def _composite_shapes(idx, weights, features, image, num_points):
+    """(npix, K, P, D); features None = all ones (D from the image, P given)."""
     _same_shape("idx", idx.shape, (weights, "weights"))
-    if features.dim() != 2:
-        raise ValueError(f"features must be (P,D), got {tuple(features.shape)}")
-    _same_shape("idx", tuple(idx.shape[:-1]) + (features.shape[1],), (image, "image"))
+    if features is not None:
+        if features.dim() != 2:
+            raise ValueError(f"features must be (P,D), got {tuple(features.shape)}")
+        P, D = features.shape
+    else:
+        if num_points is None:
+            raise ValueError("without a feature table the number of points must be given")
+        P, D = int(num_points), int(image.shape[-1])
+    _same_shape("idx", tuple(idx.shape[:-1]) + (D,), (image, "image"))
     K = idx.shape[-1]
-    return idx.numel() // K if K else 0, K, features.shape[0], features.shape[1]
+    return idx.numel() // K if K else 0, K, P, D
 
 
-def points_composite_fwd(idx, weights, features, mode, radius, image):
+def points_composite_fwd(idx, weights, features, mode, radius, image, num_points=None):
+    """features None: every feature is 1 (silhouette compositing)."""
     dev = idx.device
     _require(idx, "idx", torch.int32, dev)
     for t, n in ((weights, "weights"), (features, "features"), (image, "image")):
         _require(t, n, torch.float32, dev)
-    npix, K, P, D = _composite_shapes(idx, weights, features, image)
+    npix, K, P, D = _composite_shapes(idx, weights, features, image, num_points)
     _check("points_composite_fwd",
            lib().points_composite_fwd(_p(idx), _p(weights), _p(features), P, npix, K, D, int(mode), float(radius),
                                       _p(image), _stream(dev)))
 
 
-def points_composite_bwd(idx, weights, features, mode, radius, grad_image, grad_weights, grad_features):
+def points_composite_bwd(idx, weights, features, mode, radius, grad_image, grad_weights, grad_features,
+                         num_points=None):
     dev = idx.device
     _require(idx, "idx", torch.int32, dev)
     for t, n in ((weights, "weights"), (features, "features"), (grad_image, "grad_image"),
                  (grad_weights, "grad_weights"), (grad_features, "grad_features")):
         _require(t, n, torch.float32, dev)
-    npix, K, P, D = _composite_shapes(idx, weights, features, grad_image)
+    npix, K, P, D = _composite_shapes(idx, weights, features, grad_image, num_points)
     _same_shape("idx", idx.shape, (grad_weights, "grad_weights"))
-    _same_shape("features", features.shape, (grad_features, "grad_features"))
+    if features is not None:
+        _same_shape("features", features.shape, (grad_features, "grad_features"))
     _check("points_composite_bwd",
            lib().points_composite_bwd(_p(idx), _p(weights), _p(features), P, npix, K, D, int(mode), float(radius),
                                       _p(grad_image), _p(grad_weights), _p(grad_features), _stream(dev)))

@@ -434,8 +434,7 @@ static bool bad_composite(int64_t P, int64_t npix, int K, int D, int mode, float
 int points_composite_fwd(const int32_t* idx, const float* weights, const float* features, int64_t P, int64_t npix,
                          int K, int D, int mode, float radius, float* image, void* stream) {
     if (bad_composite(P, npix, K, D, mode, radius)) return RAST_EINVAL;
-    if (npix > 0 && (idx == nullptr || weights == nullptr || image == nullptr || (P > 0 && features == nullptr)))
-        return RAST_EINVAL;
+    if (npix > 0 && (idx == nullptr || weights == nullptr || image == nullptr)) return RAST_EINVAL;
     return hip_rc(rast::launch_composite_fwd(idx, weights, features, P, npix, K, D, mode, radius, image,
                                              (hipStream_t)stream));
 }
@@ -444,9 +443,9 @@ int points_composite_bwd(const int32_t* idx, const float* weights, const float* 
                          int K, int D, int mode, float radius, const float* grad_image, float* grad_weights,
                          float* grad_features, void* stream) {
     if (bad_composite(P, npix, K, D, mode, radius)) return RAST_EINVAL;
-    if (npix > 0 && (idx == nullptr || weights == nullptr || grad_image == nullptr || grad_weights == nullptr ||
-                     (P > 0 && features == nullptr)))
+    if (npix > 0 && (idx == nullptr || weights == nullptr || grad_image == nullptr || grad_weights == nullptr))
         return RAST_EINVAL;
+    if (features == nullptr && grad_features != nullptr) return RAST_EINVAL;
     return hip_rc(rast::launch_composite_bwd(idx, weights, features, P, npix, K, D, mode, radius, grad_image,
                                              grad_weights, grad_features, (hipStream_t)stream));
 }

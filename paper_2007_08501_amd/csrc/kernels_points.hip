@@ -743,14 +743,16 @@ hipError_t launch_points_bwd(const float* pts, int64_t P, const int64_t* first, 
 //           applied to 0 -- a suffix scan with no division by 1 - alpha_k, so
 //           a fully opaque slot is no special case;  dL/df_k = alpha_k T_k g.
 //   Norm:   dL/dalpha_k = (g_k - <g, out>) / S,  dL/df_k = alpha_k g / S.
-// Feature gradients are scattered to the point rows with float atomics.
+// Feature gradients are scattered to the point rows with float atomics.  With
+// no feature table every feature is 1 (silhouette compositing) and nothing is
+// gathered.
 // ---------------------------------------------------------------------------
 constexpr int kCompQ = 4;  // consecutive slots per lane
 
 struct CompArgs {
     const int32_t* idx;
     const float* w;
-    const float* f;
+    const float* f;  // (P, D) features, or nullptr: all ones
     int64_t P, npix;
     int K, D;
     int norm, from_d;
@@ -821,10 +823,15 @@ __global__ __launch_bounds__(256) void composite_fwd_kernel(CompArgs a, float* _
         for (int i = 0; i < kCompQ; ++i) {
             if (id[i] >= 0) {
                 const float wk = a.norm ? al[i] : al[i] * T;
-                const float* fr = a.f + (int64_t)id[i] * a.D;
+                if (a.f) {
+                    const float* fr = a.f + (int64_t)id[i] * a.D;
 #pragma unroll
-                for (int c = 0; c < CB; ++c)
-                    if (c < a.D) acc[c] = fmaf(wk, fr[c], acc[c]);
+                    for (int c = 0; c < CB; ++c)
+                        if (c < a.D) acc[c] = fmaf(wk, fr[c], acc[c]);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) acc[c] += wk;  // features all ones
+                }
             }
             T *= 1.0f - al[i];
         }
@@ -862,10 +869,15 @@ __global__ __launch_bounds__(256) void composite_bwd_kernel(CompArgs a, const fl
         for (int i = 0; i < kCompQ; ++i) {
             gk[i] = 0.0f;
             if (id[i] >= 0) {
-                const float* fr = a.f + (int64_t)id[i] * a.D;
+                if (a.f) {
+                    const float* fr = a.f + (int64_t)id[i] * a.D;
 #pragma unroll
-                for (int c = 0; c < CB; ++c)
-                    if (c < a.D) gk[i] = fmaf(g[c], fr[c], gk[i]);
+                    for (int c = 0; c < CB; ++c)
+                        if (c < a.D) gk[i] = fmaf(g[c], fr[c], gk[i]);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) gk[i] += g[c];  // features all ones
+                }
             }
         }
         float dal[kCompQ], wf[kCompQ];

@@ -90,9 +90,11 @@ class PointsGraphRunner:
     splats (Alpha or Norm, opacity 1 - d / r^2), composite backward, rasterize
     backward reusing the forward's sorted points.  Static buffers as for
     GraphRunner; ``features`` (P,D) and the upstream image gradient are set
-    with ``set_features`` / ``set_grad_image``."""
+    with ``set_features`` / ``set_grad_image``; ``silhouette`` renders with
+    every feature 1 and no feature table."""
 
-    def __init__(self, points, first_idx, num_points, H, W, radius, K, D=1, norm=False, feature_grad=False):
+    def __init__(self, points, first_idx, num_points, H, W, radius, K, D=1, norm=False, feature_grad=False,
+                 silhouette=False):
         dev = points.device
         self.device = dev
         N, P = first_idx.shape[0], points.shape[0]
@@ -106,11 +108,12 @@ class PointsGraphRunner:
         self.idx = torch.empty((N, H, W, K), dtype=torch.int32, device=dev)
         self.zbuf = torch.empty((N, H, W, K), dtype=torch.float32, device=dev)
         self.dists = torch.empty_like(self.zbuf)
-        self.features = torch.ones((P, D), dtype=torch.float32, device=dev)
-        self.image = torch.empty((N, H, W, D), dtype=torch.float32, device=dev)
+        # silhouette: no feature table, every feature is 1
+        self.features = None if silhouette else torch.ones((P, D), dtype=torch.float32, device=dev)
+        self.image = torch.empty((N, H, W, 1 if silhouette else D), dtype=torch.float32, device=dev)
         self.grad_image = torch.zeros_like(self.image)
         self.grad_dists = torch.empty_like(self.zbuf)
-        self.grad_features = torch.empty_like(self.features) if feature_grad else None
+        self.grad_features = torch.empty_like(self.features) if (feature_grad and not silhouette) else None
         self.grad_points = torch.empty_like(self.points)
         self.ws = torch.empty(_lib.rast_points_workspace_size(N, H, W, P), dtype=torch.uint8, device=dev)
         self.graph = None
@@ -125,12 +128,13 @@ class PointsGraphRunner:
         N, H, W, K, D = self.dims
         _lib.rasterize_points_fwd(self.points, self.first_idx, self.num_points, H, W, self.radius, K, self.idx,
                                   self.zbuf, self.dists, self.ws)
-        _lib.points_composite_fwd(self.idx, self.dists, self.features, self.mode, self.radius, self.image)
+        _lib.points_composite_fwd(self.idx, self.dists, self.features, self.mode, self.radius, self.image,
+                                  self.points.shape[0])
 
     def backward_eager(self):
         N, H, W, K, D = self.dims
         _lib.points_composite_bwd(self.idx, self.dists, self.features, self.mode, self.radius, self.grad_image,
-                                  self.grad_dists, self.grad_features)
+                                  self.grad_dists, self.grad_features, self.points.shape[0])
         _lib.rasterize_points_bwd(self.points, self.first_idx, self.num_points, H, W, self.radius, K,
                                   _lib.RAST_BWD_REUSE_FORWARD, self.idx, None, self.grad_dists, self.grad_points,
                                   self.ws)

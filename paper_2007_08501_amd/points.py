@@ -12,7 +12,7 @@ arguments.
 from __future__ import annotations
 
 from dataclasses import dataclass
-from typing import NamedTuple, Tuple, Union
+from typing import NamedTuple, Optional, Tuple, Union
 
 import torch
 
@@ -94,41 +94,52 @@ def rasterize_points(points: torch.Tensor, first_idx: torch.Tensor, num_points: 
 
 class _Composite(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, idx, weights, features, mode, radius):
-        image = torch.empty(tuple(idx.shape[:-1]) + (features.shape[1],), dtype=torch.float32, device=idx.device)
-        _lib.points_composite_fwd(idx, weights, features, mode, radius, image)
+    def forward(ctx, idx, weights, features, mode, radius, num_points):
+        D = features.shape[1] if features is not None else 1
+        image = torch.empty(tuple(idx.shape[:-1]) + (D,), dtype=torch.float32, device=idx.device)
+        _lib.points_composite_fwd(idx, weights, features, mode, radius, image, num_points)
         ctx.save_for_backward(idx, weights, features)
         ctx.mode = mode
         ctx.radius = radius
+        ctx.num_points = num_points
         return image
 
     @staticmethod
     def backward(ctx, g_image):
         idx, weights, features = ctx.saved_tensors
         gw = torch.empty_like(weights)
-        gf = torch.empty_like(features) if ctx.needs_input_grad[2] else None
-        _lib.points_composite_bwd(idx, weights, features, ctx.mode, ctx.radius, g_image.contiguous(), gw, gf)
-        return None, gw, gf, None, None
+        gf = torch.empty_like(features) if (features is not None and ctx.needs_input_grad[2]) else None
+        _lib.points_composite_bwd(idx, weights, features, ctx.mode, ctx.radius, g_image.contiguous(), gw, gf,
+                                  ctx.num_points)
+        return None, gw, gf, None, None, None
 
 
-def _composite(idx, weights, features, mode, radius):
-    return _Composite.apply(idx.contiguous(), weights.contiguous(), features.contiguous(), int(mode), float(radius))
+def _composite(idx, weights, features, mode, radius, num_points):
+    if features is None and num_points is None:
+        raise ValueError("without features, give num_points (the ids must be below it)")
+    f = None if features is None else features.contiguous()
+    n = int(num_points) if num_points is not None else int(f.shape[0])
+    return _Composite.apply(idx.contiguous(), weights.contiguous(), f, int(mode), float(radius), n)
 
 
-def alpha_composite(idx: torch.Tensor, alphas: torch.Tensor, features: torch.Tensor) -> torch.Tensor:
-    """sum_k alpha_k prod_{j<k} (1 - alpha_j) f_{idx_k}: idx/alphas (...,K), features (P,D) -> (...,D)."""
-    return _composite(idx, alphas, features, _lib.RAST_COMPOSITE_ALPHA, 0.0)
+def alpha_composite(idx: torch.Tensor, alphas: torch.Tensor, features: Optional[torch.Tensor] = None,
+                    num_points: Optional[int] = None) -> torch.Tensor:
+    """sum_k alpha_k prod_{j<k} (1 - alpha_j) f_{idx_k}: idx/alphas (...,K), features (P,D) -> (...,D).
+    features None: every feature is 1 (a silhouette, (...,1)); num_points then bounds the ids."""
+    return _composite(idx, alphas, features, _lib.RAST_COMPOSITE_ALPHA, 0.0, num_points)
 
 
-def norm_composite(idx: torch.Tensor, alphas: torch.Tensor, features: torch.Tensor) -> torch.Tensor:
+def norm_composite(idx: torch.Tensor, alphas: torch.Tensor, features: Optional[torch.Tensor] = None,
+                   num_points: Optional[int] = None) -> torch.Tensor:
     """sum_k alpha_k f_{idx_k} / sum_k alpha_k (0 where the sum is <= 0)."""
-    return _composite(idx, alphas, features, _lib.RAST_COMPOSITE_NORM, 0.0)
+    return _composite(idx, alphas, features, _lib.RAST_COMPOSITE_NORM, 0.0, num_points)
 
 
-def splat_composite(idx: torch.Tensor, dists: torch.Tensor, features: torch.Tensor, radius: float,
-                    norm: bool = False) -> torch.Tensor:
+def splat_composite(idx: torch.Tensor, dists: torch.Tensor, features: Optional[torch.Tensor], radius: float,
+                    norm: bool = False, num_points: Optional[int] = None) -> torch.Tensor:
     """Compositing of splats whose opacity falls from 1 at the point to 0 at
     the disc's rim, alpha = 1 - d / radius^2, formed inside the kernel from
-    the rasterizer's squared distances d (differentiable in dists)."""
+    the rasterizer's squared distances d (differentiable in dists).  features
+    None: a silhouette (every feature 1)."""
     mode = (_lib.RAST_COMPOSITE_NORM if norm else _lib.RAST_COMPOSITE_ALPHA) | _lib.RAST_COMPOSITE_FROM_DISTS
-    return _composite(idx, dists, features, mode, radius)
+    return _composite(idx, dists, features, mode, radius, num_points)

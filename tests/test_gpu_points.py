@@ -424,3 +424,29 @@ def test_points_backward_large_radius_global_form():
                  _lib.RAST_BWD_REUSE_FORWARD)
     o = oracle_pfwd(b.points, b.first_idx, b.num_points, H, W, radius, K)
     assert_grad_close(g, oracle.points_backward(b.points, (H, W), o["idx"], gz, gd, nthreads=threads()), "r0.3")
+
+
+@pytest.mark.parametrize("norm", [False, True])
+def test_composite_without_features_is_a_silhouette(norm):
+    # no feature table: every feature is 1; equal, bit for bit, to a table of ones,
+    # and to the oracle's compositing of ones
+    b, idx, w, alpha, _, _ = composite_inputs(1, True)
+    mode = (_lib.RAST_COMPOSITE_NORM if norm else 0) | _lib.RAST_COMPOSITE_FROM_DISTS
+    P = b.points.shape[0]
+    t_idx = torch.from_numpy(idx.astype(np.int32)).cuda()
+    t_w = torch.from_numpy(w).cuda()
+    ones = torch.ones((P, 1), dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(b.seed + 4)
+    gimg = torch.from_numpy(rng.standard_normal(idx.shape[:-1] + (1,)).astype(np.float32)).cuda()
+    img0 = torch.empty(idx.shape[:-1] + (1,), dtype=torch.float32, device="cuda")
+    img1 = torch.empty_like(img0)
+    _lib.points_composite_fwd(t_idx, t_w, None, mode, b.radius, img0, num_points=P)
+    _lib.points_composite_fwd(t_idx, t_w, ones, mode, b.radius, img1)
+    assert torch.equal(img0, img1)
+    gw0, gw1 = torch.empty_like(t_w), torch.empty_like(t_w)
+    _lib.points_composite_bwd(t_idx, t_w, None, mode, b.radius, gimg, gw0, None, num_points=P)
+    _lib.points_composite_bwd(t_idx, t_w, ones, mode, b.radius, gimg, gw1, None)
+    assert torch.equal(gw0, gw1)
+    f1 = np.ones((P, 1))
+    ref = (oracle.norm_composite if norm else oracle.alpha_composite)(idx, alpha, f1)
+    assert float(np.abs(img0.cpu().numpy() - ref).max()) <= TOL_COMP
