@@ -81,6 +81,7 @@ KERNEL_SOURCES = {
     "fine": ["paper_2007_08501_amd/csrc/kernels_fwd.hip", "paper_2007_08501_amd/csrc/device.hpp"],
     "backward": ["paper_2007_08501_amd/csrc/kernels_bwd.hip", "paper_2007_08501_amd/csrc/device.hpp"],
     "points_fine": ["paper_2007_08501_amd/csrc/kernels_points.hip", "paper_2007_08501_amd/csrc/device.hpp"],
+    "points_backward": ["paper_2007_08501_amd/csrc/kernels_points.hip", "paper_2007_08501_amd/csrc/device.hpp"],
 }
 
 
@@ -93,11 +94,11 @@ def sources_digest(kernel):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, config, K, bs):
+def measured_traffic(kernel, config, K, bs, path=None):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's reading), or None
     when no summary exists for this workload or the kernel changed since."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_cfg{config}_K{K}_bs{bs}.txt")
+    path = path or os.path.join(ROOT, "profiles", f"traffic_{kernel}_cfg{config}_K{K}_bs{bs}.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -341,6 +342,15 @@ def points_main(args):
         lane_ops = valu * 64 / (dom_ms * 1e-3)
         roofline["valu"] = {"lane_ops_per_s": float(f"{lane_ops:.4g}"), "peak": VALU_PEAK_LANE_OPS,
                             "frac": round(lane_ops / VALU_PEAK_LANE_OPS, 4), "wave_instructions": int(valu)}
+    roofline["traffic"] = measured_traffic(dom, "pts3", K, 0, path=os.path.join(
+        ROOT, "profiles", f"traffic_{dom}_pts3_K{K}.txt"))
+    if args.copy_probe:
+        # a plain streaming kernel of known size, the scale for the byte counters of a profiled run
+        src = torch.ones(64 << 20, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
     cpu, parity = None, None
     if not args.no_cpu_baseline:
         cpu, parity = points_cpu_leg(b, args.cpu_seconds, gr.idx, gr.zbuf, gr.dists, gd_np)
