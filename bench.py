@@ -120,18 +120,19 @@ def measured_valu(kernel, config, K, bs, path=None):
     kernel-trace summary (SQ_INSTS_VALU), or None when there is none for this
     workload or the kernel changed since it was taken."""
     path = path or os.path.join(ROOT, "profiles", f"kernels_cfg{config}_K{K}_bs{bs}.txt")
-    if kernel not in ("fine", "points_fine") or not os.path.exists(path):
+    if kernel not in ("fine", "points_fine", "backward") or not os.path.exists(path):
         return None
+    prefix = "backward_" if kernel == "backward" else ""
     vals = {}
     with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith((" ", "#")):
                 k, _, v = line.partition(":")
                 vals[k.strip()] = v.strip().split()[0] if v.strip() else ""
-    if vals.get("sources_sha256") != sources_digest(kernel):
+    if vals.get(prefix + "sources_sha256") != sources_digest(kernel):
         return None
     try:
-        return float(vals["valu_wave_instructions_per_launch"])
+        return float(vals[prefix + "valu_wave_instructions_per_launch"])
     except (KeyError, ValueError):
         return None
 
