@@ -323,7 +323,7 @@ int softmax_blend_bwd(const int32_t* pix_to_face, const float* zbuf, const float
 namespace {
 
 struct PtLayout {
-    size_t hdr, start, bsum, home, rank, sorted, total;
+    size_t hdr, start, bsum, home, rank, sorted, order, ohist, total;
 };
 
 bool make_pt_layout(int N, int H, int W, int64_t P, PtLayout* L) {
@@ -342,6 +342,10 @@ bool make_pt_layout(int N, int H, int W, int64_t P, PtLayout* L) {
     off = align_up(off + (size_t)P * 4);
     L->sorted = off;
     off = align_up(off + (size_t)P * 16);
+    L->order = off;
+    off = align_up(off + (size_t)T * 4);
+    L->ohist = off;
+    off = align_up(off + 64 * 4);
     L->total = off;
     return true;
 }
@@ -392,8 +396,9 @@ int rasterize_points_fwd(const float* points, int64_t P, const int64_t* cloud_to
     if (rast::launch_header_init(hdr, pt_signature(P, N, H, W, radius), s) != hipSuccess) return RAST_EHIP;
     return hip_rc(rast::launch_points_fwd(points, P, cloud_to_first_idx, num_points_per_cloud, N, H, W, radius,
                                           points_per_pixel, hdr, (int*)(ws + L.start), (int*)(ws + L.bsum),
-                                          (int*)(ws + L.home), (int*)(ws + L.rank), (float4*)(ws + L.sorted), idx,
-                                          zbuf, dists, s, tl_events.begin[RAST_KERNEL_POINTS_FINE],
+                                          (int*)(ws + L.home), (int*)(ws + L.rank), (float4*)(ws + L.sorted),
+                                          (int*)(ws + L.order), (int*)(ws + L.ohist), idx, zbuf, dists, s,
+                                          tl_events.begin[RAST_KERNEL_POINTS_FINE],
                                           tl_events.end[RAST_KERNEL_POINTS_FINE]));
 }
 

@@ -328,24 +328,31 @@ __device__ __forceinline__ bool face_bins(const FaceRec& R, int H, int W, int bs
 
 // Sort key: ascending z, then ascending face id, as one unsigned 64-bit
 // integer (the bit pattern of a non-negative float is monotone in its value).
+// Only z >= 0 is ever keyed (-0 becomes +0), so a key's top bit is clear and
+// its top twelve bits are at most those of +inf as a float; read as an IEEE
+// double the key is therefore a non-negative number below +inf (a subnormal
+// when z = 0), and doubles of that range order exactly as their bit patterns.
+// The empty key is +inf as a double, above every real key.
 __device__ __forceinline__ uint64_t make_key(float z, int fid) {
     uint32_t zb = (z == 0.0f) ? 0u : __float_as_uint(z);
     return ((uint64_t)zb << 32) | (uint32_t)fid;
 }
-constexpr uint64_t kEmptyKey = ~0ull;
+constexpr uint64_t kEmptyKey = 0x7ff0000000000000ull;
 
-// Register-resident sorted list of the KB smallest keys; every slot is a
-// compare-exchange with the travelling key, so the array is only ever
-// indexed with compile-time constants.
-// Compare-exchange: a <- min, b <- max.  One 64-bit compare drives four
-// 32-bit selects (written on the halves so that the compiler does not turn
-// the pair into a separate min and max with a compare each).
+__device__ __forceinline__ double key_as_f64(uint64_t k) { return __longlong_as_double((long long)k); }
+__device__ __forceinline__ uint64_t f64_as_key(double d) { return (uint64_t)__double_as_longlong(d); }
+
+// Compare-exchange: a <- min, b <- max, as one FP64 min and one FP64 max
+// (two instructions, against a 64-bit compare and four selects).  Both are
+// exact on the keys' range: no NaN ever occurs, and the kernels keep FP64
+// subnormals (denormal mode "preserve"), so the keys of z = 0 stay distinct.
 __device__ __forceinline__ void cex(uint64_t& a, uint64_t& b) {
-    const bool lt = b < a;
-    const uint32_t al = (uint32_t)a, ah = (uint32_t)(a >> 32), bl = (uint32_t)b, bh = (uint32_t)(b >> 32);
-    const uint32_t ll = lt ? bl : al, lh = lt ? bh : ah, hl = lt ? al : bl, hh = lt ? ah : bh;
-    a = ((uint64_t)lh << 32) | ll;
-    b = ((uint64_t)hh << 32) | hl;
+    const double x = key_as_f64(a), y = key_as_f64(b);
+    a = f64_as_key(__builtin_fmin(x, y));
+    b = f64_as_key(__builtin_fmax(x, y));
+}
+__device__ __forceinline__ uint64_t key_min(uint64_t a, uint64_t b) {
+    return f64_as_key(__builtin_fmin(key_as_f64(a), key_as_f64(b)));
 }
 
 // Sorts eight keys ascending with a 19-comparator network.
@@ -360,6 +367,8 @@ __device__ __forceinline__ void sort8(uint64_t (&b)[8]) {
 
 constexpr bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
+// Register-resident sorted list of the KB smallest keys, only ever indexed
+// with compile-time constants.
 template <int KB>
 struct TopK {
     uint64_t q[KB];
@@ -378,12 +387,33 @@ struct TopK {
 #pragma unroll
         for (int i = 0; i < M; ++i) {
             const int qi = KB - M + i;
-            q[qi] = b[M - 1 - i] < q[qi] ? b[M - 1 - i] : q[qi];
+            q[qi] = key_min(b[M - 1 - i], q[qi]);
         }
 #pragma unroll
         for (int d = KB / 2; d >= 1; d /= 2) {
 #pragma unroll
             for (int i = 0; i < KB; ++i)
+                if (!(i & d)) cex(q[i], q[i + d]);
+        }
+    }
+    // merge8 confined to the first S slots, for a lane whose queue holds c
+    // keys and gets n new ones with c + n <= S: the slots from S on stay
+    // empty, the eight keys the half-cleaner drops are empty ones, and the
+    // merge costs log2(S) stages of S / 2 compare-exchanges instead of
+    // log2(KB) stages of KB / 2.
+    template <int S>
+    __device__ __forceinline__ void merge8_prefix(uint64_t (&b)[8]) {
+        static_assert(S >= 8 && S <= KB && is_pow2(S), "prefix size");
+        sort8(b);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int qi = S - 8 + i;
+            q[qi] = key_min(b[7 - i], q[qi]);
+        }
+#pragma unroll
+        for (int d = S / 2; d >= 1; d /= 2) {
+#pragma unroll
+            for (int i = 0; i < S; ++i)
                 if (!(i & d)) cex(q[i], q[i + d]);
         }
     }
@@ -402,12 +432,7 @@ struct TopK {
     __device__ __forceinline__ void insert(uint64_t key, bool want = true) {
         if (!want) key = kEmptyKey;
 #pragma unroll
-        for (int i = 0; i < KB; ++i) {
-            const bool lt = key < q[i];
-            const uint64_t lo = lt ? key : q[i];
-            key = lt ? q[i] : key;
-            q[i] = lo;
-        }
+        for (int i = 0; i < KB; ++i) cex(q[i], key);
     }
 };
 

@@ -4,6 +4,7 @@
 //                 (counts gathered per block in LDS when the tiles fit)
 //   pt_scan_*     exclusive scan of the per-tile counts into tile starts
 //   pt_scatter    one thread per point: 16-byte record at its sorted slot
+//   pt_order_*    tile order for the fine pass, heaviest first
 //   pt_raster     one wave per 8x8 tile: candidates from the home lists of
 //                 the tiles that can reach it, cull, exact FP64 test per
 //                 pixel, K nearest along z in registers, write the fragments
@@ -55,6 +56,8 @@ struct PtArgs {
     int* home;              // (P) home tile or -1
     int* rank;              // (P) rank within the home tile
     float4* sorted;         // (P) x, y, z, id
+    int* order;             // (T) tiles, heaviest first
+    int* ohist;             // (64) tile counts per work bucket, then bucket starts
     int32_t* idx;           // (N,H,W,K) outputs
     float* zbuf;
     float* dists;
@@ -217,6 +220,60 @@ __global__ __launch_bounds__(256) void pt_scatter_kernel(PtArgs a) {
     a.sorted[a.start[h] + a.rank[p]] = make_float4(x, y, z, __int_as_float((int)p));
 }
 
+// Tile order for the fine pass, heaviest first: a tile's work is its number
+// of candidates (the sorted points of the home tiles that can reach it),
+// bucketed on a log scale (two buckets per octave), and a counting sort over
+// the 64 buckets lists the tiles.  Within a bucket the order is arbitrary;
+// the fragments do not depend on it.
+__device__ __forceinline__ int pt_tile_bucket(const PtArgs& a, int t) {
+    const int per_img = a.tiles_x * a.tiles_y;
+    const int n = t / per_img;
+    const int tt = t - n * per_img;
+    const int ty = tt / a.tiles_x, tx = tt - ty * a.tiles_x;
+    int w = 0;
+    for (int yy = max(ty - a.ry, 0); yy <= ty; ++yy) {
+        const int64_t row = ((int64_t)n * a.tiles_y + yy) * a.tiles_x;
+        w += a.start[row + tx + 1] - a.start[row + max(tx - a.rx, 0)];
+    }
+    const unsigned v = (unsigned)w + 1u;
+    const int lg = 31 - __clz(v);
+    const int level = min(2 * lg + (lg > 0 ? (int)((v >> (lg - 1)) & 1u) : 0), 63);
+    return 63 - level;
+}
+
+__global__ __launch_bounds__(256) void pt_order_hist_kernel(PtArgs a) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.T) return;
+    atomicAdd(&a.ohist[pt_tile_bucket(a, (int)t)], 1);
+}
+
+__global__ void pt_order_scan_kernel(int* __restrict__ ohist) {
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int i = 0; i < 64; ++i) {
+            const int v = ohist[i];
+            ohist[i] = acc;
+            acc += v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void pt_order_scatter_kernel(PtArgs a) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.T) return;
+    a.order[atomicAdd(&a.ohist[pt_tile_bucket(a, (int)t)], 1)] = (int)t;
+}
+
+static hipError_t pt_order(const PtArgs& a, hipStream_t s) {
+    hipError_t e = launch_fill_i32(a.ohist, 64, 0, s);
+    if (e != hipSuccess) return e;
+    const unsigned g = (unsigned)((a.T + 255) / 256);
+    hipLaunchKernelGGL(pt_order_hist_kernel, dim3(g), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(pt_order_scan_kernel, dim3(1), dim3(64), 0, s, a.ohist);
+    hipLaunchKernelGGL(pt_order_scatter_kernel, dim3(g), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Fine pass.  Candidates are gathered a wave-wide chunk at a time, culled on
 // their pixel ranges and compacted into an LDS batch of up to kPtBatch
@@ -248,9 +305,27 @@ __device__ __forceinline__ double pt_d2(double x, double y, double px, double py
     return dx * dx + dy * dy;
 }
 
+// Pushes a lane's listed hits into its queue, eight at a time, merging
+// within the first S slots (S = KB: the whole queue).
+template <int S, int KB>
+__device__ __forceinline__ void pt_push_hits(TopK<KB>& top, const PtBatchLds& L, const unsigned char* my, int nl,
+                                             int nmax) {
+    for (int i0 = 0; i0 < nmax; i0 += 8) {
+        uint64_t b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) b[u] = (i0 + u < nl) ? L.key[my[64 * (i0 + u)]] : kEmptyKey;
+        if constexpr (S == KB)
+            top.push8(b);
+        else
+            top.template merge8_prefix<S>(b);
+    }
+}
+
+// `held`: keys in the lane's queue (at most KB); the queue's keys are its
+// first `held` slots, in order.
 template <int KB>
-__device__ __forceinline__ void pt_batch(const PtArgs& a, PtBatchLds& L, TopK<KB>& top, int m, bool live, double px,
-                                         double py) {
+__device__ __forceinline__ void pt_batch(const PtArgs& a, PtBatchLds& L, TopK<KB>& top, int& held, int m, bool live,
+                                         double px, double py) {
     __syncthreads();
     const int lane = threadIdx.x & 63;
     unsigned char* my = L.lst + lane;
@@ -260,12 +335,22 @@ __device__ __forceinline__ void pt_batch(const PtArgs& a, PtBatchLds& L, TopK<KB
         if (live && pt_d2(q.x, q.y, px, py) < a.r2) my[64 * nl++] = (unsigned char)j;
     }
     const int nmax = wave_max(nl);
-    for (int i0 = 0; i0 < nmax; i0 += 8) {
-        uint64_t b[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) b[u] = (i0 + u < nl) ? L.key[my[64 * (i0 + u)]] : kEmptyKey;
-        top.push8(b);
+    if constexpr (KB >= 16 && is_pow2(KB)) {
+        // every push of this batch fits the smallest prefix that holds the
+        // wave's largest queue after it (the choice is uniform over the wave)
+        const int need = wave_max(held + nl);
+        if (need <= 8)
+            pt_push_hits<8, KB>(top, L, my, nl, nmax);
+        else if (need <= 16)
+            pt_push_hits<16, KB>(top, L, my, nl, nmax);
+        else if (need <= 32 && KB > 32)
+            pt_push_hits<(KB > 32 ? 32 : KB), KB>(top, L, my, nl, nmax);
+        else
+            pt_push_hits<KB, KB>(top, L, my, nl, nmax);
+    } else {
+        pt_push_hits<KB, KB>(top, L, my, nl, nmax);
     }
+    held = min(held + nl, KB);
     __syncthreads();
 }
 
@@ -332,10 +417,18 @@ __device__ __forceinline__ void pt_write(const PtArgs& a, PtLds<KB>& L, const To
     pt_store_rows(reinterpret_cast<uint32_t*>(a.dists + pix0 * K), L.stage, K, rowK, rows, cols, vec);
 }
 
+// At least two waves per SIMD: left alone, the compiler takes more than half
+// the register file for the 64-key queue (one wave per SIMD), and the pass
+// runs a quarter slower than with the few spills the bound costs.
 template <int KB, bool EXACT>
-__global__ __launch_bounds__(64) void pt_raster_kernel(PtArgs a, bool aligned) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pt_raster_kernel(PtArgs a, bool aligned) {
     __shared__ PtLds<KB> L;
-    const int tx = blockIdx.x, ty = blockIdx.y, n = blockIdx.z;
+    // workgroups start in launch order, so the tiles are taken heaviest first
+    const int t = a.order[blockIdx.x];
+    const int per_img = a.tiles_x * a.tiles_y;
+    const int n = t / per_img;
+    const int tt = t - n * per_img;
+    const int ty = tt / a.tiles_x, tx = tt - ty * a.tiles_x;
     const int lane = threadIdx.x & 63;
     const int r = ty * kTile + (lane >> 3), c = tx * kTile + (lane & 7);
     const bool live = r < a.H && c < a.W;
@@ -347,6 +440,7 @@ __global__ __launch_bounds__(64) void pt_raster_kernel(PtArgs a, bool aligned) {
 
     TopK<KB> top;
     top.init();
+    int held = 0;
     int m = 0;
     for (int yy = max(ty - a.ry, 0); yy <= ty; ++yy) {
         const int64_t row = ((int64_t)n * a.tiles_y + yy) * a.tiles_x;
@@ -374,7 +468,7 @@ __global__ __launch_bounds__(64) void pt_raster_kernel(PtArgs a, bool aligned) {
                 const uint64_t kept = __ballot(keep);
                 const int cnt = __popcll(kept);
                 if (m + cnt > kPtBatch) {
-                    pt_batch<KB>(a, L.b, top, m, live, px, py);
+                    pt_batch<KB>(a, L.b, top, held, m, live, px, py);
                     m = 0;
                 }
                 if (keep) {
@@ -386,7 +480,7 @@ __global__ __launch_bounds__(64) void pt_raster_kernel(PtArgs a, bool aligned) {
             }
         }
     }
-    if (m > 0) pt_batch<KB>(a, L.b, top, m, live, px, py);
+    if (m > 0) pt_batch<KB>(a, L.b, top, held, m, live, px, py);
     __syncthreads();
     pt_write<KB, EXACT>(a, L, top, px, py, n, tx, ty, aligned);
 }
@@ -419,6 +513,8 @@ static PtArgs pt_args(const float* pts, int64_t P, const int64_t* first, const i
     a.home = home;
     a.rank = rank;
     a.sorted = sorted;
+    a.order = nullptr;
+    a.ohist = nullptr;
     a.idx = nullptr;
     a.zbuf = nullptr;
     a.dists = nullptr;
@@ -449,7 +545,7 @@ static hipError_t pt_sort(const PtArgs& a, hipStream_t s) {
 
 template <int KB, bool EXACT>
 static hipError_t pt_fine_k(const PtArgs& a, bool aligned, hipStream_t s, hipEvent_t eb, hipEvent_t ee) {
-    const dim3 grid(a.tiles_x, a.tiles_y, a.N);
+    const dim3 grid((unsigned)a.T);
     if (eb) (void)hipEventRecord(eb, s);
     hipLaunchKernelGGL((pt_raster_kernel<KB, EXACT>), grid, dim3(64), 0, s, a, aligned);
     if (ee) (void)hipEventRecord(ee, s);
@@ -458,13 +554,17 @@ static hipError_t pt_fine_k(const PtArgs& a, bool aligned, hipStream_t s, hipEve
 
 hipError_t launch_points_fwd(const float* pts, int64_t P, const int64_t* first, const int64_t* np, int N, int H,
                              int W, float radius, int K, int* hdr, int* start, int* bsum, int* home, int* rank,
-                             float4* sorted, int32_t* idx, float* zbuf, float* dists, hipStream_t s, hipEvent_t eb,
-                             hipEvent_t ee) {
+                             float4* sorted, int* order, int* ohist, int32_t* idx, float* zbuf, float* dists,
+                             hipStream_t s, hipEvent_t eb, hipEvent_t ee) {
     PtArgs a = pt_args(pts, P, first, np, N, H, W, radius, K, hdr, start, bsum, home, rank, sorted);
+    a.order = order;
+    a.ohist = ohist;
     a.idx = idx;
     a.zbuf = zbuf;
     a.dists = dists;
     hipError_t e = pt_sort(a, s);
+    if (e != hipSuccess) return e;
+    e = pt_order(a, s);
     if (e != hipSuccess) return e;
     const bool aligned = (((uintptr_t)idx | (uintptr_t)zbuf | (uintptr_t)dists) & 15) == 0;
 #define PT_FINE_BUCKET(KB)                                                     \

@@ -45,8 +45,8 @@ hipError_t launch_softmax_bwd(const int32_t* p2f, const float* z, const float* d
 int64_t pt_scan_blocks(int64_t T);
 hipError_t launch_points_fwd(const float* pts, int64_t P, const int64_t* first, const int64_t* np, int N, int H,
                              int W, float radius, int K, int* hdr, int* start, int* bsum, int* home, int* rank,
-                             float4* sorted, int32_t* idx, float* zbuf, float* dists, hipStream_t s, hipEvent_t eb,
-                             hipEvent_t ee);
+                             float4* sorted, int* order, int* ohist, int32_t* idx, float* zbuf, float* dists,
+                             hipStream_t s, hipEvent_t eb, hipEvent_t ee);
 hipError_t launch_points_bwd(const float* pts, int64_t P, const int64_t* first, const int64_t* np, int N, int H,
                              int W, float radius, int K, const int32_t* idx, const float* gz, const float* gd,
                              float* grad, int* hdr, int* start, int* bsum, int* home, int* rank, float4* sorted,

@@ -309,6 +309,32 @@ def test_zero_faces_total():
         assert (out.pix_to_face == -1).all() and (out.zbuf == -1).all()
 
 
+def test_zero_depth_faces_order_by_id():
+    # coplanar copies of one triangle at z = +0 and -0: every key has a zero
+    # depth, so a covered pixel lists the copies in face-id order, on both the
+    # binned and the single-pass path, and agrees with the oracle
+    tri = np.array([[0.8, -0.7, 0.0], [-0.8, -0.7, 0.0], [0.0, 0.8, 0.0]], np.float32)
+    neg = tri.copy()
+    neg[:, 2] = -0.0
+    copies = 6
+    v = np.concatenate([tri, neg, tri, neg, tri, neg]).astype(np.float32)
+    f = (np.arange(copies)[:, None] * 3 + np.arange(3)[None, :]).astype(np.int32)
+    b = meshgen.Batch(name="z0", verts=v, faces=f, first_idx=np.array([0]), num_faces=np.array([copies]),
+                      verts_first_idx=np.array([0]), num_verts=np.array([v.shape[0]]), image_size=(16, 16),
+                      faces_per_pixel=8, blur_radius=0.0, bin_size=8, max_faces_per_bin=None)
+    o = oracle_full(b)
+    covered = o["p2f"][0, ..., 0] >= 0
+    assert covered.sum() > 40
+    want = np.array(list(range(copies)) + [-1] * (8 - copies))
+    assert (o["p2f"][0][covered] == want).all()
+    for bs in (0, 8):
+        out, _ = run_fwd(b, bs)
+        g = frag_numpy(out)
+        np.testing.assert_array_equal(g["p2f"][0][covered], np.broadcast_to(want, (int(covered.sum()), 8)))
+        np.testing.assert_array_equal(g["p2f"].astype(np.int64), o["p2f"])
+        assert (g["zbuf"][0][covered][:, :copies] == 0).all()
+
+
 # ----------------------------------------------------------------- blend
 
 def test_silhouette_blend_vs_oracle():

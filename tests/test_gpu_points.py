@@ -128,6 +128,23 @@ def test_points_edge_cases():
     check_case(pts, [10], [30], H, W, 0.2, 4, "partial cloud")
 
 
+@pytest.mark.parametrize("K", [5, 16, 32])
+def test_points_zero_and_subnormal_depths(K):
+    # coincident points whose depths are +0, -0, FP32 subnormals, tiny and
+    # huge normals: the (depth, index) order must hold exactly at the bottom
+    # of the depth range, where many keys share their high word
+    rng = np.random.default_rng(23)
+    z = np.array([0.0] * 6 + [-0.0] * 6 + [1e-45, 3e-45, 1e-44, 1e-40, 1e-39, 1.2e-38, 1e-37, 0.5,
+                                           3.0e38, 1e-45, 0.0, -0.0], np.float32)
+    z = z[rng.permutation(z.size)]
+    xy = np.array([1 - 7 / 16, 1 - 5 / 16], np.float32)
+    c = np.c_[np.tile(xy, (z.size, 1)), z].astype(np.float32)
+    o = check_case(c, [0], [z.size], 16, 16, 0.1, K, f"depth0 K{K}")
+    ids = o["idx"][0, 2, 3]
+    order = sorted(range(z.size), key=lambda i: (float(z[i]), i))
+    assert list(ids[:min(K, z.size)]) == order[:K]
+
+
 def test_points_zero_points():
     p = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
     f = torch.zeros(2, dtype=torch.int64, device="cuda")
