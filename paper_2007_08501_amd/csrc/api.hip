@@ -420,7 +420,8 @@ int rasterize_points_bwd(const float* points, int64_t P, const int64_t* cloud_to
     return hip_rc(rast::launch_points_bwd(
         points, P, cloud_to_first_idx, num_points_per_cloud, N, H, W, radius, points_per_pixel, idx, grad_zbuf,
         grad_dists, grad_points, (int*)(ws + L.hdr), (int*)(ws + L.start), (int*)(ws + L.bsum), (int*)(ws + L.home),
-        (int*)(ws + L.rank), (float4*)(ws + L.sorted), (flags & RAST_BWD_REUSE_FORWARD) != 0,
+        (int*)(ws + L.rank), (float4*)(ws + L.sorted), (int*)(ws + L.order), (int*)(ws + L.ohist),
+        n_workers_for_current_device() / 32, (flags & RAST_BWD_REUSE_FORWARD) != 0,
         pt_signature(P, N, H, W, radius), s, tl_events.begin[RAST_KERNEL_POINTS_BWD],
         tl_events.end[RAST_KERNEL_POINTS_BWD]));
 }

@@ -57,7 +57,7 @@ struct PtArgs {
     int* rank;              // (P) rank within the home tile
     float4* sorted;         // (P) x, y, z, id
     int* order;             // (T) tiles, heaviest first
-    int* ohist;             // (64) tile counts per work bucket, then bucket starts
+    int* ohist;             // (64) tile counts per work bucket, then bucket starts, then bucket ends
     int32_t* idx;           // (N,H,W,K) outputs
     float* zbuf;
     float* dists;
@@ -225,6 +225,8 @@ __global__ __launch_bounds__(256) void pt_scatter_kernel(PtArgs a) {
 // bucketed on a log scale (two buckets per octave), and a counting sort over
 // the 64 buckets lists the tiles.  Within a bucket the order is arbitrary;
 // the fragments do not depend on it.
+constexpr int kPtOrderBuckets = 64;
+
 __device__ __forceinline__ int pt_tile_bucket(const PtArgs& a, int t) {
     const int per_img = a.tiles_x * a.tiles_y;
     const int n = t / per_img;
@@ -237,8 +239,8 @@ __device__ __forceinline__ int pt_tile_bucket(const PtArgs& a, int t) {
     }
     const unsigned v = (unsigned)w + 1u;
     const int lg = 31 - __clz(v);
-    const int level = min(2 * lg + (lg > 0 ? (int)((v >> (lg - 1)) & 1u) : 0), 63);
-    return 63 - level;
+    const int level = min(2 * lg + (lg > 0 ? (int)((v >> (lg - 1)) & 1u) : 0), kPtOrderBuckets - 1);
+    return kPtOrderBuckets - 1 - level;  // the last bucket: tiles without candidates
 }
 
 __global__ __launch_bounds__(256) void pt_order_hist_kernel(PtArgs a) {
@@ -250,7 +252,7 @@ __global__ __launch_bounds__(256) void pt_order_hist_kernel(PtArgs a) {
 __global__ void pt_order_scan_kernel(int* __restrict__ ohist) {
     if (threadIdx.x == 0) {
         int acc = 0;
-        for (int i = 0; i < 64; ++i) {
+        for (int i = 0; i < kPtOrderBuckets; ++i) {
             const int v = ohist[i];
             ohist[i] = acc;
             acc += v;
@@ -265,7 +267,7 @@ __global__ __launch_bounds__(256) void pt_order_scatter_kernel(PtArgs a) {
 }
 
 static hipError_t pt_order(const PtArgs& a, hipStream_t s) {
-    hipError_t e = launch_fill_i32(a.ohist, 64, 0, s);
+    hipError_t e = launch_fill_i32(a.ohist, kPtOrderBuckets, 0, s);
     if (e != hipSuccess) return e;
     const unsigned g = (unsigned)((a.T + 255) / 256);
     hipLaunchKernelGGL(pt_order_hist_kernel, dim3(g), dim3(256), 0, s, a);
@@ -609,6 +611,8 @@ struct PtBwdArgs {
     const float* gd;
     float* grad;
     int* hdr;
+    const int* order;  // tiles, most candidates first (the forward's order)
+    const int* ohist;  // bucket ends of that order
     int64_t T;
     int N, H, W, K;
     float r;
@@ -669,6 +673,7 @@ __global__ __launch_bounds__(256) void pt_bwd_kernel(PtBwdArgs b) {
 }
 
 constexpr int kBwdTileThreads = 256;
+constexpr int64_t kLdsPerCu = 160 * 1024;
 
 // e / d for 0 <= e < 2^22 and d > 0: the float estimate is off by at most one.
 __device__ __forceinline__ int small_div(int e, int d, float inv_d) {
@@ -679,9 +684,7 @@ __device__ __forceinline__ int small_div(int e, int d, float inv_d) {
 }
 extern __shared__ uint32_t bwd_lds[];
 
-__global__ __launch_bounds__(kBwdTileThreads) void pt_bwd_tile_kernel(PtBwdArgs b) {
-    if (!pt_bwd_usable(b)) return;
-    const int t = blockIdx.x;
+__device__ __forceinline__ void pt_bwd_tile(const PtBwdArgs& b, int t) {
     const int lo = b.start[t], hi = b.start[t + 1];
     if (lo == hi) return;  // uniform: no point has this home tile
     const int per_img = b.tiles_x * b.tiles_y;
@@ -770,6 +773,159 @@ __global__ __launch_bounds__(kBwdTileThreads) void pt_bwd_tile_kernel(PtBwdArgs 
     }
 }
 
+// A device-sized grid walks the tiles that have candidates (a point's home
+// tile is among its own candidates), most loaded first; tiles with no home
+// point are skipped.
+__global__ __launch_bounds__(kBwdTileThreads) void pt_bwd_tile_kernel(PtBwdArgs b) {
+    if (!pt_bwd_usable(b)) return;
+    const int ntile = b.ohist[kPtOrderBuckets - 2];
+    for (int j = blockIdx.x; j < ntile; j += gridDim.x) {
+        pt_bwd_tile(b, b.order[j]);
+        __syncthreads();  // the next tile restages the LDS box
+    }
+}
+
+// Slot-major form of the same backward.  Every slot that names a point lies
+// in that point's pixel range, hence in the box of its home tile, so each
+// slot is claimed by exactly one tile.  A tile hashes its own points (id ->
+// local index) in LDS, reads its box of slots in coalesced rows, and notes
+// for each slot naming one of its points the slot's k in a per-point cell of
+// the pixel's offset within the point's pixel range; a point is listed at
+// most once per pixel, so every cell has one writer and no atomics are
+// needed.  Each point then sums its cells in row-major pixel order in FP64,
+// as the point-major form does.  Points beyond kSlotCap per tile are taken in
+// chunks, each rescanning the box.
+constexpr int kSlotCap = 1024;          // points per chunk
+constexpr int kSlotHash = 2 * kSlotCap; // hash entries (power of two)
+constexpr int kSlotMaxCells = 25;       // (span_x + 1) * (span_y + 1) at most
+constexpr int kSlotLoads = 8;           // slots loaded per thread before any is used
+constexpr uint8_t kNoSlot = 0xff;
+
+static_assert(kSlotHash == 1 << 11, "slot_hash yields 11 bits");
+__device__ __forceinline__ int slot_hash(int id) { return (int)(((uint32_t)id * 2654435761u) >> 21); }
+
+__device__ __forceinline__ void pt_bwd_slots_tile(const PtBwdArgs& b, int t, int2* htab, int* prc, uint8_t* cell) {
+    const int lo = b.start[t], hi = b.start[t + 1];
+    if (lo == hi) return;  // uniform: no point has this home tile
+    const int per_img = b.tiles_x * b.tiles_y;
+    const int n = t / per_img;
+    const int rem = t - n * per_img;
+    const int ty = rem / b.tiles_x, tx = rem - ty * b.tiles_x;
+    const int x0 = tx * kTile, y0 = ty * kTile;
+    const int bw = min(x0 + kTile + b.span_x, b.W) - x0;
+    const int bh = min(y0 + kTile + b.span_y, b.H) - y0;
+    const int K = b.K;
+    const int ex = b.span_x + 1, ey = b.span_y + 1, ncell = ex * ey;
+    const int rowl = bw * K, nbox = bh * rowl;
+    const float inv_rowl = 1.0f / (float)rowl, inv_k = 1.0f / (float)K;
+    for (int c_lo = lo; c_lo < hi; c_lo += kSlotCap) {
+        const int nloc = min(kSlotCap, hi - c_lo);
+        for (int i = threadIdx.x; i < kSlotHash; i += kBwdTileThreads) htab[i] = make_int2(-1, 0);
+        uint32_t* cw = reinterpret_cast<uint32_t*>(cell);
+        for (int i = threadIdx.x; i < (nloc * ncell + 3) / 4; i += kBwdTileThreads) cw[i] = 0xffffffffu;
+        __syncthreads();
+        for (int i = threadIdx.x; i < nloc; i += kBwdTileThreads) {
+            const float4 rec = b.sorted[c_lo + i];
+            const int id = __float_as_int(rec.w);
+            int c0, c1, r0, r1;
+            disc_pixels(rec.x, rec.y, b.r, b.H, b.W, c0, c1, r0, r1);
+            prc[i] = max(r0, y0) | (max(c0, x0) << 16);
+            // ids are distinct, and the table is at least half empty
+            for (int h = slot_hash(id);; h = (h + 1) & (kSlotHash - 1)) {
+                if (atomicCAS(&htab[h].x, -1, id) == -1) {
+                    htab[h].y = i;
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+        for (int e0 = 0; e0 < nbox; e0 += kSlotLoads * kBwdTileThreads) {
+            int vi[kSlotLoads];
+#pragma unroll
+            for (int j = 0; j < kSlotLoads; ++j) {
+                const int e = e0 + j * kBwdTileThreads + (int)threadIdx.x;
+                vi[j] = -1;
+                if (e < nbox) {
+                    const int r = small_div(e, rowl, inv_rowl);
+                    const int q = e - r * rowl;
+                    const int64_t g = ((int64_t)n * b.H + y0 + r) * b.W * K + (int64_t)x0 * K + q;
+                    vi[j] = b.idx[g];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kSlotLoads; ++j) {
+                const int id = vi[j];
+                if (id < 0) continue;
+                int local = -1;
+                for (int h = slot_hash(id);; h = (h + 1) & (kSlotHash - 1)) {
+                    const int2 en = htab[h];
+                    if (en.x == id) {
+                        local = en.y;
+                        break;
+                    }
+                    if (en.x < 0) break;
+                }
+                if (local < 0) continue;  // another tile's point, or another chunk's
+                const int e = e0 + j * kBwdTileThreads + (int)threadIdx.x;
+                const int r = small_div(e, rowl, inv_rowl);
+                const int q = e - r * rowl;
+                const int c = small_div(q, K, inv_k);
+                const int k = q - c * K;
+                const int pr = prc[local];
+                const int dr = y0 + r - (pr & 0xffff), dc = x0 + c - (pr >> 16);
+                if (dr < 0 || dr >= ey || dc < 0 || dc >= ex) continue;  // outside the point's pixel range
+                cell[local * ncell + dr * ex + dc] = (uint8_t)k;
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < nloc; i += kBwdTileThreads) {
+            const float4 rec = b.sorted[c_lo + i];
+            const int id = __float_as_int(rec.w);
+            const int pr = prc[i];
+            const int pr0 = pr & 0xffff, pc0 = pr >> 16;
+            const double x = rec.x, y = rec.y;
+            double gx = 0.0, gy = 0.0, gzs = 0.0;
+            const uint8_t* mine = cell + i * ncell;
+            for (int dr = 0; dr < ey; ++dr) {
+                const int r = pr0 + dr;
+                const double py = 1.0 - (double)(2 * r + 1) / (double)b.H;
+                for (int dc = 0; dc < ex; ++dc) {
+                    const int k = mine[dr * ex + dc];
+                    if (k == kNoSlot) continue;
+                    const int c = pc0 + dc;
+                    const double px = 1.0 - (double)(2 * c + 1) / (double)b.W;
+                    const int64_t g = (((int64_t)n * b.H + r) * b.W + c) * K + k;
+                    if (b.gz) gzs += (double)b.gz[g];
+                    if (b.gd) {
+                        const double gg = 2.0 * (double)b.gd[g];
+                        gx += gg * (x - px);
+                        gy += gg * (y - py);
+                    }
+                }
+            }
+            pt_write_grad(b, id, gx, gy, gzs);
+        }
+        __syncthreads();  // the next chunk or tile clears the tables
+    }
+}
+
+__global__ __launch_bounds__(kBwdTileThreads) void pt_bwd_slots_kernel(PtBwdArgs b) {
+    if (!pt_bwd_usable(b)) return;
+    int2* htab = reinterpret_cast<int2*>(bwd_lds);
+    int* prc = reinterpret_cast<int*>(htab + kSlotHash);
+    uint8_t* cell = reinterpret_cast<uint8_t*>(prc + kSlotCap);
+    const int ntile = b.ohist[kPtOrderBuckets - 2];
+    for (int j = blockIdx.x; j < ntile; j += gridDim.x) pt_bwd_slots_tile(b, b.order[j], htab, prc, cell);
+}
+
+// LDS bytes of the slot-major backward, or 0 when its cells do not fit.
+static size_t pt_bwd_slots_lds_bytes(int span_x, int span_y, int K) {
+    const int64_t ncell = (int64_t)(span_x + 1) * (span_y + 1);
+    if (ncell > kSlotMaxCells || K >= kNoSlot) return 0;
+    return (size_t)kSlotHash * sizeof(int2) + (size_t)kSlotCap * sizeof(int) +
+           (((size_t)kSlotCap * ncell + 3) & ~(size_t)3);
+}
+
 // LDS bytes of the box-staged backward, or 0 when it does not fit.
 static size_t pt_bwd_lds_bytes(const PtArgs& a, int span_x, int span_y, bool gz, bool gd) {
     const int64_t bw = min(kTile + span_x, a.W), bh = min(kTile + span_y, a.H);
@@ -781,14 +937,19 @@ static size_t pt_bwd_lds_bytes(const PtArgs& a, int span_x, int span_y, bool gz,
 hipError_t launch_points_bwd(const float* pts, int64_t P, const int64_t* first, const int64_t* np, int N, int H,
                              int W, float radius, int K, const int32_t* idx, const float* gz, const float* gd,
                              float* grad, int* hdr, int* start, int* bsum, int* home, int* rank, float4* sorted,
-                             bool reuse, const BinSig& sig, hipStream_t s, hipEvent_t eb, hipEvent_t ee) {
-    const PtArgs a = pt_args(pts, P, first, np, N, H, W, radius, K, hdr, start, bsum, home, rank, sorted);
+                             int* order, int* ohist, int n_cus, bool reuse, const BinSig& sig, hipStream_t s,
+                             hipEvent_t eb, hipEvent_t ee) {
+    PtArgs a = pt_args(pts, P, first, np, N, H, W, radius, K, hdr, start, bsum, home, rank, sorted);
+    a.order = order;
+    a.ohist = ohist;
     hipError_t e = launch_fill_f32(grad, 3 * P, 0.0f, s);
     if (e != hipSuccess) return e;
     if (!reuse) {
         e = launch_header_init(hdr, sig, s);
         if (e != hipSuccess) return e;
         e = pt_sort(a, s);
+        if (e != hipSuccess) return e;
+        e = pt_order(a, s);
         if (e != hipSuccess) return e;
     }
     if (P == 0) return hipSuccess;
@@ -802,6 +963,8 @@ hipError_t launch_points_bwd(const float* pts, int64_t P, const int64_t* first, 
     b.gd = gd;
     b.grad = grad;
     b.hdr = hdr;
+    b.order = order;
+    b.ohist = ohist;
     b.T = a.T;
     b.N = N;
     b.H = H;
@@ -816,10 +979,19 @@ hipError_t launch_points_bwd(const float* pts, int64_t P, const int64_t* first, 
     b.Kp = (K + 3) & ~3;
     b.reuse = reuse ? 1 : 0;
     b.sig = sig;
+    const size_t slds = pt_bwd_slots_lds_bytes(a.span_x, a.span_y, K);
     const size_t lds = pt_bwd_lds_bytes(a, a.span_x, a.span_y, gz != nullptr, gd != nullptr);
     if (eb) (void)hipEventRecord(eb, s);
-    if (lds > 0)
-        hipLaunchKernelGGL(pt_bwd_tile_kernel, dim3((unsigned)a.T), dim3(kBwdTileThreads), lds, s, b);
+    if (slds > 0) {
+        const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(8, kLdsPerCu / (int64_t)slds));
+        const int64_t grid = std::min<int64_t>(a.T, (int64_t)std::max(n_cus, 1) * per_cu);
+        hipLaunchKernelGGL(pt_bwd_slots_kernel, dim3((unsigned)grid), dim3(kBwdTileThreads), slds, s, b);
+    } else if (lds > 0) {
+        // as many workgroups as the compute units hold at once (LDS-bound)
+        const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(8, kLdsPerCu / (int64_t)lds));
+        const int64_t grid = std::min<int64_t>(a.T, (int64_t)std::max(n_cus, 1) * per_cu);
+        hipLaunchKernelGGL(pt_bwd_tile_kernel, dim3((unsigned)grid), dim3(kBwdTileThreads), lds, s, b);
+    }
     else
         hipLaunchKernelGGL(pt_bwd_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, b);
     if (ee) (void)hipEventRecord(ee, s);

@@ -50,7 +50,8 @@ hipError_t launch_points_fwd(const float* pts, int64_t P, const int64_t* first, 
 hipError_t launch_points_bwd(const float* pts, int64_t P, const int64_t* first, const int64_t* np, int N, int H,
                              int W, float radius, int K, const int32_t* idx, const float* gz, const float* gd,
                              float* grad, int* hdr, int* start, int* bsum, int* home, int* rank, float4* sorted,
-                             bool reuse, const BinSig& sig, hipStream_t s, hipEvent_t eb, hipEvent_t ee);
+                             int* order, int* ohist, int n_cus, bool reuse, const BinSig& sig, hipStream_t s,
+                             hipEvent_t eb, hipEvent_t ee);
 hipError_t launch_composite_fwd(const int32_t* idx, const float* w, const float* f, int64_t P, int64_t npix, int K,
                                 int D, int mode, float radius, float* img, hipStream_t s);
 hipError_t launch_composite_bwd(const int32_t* idx, const float* w, const float* f, int64_t P, int64_t npix, int K,

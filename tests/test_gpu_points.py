@@ -247,6 +247,43 @@ def test_points_backward_full(cfg):
     assert (g_z[:, :2] == 0).all() and (g_d[:, 2] == 0).all()
 
 
+@pytest.mark.parametrize("form", ["chunked", "box"])
+def test_points_backward_other_forms(form):
+    # "chunked": 3000 points whose discs start in one 8x8 tile, more than the
+    # slot-major form holds at once, so it takes them in chunks; "box": a
+    # radius whose per-point pixel range is too large for that form's cells,
+    # so the box-staged form runs
+    rng = np.random.default_rng(31)
+    H = W = 64
+    if form == "chunked":
+        n_pts, K, radius = 3000, 64, 0.03
+        # pixel centres of columns/rows 9..14 lie in [1 - 30/64, 1 - 19/64]
+        xy = rng.uniform(1 - 29 / 64, 1 - 20 / 64, (n_pts, 2))
+    else:
+        n_pts, K, radius = 400, 8, 0.09
+        xy = rng.uniform(-0.9, 0.9, (n_pts, 2))
+    pts_np = np.c_[xy, rng.uniform(0.5, 3.0, n_pts)].astype(np.float32)
+    radius = float(np.float32(radius))
+    p = torch.from_numpy(pts_np).cuda()
+    f = torch.zeros(1, dtype=torch.int64, device="cuda")
+    n = torch.full((1,), n_pts, dtype=torch.int64, device="cuda")
+    log(form, "P", n_pts, "K", K, "r", radius)
+    idx, _, _, ws = run_pfwd(p, f, n, H, W, radius, K)
+    gz = rng.standard_normal((1, H, W, K)).astype(np.float32)
+    gd = rng.standard_normal((1, H, W, K)).astype(np.float32)
+    gz_t, gd_t = torch.from_numpy(gz).cuda(), torch.from_numpy(gd).cuda()
+    g = run_pbwd(p, f, n, H, W, radius, K, idx, gz_t, gd_t, ws, _lib.RAST_BWD_REUSE_FORWARD)
+    ws2 = _lib.alloc_workspace(_lib.rast_points_workspace_size(1, H, W, n_pts), "cuda")
+    g2 = run_pbwd(p, f, n, H, W, radius, K, idx, gz_t, gd_t, ws2, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(g, g2)
+    o = oracle_pfwd(pts_np, [0], [n_pts], H, W, radius, K)
+    np.testing.assert_array_equal(idx.cpu().numpy(), o["idx"])
+    if form == "chunked":
+        assert (o["idx"] >= 0).sum(-1).max() == K
+    assert_grad_close(g, oracle.points_backward(pts_np, (H, W), o["idx"], gz, gd, nthreads=threads()), form)
+
+
 def test_points_backward_reuse_mismatch_flagged():
     b = meshgen.make_points_config(1)
     H, W = b.image_size
