@@ -291,7 +291,10 @@ static_assert(kPtBatch <= 256, "per-lane lists hold byte indices");
 struct PtBatchLds {
     double2 xy[kPtBatch];
     uint64_t key[kPtBatch];                 // (z, id) sort key
-    unsigned char lst[kPtBatch * 64];       // entry i of lane l at [i * 64 + l]
+    int rng[kPtBatch];                      // pixel range in the tile: c0 | c1 << 3 | r0 << 6 | r1 << 9
+    int cnt[64];                            // hits of each pixel in the batch
+    double cx[kTile], cy[kTile];            // FP64 centres of the tile's pixel columns and rows
+    unsigned char lst[kPtBatch * 64];       // entry i of pixel l at [i * 64 + l]
 };
 
 // The tile's LDS: the candidate batch, reused at the end to stage one output
@@ -324,18 +327,33 @@ __device__ __forceinline__ void pt_push_hits(TopK<KB>& top, const PtBatchLds& L,
 }
 
 // `held`: keys in the lane's queue (at most KB); the queue's keys are its
-// first `held` slots, in order.
+// first `held` slots, in order.  The coverage tests are made candidate-major:
+// a lane takes a candidate and tests only the pixels of its range, listing
+// each hit under its pixel; the lists' order depends on the LDS atomics, the
+// queues do not (every key is distinct and a queue keeps the smallest ones).
 template <int KB>
-__device__ __forceinline__ void pt_batch(const PtArgs& a, PtBatchLds& L, TopK<KB>& top, int& held, int m, bool live,
-                                         double px, double py) {
+__device__ __forceinline__ void pt_batch(const PtArgs& a, PtBatchLds& L, TopK<KB>& top, int& held, int m) {
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    unsigned char* my = L.lst + lane;
-    int nl = 0;
-    for (int j = 0; j < m; ++j) {
+    for (int j = lane; j < m; j += 64) {
         const double2 q = L.xy[j];
-        if (live && pt_d2(q.x, q.y, px, py) < a.r2) my[64 * nl++] = (unsigned char)j;
+        const int g = L.rng[j];
+        const int ca = g & 7, cb = (g >> 3) & 7, ra = (g >> 6) & 7, rb = (g >> 9) & 7;
+        for (int rr = ra; rr <= rb; ++rr) {
+            const double dy = q.y - L.cy[rr];
+            for (int cc = ca; cc <= cb; ++cc) {
+                const double dx = q.x - L.cx[cc];
+                if (dx * dx + dy * dy < a.r2) {
+                    const int pix = rr * kTile + cc;
+                    const int pos = atomicAdd(&L.cnt[pix], 1);
+                    L.lst[pos * 64 + pix] = (unsigned char)j;
+                }
+            }
+        }
     }
+    __syncthreads();
+    const int nl = L.cnt[lane];
+    const unsigned char* my = L.lst + lane;
     const int nmax = wave_max(nl);
     if constexpr (KB >= 16 && is_pow2(KB)) {
         // every push of this batch fits the smallest prefix that holds the
@@ -353,6 +371,7 @@ __device__ __forceinline__ void pt_batch(const PtArgs& a, PtBatchLds& L, TopK<KB
         pt_push_hits<KB, KB>(top, L, my, nl, nmax);
     }
     held = min(held + nl, KB);
+    L.cnt[lane] = 0;
     __syncthreads();
 }
 
@@ -433,12 +452,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pt
     const int ty = tt / a.tiles_x, tx = tt - ty * a.tiles_x;
     const int lane = threadIdx.x & 63;
     const int r = ty * kTile + (lane >> 3), c = tx * kTile + (lane & 7);
-    const bool live = r < a.H && c < a.W;
     const double px = 1.0 - (double)(2 * c + 1) / (double)a.W;
     const double py = 1.0 - (double)(2 * r + 1) / (double)a.H;
     const int x0 = tx * kTile, y0 = ty * kTile;
     const int x1 = min(x0 + kTile, a.W) - 1, y1 = min(y0 + kTile, a.H) - 1;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    // pixel centres as in a plain evaluation (the first batch's barrier
+    // publishes them); columns or rows past the image edge are never tested
+    if (lane < kTile)
+        L.b.cx[lane] = 1.0 - (double)(2 * (x0 + lane) + 1) / (double)a.W;
+    else if (lane < 2 * kTile)
+        L.b.cy[lane - kTile] = 1.0 - (double)(2 * (y0 + lane - kTile) + 1) / (double)a.H;
+    L.b.cnt[lane] = 0;
 
     TopK<KB> top;
     top.init();
@@ -462,27 +487,29 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pt
                 if (e0 + 64 * u >= hi) break;  // uniform
                 const float4 rec = recs[u];
                 bool keep = false;
+                int c0 = 0, c1 = 0, r0 = 0, r1 = 0;
                 if (e0 + 64 * u + lane < hi) {
-                    int c0, c1, r0, r1;
                     keep = disc_pixels(rec.x, rec.y, a.r, a.H, a.W, c0, c1, r0, r1) && c1 >= x0 && c0 <= x1 &&
                            r1 >= y0 && r0 <= y1;
                 }
                 const uint64_t kept = __ballot(keep);
                 const int cnt = __popcll(kept);
                 if (m + cnt > kPtBatch) {
-                    pt_batch<KB>(a, L.b, top, held, m, live, px, py);
+                    pt_batch<KB>(a, L.b, top, held, m);
                     m = 0;
                 }
                 if (keep) {
                     const int d = m + __popcll(kept & lt_mask);
                     L.b.xy[d] = make_double2((double)rec.x, (double)rec.y);
                     L.b.key[d] = make_key(rec.z, __float_as_int(rec.w));
+                    L.b.rng[d] = (max(c0, x0) - x0) | ((min(c1, x1) - x0) << 3) | ((max(r0, y0) - y0) << 6) |
+                                 ((min(r1, y1) - y0) << 9);
                 }
                 m += cnt;
             }
         }
     }
-    if (m > 0) pt_batch<KB>(a, L.b, top, held, m, live, px, py);
+    if (m > 0) pt_batch<KB>(a, L.b, top, held, m);
     __syncthreads();
     pt_write<KB, EXACT>(a, L, top, px, py, n, tx, ty, aligned);
 }
