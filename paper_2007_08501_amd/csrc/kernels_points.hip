@@ -1068,6 +1068,9 @@ hipError_t launch_points_bwd(const float* pts, int64_t P, const int64_t* first, 
 // gathered.
 // ---------------------------------------------------------------------------
 constexpr int kCompQ = 4;  // consecutive slots per lane
+// four words at 4-byte alignment (one 16-byte global load)
+typedef int i32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef float f32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
 
 struct CompArgs {
     const int32_t* idx;
@@ -1085,11 +1088,23 @@ __device__ __forceinline__ void comp_slots(const CompArgs& a, int64_t p, int sub
     int32_t iv[kCompQ];
     float wv[kCompQ];
     const int64_t o = p * a.K + kCompQ * sub;
+    if (p < a.npix && kCompQ * (sub + 1) <= a.K) {
+        // the lane's four slots as one 16-byte load per array (4-byte
+        // aligned: a pixel's slots start at any word)
+        const i32x4_a4 vi = *reinterpret_cast<const i32x4_a4*>(a.idx + o);
+        const f32x4_a4 vw = *reinterpret_cast<const f32x4_a4*>(a.w + o);
 #pragma unroll
-    for (int i = 0; i < kCompQ; ++i) {
-        const bool in = p < a.npix && kCompQ * sub + i < a.K;
-        iv[i] = in ? a.idx[o + i] : -1;
-        wv[i] = in ? a.w[o + i] : 0.0f;
+        for (int i = 0; i < kCompQ; ++i) {
+            iv[i] = vi[i];
+            wv[i] = vw[i];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kCompQ; ++i) {
+            const bool in = p < a.npix && kCompQ * sub + i < a.K;
+            iv[i] = in ? a.idx[o + i] : -1;
+            wv[i] = in ? a.w[o + i] : 0.0f;
+        }
     }
 #pragma unroll
     for (int i = 0; i < kCompQ; ++i) {
@@ -1253,9 +1268,18 @@ __global__ __launch_bounds__(256) void composite_bwd_kernel(CompArgs a, const fl
             }
         }
         const int64_t o = p * a.K + kCompQ * sub;
+        if (p < a.npix && kCompQ * (sub + 1) <= a.K) {
+            f32x4_a4 v;
+#pragma unroll
+            for (int i = 0; i < kCompQ; ++i) v[i] = id[i] >= 0 ? dal[i] * chain : 0.0f;
+            *reinterpret_cast<f32x4_a4*>(gw + o) = v;  // one 16-byte store
+        } else {
+#pragma unroll
+            for (int i = 0; i < kCompQ; ++i)
+                if (p < a.npix && kCompQ * sub + i < a.K) gw[o + i] = id[i] >= 0 ? dal[i] * chain : 0.0f;
+        }
 #pragma unroll
         for (int i = 0; i < kCompQ; ++i) {
-            if (p < a.npix && kCompQ * sub + i < a.K) gw[o + i] = id[i] >= 0 ? dal[i] * chain : 0.0f;
             if (gf && id[i] >= 0 && wf[i] != 0.0f) {
 #pragma unroll
                 for (int c = 0; c < CB; ++c)
