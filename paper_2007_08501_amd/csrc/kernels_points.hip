@@ -299,30 +299,38 @@ static hipError_t pt_order(const PtArgs& a, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // Fine pass.  Candidates are gathered a wave-wide chunk at a time, culled on
-// their pixel ranges and compacted into an LDS batch of up to kPtBatch
-// points; a full batch is then tested per pixel in FP64 (the squared
-// distance in the same operations and order as a plain evaluation, so the
-// decision is reproducible bit for bit), each lane lists its hits, and the
-// lists go through the register top-K eight keys at a time.
+// their pixel ranges and compacted into an LDS batch; a full batch is tested
+// in FP64 over each candidate's pixel range (the squared distance in the
+// same operations and order as a plain evaluation, so the decision is
+// reproducible bit for bit), the hits are listed per pixel, and each lane's
+// list goes through its register top-K eight keys at a time.
 // ---------------------------------------------------------------------------
-constexpr int kPtBatch = 128;
 constexpr int kPtLoads = 4;  // candidate chunks loaded at once
-static_assert(kPtBatch <= 256, "per-lane lists hold byte indices");
 
+// Candidates per batch: larger batches waste less of the last eight-key push
+// of each batch, and the 64-key queue's kernel is held to two waves per SIMD
+// by its registers anyway; the smaller queues keep a smaller batch, whose
+// LDS lets more waves share a compute unit.
+template <int KB>
+constexpr int pt_batch_size() { return KB >= 64 ? 192 : 128; }
+
+template <int B>
 struct PtBatchLds {
-    double2 xy[kPtBatch];
-    uint64_t key[kPtBatch];                 // (z, id) sort key
-    int rng[kPtBatch];                      // pixel range in the tile: c0 | c1 << 3 | r0 << 6 | r1 << 9
+    static_assert(B <= 256, "the per-pixel lists hold byte indices");
+    static constexpr int kCap = B;
+    double2 xy[B];
+    uint64_t key[B];                        // (z, id) sort key
+    int rng[B];                             // pixel range in the tile: c0 | c1 << 3 | r0 << 6 | r1 << 9
     int cnt[64];                            // hits of each pixel in the batch
     double cx[kTile], cy[kTile];            // FP64 centres of the tile's pixel columns and rows
-    unsigned char lst[kPtBatch * 64];       // entry i of pixel l at [i * 64 + l]
+    unsigned char lst[B * 64];              // entry i of pixel l at [i * 64 + l]
 };
 
 // The tile's LDS: the candidate batch, reused at the end to stage one output
 // array of the tile (64 pixels x K slots, pixel-major) for the row stores.
 template <int KB>
 union PtLds {
-    PtBatchLds b;
+    PtBatchLds<pt_batch_size<KB>()> b;
     uint32_t stage[64 * KB];
 };
 
@@ -333,9 +341,8 @@ __device__ __forceinline__ double pt_d2(double x, double y, double px, double py
 
 // Pushes a lane's listed hits into its queue, eight at a time, merging
 // within the first S slots (S = KB: the whole queue).
-template <int S, int KB>
-__device__ __forceinline__ void pt_push_hits(TopK<KB>& top, const PtBatchLds& L, const unsigned char* my, int nl,
-                                             int nmax) {
+template <int S, int KB, class BL>
+__device__ __forceinline__ void pt_push_hits(TopK<KB>& top, const BL& L, const unsigned char* my, int nl, int nmax) {
     for (int i0 = 0; i0 < nmax; i0 += 8) {
         uint64_t b[8];
 #pragma unroll
@@ -352,8 +359,8 @@ __device__ __forceinline__ void pt_push_hits(TopK<KB>& top, const PtBatchLds& L,
 // a lane takes a candidate and tests only the pixels of its range, listing
 // each hit under its pixel; the lists' order depends on the LDS atomics, the
 // queues do not (every key is distinct and a queue keeps the smallest ones).
-template <int KB>
-__device__ __forceinline__ void pt_batch(const PtArgs& a, PtBatchLds& L, TopK<KB>& top, int& held, int m) {
+template <int KB, class BL>
+__device__ __forceinline__ void pt_batch(const PtArgs& a, BL& L, TopK<KB>& top, int& held, int m) {
     __syncthreads();
     const int lane = threadIdx.x & 63;
     for (int j = lane; j < m; j += 64) {
@@ -515,7 +522,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void pt
                 }
                 const uint64_t kept = __ballot(keep);
                 const int cnt = __popcll(kept);
-                if (m + cnt > kPtBatch) {
+                if (m + cnt > L.b.kCap) {
                     pt_batch<KB>(a, L.b, top, held, m);
                     m = 0;
                 }
