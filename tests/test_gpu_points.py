@@ -284,6 +284,29 @@ def test_points_backward_other_forms(form):
     assert_grad_close(g, oracle.points_backward(pts_np, (H, W), o["idx"], gz, gd, nthreads=threads()), form)
 
 
+def test_points_backward_ragged_image_several_clouds():
+    # four clouds on a 37 x 53 image: partial edge tiles, pixel boxes cut by
+    # the image border, and tile ranges of several images in one order
+    b = meshgen.make_points_config(2, image_override=40)
+    H, W, K = 37, 53, 13
+    radius = float(np.float32(b.radius * 2))
+    p, f, n = dev_cloud(b)
+    idx, _, _, ws = run_pfwd(p, f, n, H, W, radius, K)
+    rng = np.random.default_rng(41)
+    gz = rng.standard_normal((b.N, H, W, K)).astype(np.float32)
+    gd = rng.standard_normal((b.N, H, W, K)).astype(np.float32)
+    gz_t, gd_t = torch.from_numpy(gz).cuda(), torch.from_numpy(gd).cuda()
+    g = run_pbwd(p, f, n, H, W, radius, K, idx, gz_t, gd_t, ws, _lib.RAST_BWD_REUSE_FORWARD)
+    ws2 = _lib.alloc_workspace(_lib.rast_points_workspace_size(b.N, H, W, p.shape[0]), "cuda")
+    g2 = run_pbwd(p, f, n, H, W, radius, K, idx, gz_t, gd_t, ws2, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(g, g2)
+    o = oracle_pfwd(b.points, b.first_idx, b.num_points, H, W, radius, K)
+    np.testing.assert_array_equal(idx.cpu().numpy(), o["idx"])
+    assert (o["idx"] >= 0).sum() > 1000
+    assert_grad_close(g, oracle.points_backward(b.points, (H, W), o["idx"], gz, gd, nthreads=threads()), "ragged")
+
+
 def test_points_backward_reuse_mismatch_flagged():
     b = meshgen.make_points_config(1)
     H, W = b.image_size
