@@ -853,7 +853,7 @@ __global__ __launch_bounds__(kBwdTileThreads) void pt_bwd_tile_kernel(PtBwdArgs 
 constexpr int kSlotCap = 1024;          // points per chunk
 constexpr int kSlotHash = 2 * kSlotCap; // hash entries (power of two)
 constexpr int kSlotMaxCells = 25;       // (span_x + 1) * (span_y + 1) at most
-constexpr int kSlotLoads = 8;           // slots loaded per thread before any is used
+constexpr int kSlotLoads = 16;          // slots loaded per thread before any is used
 constexpr uint8_t kNoSlot = 0xff;
 
 static_assert(kSlotHash == 1 << 11, "slot_hash yields 11 bits");
