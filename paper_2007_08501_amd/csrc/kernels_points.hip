@@ -6,11 +6,14 @@
 //   pt_scatter    one thread per point: 16-byte record at its sorted slot
 //   pt_order_*    tile order for the fine pass, heaviest first
 //   pt_raster     one wave per 8x8 tile: candidates from the home lists of
-//                 the tiles that can reach it, cull, exact FP64 test per
-//                 pixel, K nearest along z in registers, write the fragments
-//   pt_bwd        one thread per sorted point, one workgroup per home tile:
-//                 gathers the gradient of the point's own slots from the
-//                 pixels its disc covers, staged in LDS (no atomics)
+//                 the tiles that can reach it, cull, exact FP64 test over
+//                 each candidate's pixel range, K nearest along z in
+//                 registers, write the fragments
+//   pt_bwd_slots  one workgroup per home tile (device-sized grid): the ids of
+//                 the tile's pixel box, matched to the tile's own points
+//                 through an LDS hash; each point sums its own slots (no
+//                 atomics).  pt_bwd_tile / pt_bwd: the point-major forms
+//                 for large radii
 //   composite     a pixel's slots over the lanes of a wave segment, four per
 //                 lane: Alpha / Norm compositing and its backward
 //
