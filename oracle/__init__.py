@@ -56,6 +56,8 @@ def _load():
     lib.oracle_rasterize.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, ctypes.c_double, ci, P, i64,
                                      P, P, P, P, P, P, ci, ci]
     lib.oracle_rasterize.restype = ci
+    lib.oracle_candidates.argtypes = [P, P, P, P, ci, ci, ci, ctypes.c_double, P, i64, ci, P, P, P, P, P, P, ci, ci]
+    lib.oracle_candidates.restype = ci
     lib.oracle_fragments_fixed.argtypes = [P, P, ci, ci, ci, ci, P, ctypes.c_int64, P, P, P, P, P, ci, ci]
     lib.oracle_fragments_fixed.restype = ci
     lib.oracle_backward.argtypes = [P, i64, P, ci, ci, ci, ci, P, i64, P, P, P, P, P, ci, ci]
@@ -89,6 +91,13 @@ def _i64(a):
     return np.ascontiguousarray(a, dtype=np.int64)
 
 
+# Bits of the per-pixel ambiguity mask (see oracle_rast.c)
+AMB_M1, AMB_M2, AMB_M3, AMB_M4, AMB_M5, AMB_M7, AMB_M8 = 1, 2, 4, 8, 16, 64, 128
+AMB_BITS = dict(M1=AMB_M1, M2=AMB_M2, M3=AMB_M3, M4=AMB_M4, M5=AMB_M5, M7=AMB_M7, M8=AMB_M8)
+# Per-face classes of candidates(): counts; counts but within a margin of not
+# counting; does not count but within a margin of counting
+CLS_COUNTS, CLS_BORDER_IN, CLS_BORDER_OUT = 0, 1, 2
+
 # Rasterizer options (bits; see oracle_rast.c for their definitions)
 PERSPECTIVE_CORRECT = 0x100
 CLIP_BARYCENTRIC = 0x200
@@ -102,7 +111,7 @@ def rasterize(verts, faces, first_idx, num_faces, image_size, blur_radius, faces
     verts (V,3) (float32 inputs are promoted exactly), faces (F,3) global ids,
     first_idx/num_faces (N,).  ``pixels``: optional 1-D array of linear pixel
     ids n*H*W + r*W + c; default every pixel.  Returns a dict with p2f (int64),
-    zbuf, bary, dists (float64), amb (uint8 bit mask M1..M5) and nhits (int64),
+    zbuf, bary, dists (float64), amb (uint8 bit mask, AMB_*) and nhits (int64),
     shaped (N,H,W,K[,3]) for full images or (npix,K[,3]) for a pixel list.
     """
     lib = _load()
@@ -130,6 +139,36 @@ def rasterize(verts, faces, first_idx, num_faces, image_size, blur_radius, faces
     if pix is None:
         out = {k: a.reshape((N, H, W) + a.shape[1:]) for k, a in out.items()}
     return out
+
+
+def candidates(verts, faces, first_idx, num_faces, image_size, blur_radius, pixels, cap: int = 64,
+               nthreads: Optional[int] = None, options: int = 0):
+    """Every face that counts for each listed pixel, or lies within a margin
+    of counting, sorted by (z, face id): f (int64, -1 past the end), z, bary
+    (3), dists, cls (CLS_*), each (npix, cap), and n (npix,), the number of
+    such faces (only the first cap are listed when n > cap)."""
+    lib = _load()
+    H, W = image_size
+    N = int(np.asarray(first_idx).shape[0])
+    v = _f64(verts)
+    f = _i64(faces)
+    fi = _i64(first_idx)
+    nf = _i64(num_faces)
+    pix = _i64(pixels)
+    npix = pix.shape[0]
+    cap = int(cap)
+    cf = np.empty((npix, cap), np.int64)
+    cz = np.empty((npix, cap), np.float64)
+    cw = np.empty((npix, cap, 3), np.float64)
+    cd = np.empty((npix, cap), np.float64)
+    cc = np.empty((npix, cap), np.uint8)
+    n = np.empty((npix,), np.int64)
+    rc = lib.oracle_candidates(_ptr(v), _ptr(f), _ptr(fi), _ptr(nf), N, H, W, float(blur_radius), _ptr(pix), npix,
+                               cap, _ptr(cf), _ptr(cz), _ptr(cw), _ptr(cd), _ptr(cc), _ptr(n), int(options),
+                               nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("oracle_candidates rejected its arguments")
+    return dict(f=cf, z=cz, bary=cw, dists=cd, cls=cc, n=n)
 
 
 def fragments_fixed(verts, faces, image_size, p2f, nthreads: Optional[int] = None, pixels=None, options: int = 0):

@@ -49,18 +49,25 @@
  *
  * Ambiguity mask (decision margin tau = 1e-6 in linear NDC units): a pixel is
  * flagged when a rounding-level change of the inputs could change its face
- * selection; parity of the face ids is only claimed on unflagged pixels.
+ * selection; exact equality of the face ids is only claimed on unflagged
+ * pixels (any valid answer is still checked there, see oracle_candidates).
  *    M1 blur == 0 and some face passes within tau of the pixel centre
  *    M2 blur > 0 and some face that does not contain the pixel has
  *       abs(sqrt(d2) - sqrt(blur)) < tau
- *    M3 two neighbours among the first min(K+1, hits) sorted hits differ in z
- *       by less than tau
+ *    M3 the set of K faces is tied: the K-th and the (K+1)-th sorted hits
+ *       differ in z by less than tau
  *    M4 some face that covers the pixel has abs(z) < tau
- *    M5 some face has abs(abs(E) - 1e-8) < 1e-3 * 1e-8
+ *    M5 some face that would cover the pixel if it were not degenerate (or
+ *       that does cover it) has abs(abs(E) - 1e-8) < 1e-3 * 1e-8
  *    M6 (per slot, gradients only) the two smallest edge distances of the
  *       slot's face differ by less than tau (in linear units)
  *    M7 (perspective correction) a face that passes the coverage test has a
  *       vertex depth within tau of 0, or sum_j (w_j / z_j) within tau of 0
+ *    M8 only the order is tied: two neighbours among the first K sorted hits
+ *       differ in z by less than tau (the set of K faces is still unique, the
+ *       order inside each run of tied hits is not)
+ * M1, M2, M4, M5 and M7 are also recorded per face by oracle_candidates,
+ * which lists every face that counts or nearly counts for a pixel.
  */
 #include <math.h>
 #include <stdint.h>
@@ -79,6 +86,12 @@
 #define AMB_M4 8
 #define AMB_M5 16
 #define AMB_M7 64
+#define AMB_M8 128
+
+/* per-face classes of oracle_candidates */
+#define CLS_COUNTS 0     /* counts, and no margin case applies to it */
+#define CLS_BORDER_IN 1  /* counts, but within a margin of not counting */
+#define CLS_BORDER_OUT 2 /* does not count, but within a margin of counting */
 
 #define ORC_PERSPECTIVE 0x100
 #define ORC_CLIP 0x200
@@ -89,6 +102,7 @@ typedef struct {
     int64_t f;
     double w[3];
     double sd; /* signed squared distance */
+    int cls;   /* CLS_* */
 } hit_t;
 
 static double cross2(double ux, double uy, double vx, double vy) { return ux * vy - uy * vx; }
@@ -164,12 +178,13 @@ static void apply_options(int opts, const double* a, const double* b, const doub
 }
 
 /* Evaluate face (a, b, c) at pixel p under the options.  Returns 0 if the
- * face is degenerate. */
+ * face is degenerate (abs(E) < 1e-8); its values are still filled in when
+ * E != 0, for the margin test M5. */
 static int eval_face(const double* a, const double* b, const double* c, double px, double py, int opts,
                           eval_t* ev) {
     double E = cross2(b[0] - a[0], b[1] - a[1], c[0] - a[0], c[1] - a[1]);
     ev->E = E;
-    if (fabs(E) < ORC_EPS_AREA) return 0;
+    if (E == 0.0) return 0;
     double e0 = cross2(b[0] - px, b[1] - py, c[0] - px, c[1] - py);
     double e1 = cross2(c[0] - px, c[1] - py, a[0] - px, a[1] - py);
     double e2 = cross2(a[0] - px, a[1] - py, b[0] - px, b[1] - py);
@@ -187,7 +202,7 @@ static int eval_face(const double* a, const double* b, const double* c, double p
     ev->argmin = am;
     ev->d2 = ev->de[am];
     apply_options(opts, a, b, c, ev);
-    return 1;
+    return fabs(E) >= ORC_EPS_AREA;
 }
 
 static int hit_cmp(const void* pa, const void* pb) {
@@ -206,13 +221,89 @@ static void load_vert(const double* verts, int64_t vi, double* out) {
     out[2] = verts[3 * vi + 2];
 }
 
+/* Every face of mesh n tested at pixel centre p: appends to *hits (grown
+ * as needed) the faces that count, and with want_border also those that do
+ * not count but lie within a margin of counting (class CLS_BORDER_OUT);
+ * ORs the per-face margin bits M1, M2, M4, M5, M7 into *am.  Returns the
+ * number of records, or -1 when memory runs out. */
+static int64_t pixel_hits(const double* verts, const int64_t* faces, const int64_t* first, const int64_t* nfaces,
+                          int64_t n, double px, double py, double blur, int opts, int want_border, hit_t** hits,
+                          int64_t* cap, uint8_t* am) {
+    const double sqrt_blur = sqrt(blur);
+    int64_t nh = 0;
+    for (int64_t f = first[n]; f < first[n] + nfaces[n]; ++f) {
+        double a[3], b[3], cc[3];
+        load_vert(verts, faces[3 * f + 0], a);
+        load_vert(verts, faces[3 * f + 1], b);
+        load_vert(verts, faces[3 * f + 2], cc);
+        eval_t ev;
+        const int nondegen = eval_face(a, b, cc, px, py, opts, &ev);
+        if (ev.E == 0.0) continue;
+        if ((opts & ORC_CULL) && ev.E > 0.0) continue;
+        /* the four conditions of counting, each with the margin bit that
+         * makes its outcome uncertain */
+        const double dist = sqrt(ev.d2);
+        const int covers = ev.inside || (ev.d2 < blur);
+        uint8_t b_cov = 0;
+        if (blur == 0.0) {
+            if (dist < ORC_TAU) b_cov = AMB_M1;
+        } else if (!ev.inside && fabs(dist - sqrt_blur) < ORC_TAU) {
+            b_cov = AMB_M2;
+        }
+        const uint8_t b_nd = fabs(fabs(ev.E) - ORC_EPS_AREA) < 1e-3 * ORC_EPS_AREA ? AMB_M5 : 0;
+        uint8_t b_opt = 0;
+        if ((opts & ORC_PERSPECTIVE) &&
+            (fabs(a[2]) < ORC_TAU || fabs(b[2]) < ORC_TAU || fabs(cc[2]) < ORC_TAU || fabs(ev.D) < ORC_TAU))
+            b_opt = AMB_M7;
+        const int z_ok = ev.zf >= 0.0;
+        const uint8_t b_z = fabs(ev.zf) < ORC_TAU ? AMB_M4 : 0;
+        const int counts = nondegen && covers && ev.opts_ok && z_ok;
+        /* could it count under a rounding-level change?  Each condition holds
+         * or is on its margin. */
+        const int could = (nondegen || b_nd) && (covers || b_cov) && (ev.opts_ok || b_opt) && (z_ok || b_z);
+        if (!could) continue;
+        const uint8_t fb = b_cov | b_nd | b_opt | b_z;
+        *am |= fb;
+        if (!counts && !want_border) continue;
+        if (nh == *cap) {
+            int64_t ncap = *cap * 2;
+            hit_t* nhp = (hit_t*)realloc(*hits, sizeof(hit_t) * (size_t)ncap);
+            if (!nhp) return -1;
+            *hits = nhp;
+            *cap = ncap;
+        }
+        hit_t* h = &(*hits)[nh++];
+        h->z = ev.zf;
+        h->f = f;
+        h->w[0] = ev.wf[0];
+        h->w[1] = ev.wf[1];
+        h->w[2] = ev.wf[2];
+        h->sd = ev.inside ? -ev.d2 : ev.d2;
+        h->cls = counts ? (fb ? CLS_BORDER_IN : CLS_COUNTS) : CLS_BORDER_OUT;
+    }
+    return nh;
+}
+
+/* Order-tie bits of a pixel from its sorted hits (faces that count only):
+ * M3 when the K-th and (K+1)-th differ in z by less than tau, M8 when two
+ * neighbours among the first K do. */
+static uint8_t tie_bits(const hit_t* hits, int64_t nh, int K) {
+    uint8_t am = 0;
+    if (nh > K && fabs(hits[K].z - hits[K - 1].z) < ORC_TAU) am |= AMB_M3;
+    int64_t lim = nh < (int64_t)K ? nh : (int64_t)K;
+    for (int64_t j = 0; j + 1 < lim; ++j)
+        if (fabs(hits[j + 1].z - hits[j].z) < ORC_TAU) am |= AMB_M8;
+    return am;
+}
+
 /*
  * Forward over a list of pixels.
  *   verts (V,3) f64, faces (F,3) i64 global vertex ids, first/nfaces (N) i64
  *   pix: linear pixel ids n*H*W + r*W + c (npix of them); NULL = every pixel
  *   outputs per listed pixel i (row-major like the pixel list):
  *     p2f (npix,K) i64, zbuf (npix,K), bary (npix,K,3), dists (npix,K) f64,
- *     amb (npix) u8 bit mask of M1..M5 (may be NULL), nhits (npix) i64 (may be NULL)
+ *     amb (npix) u8 bit mask of M1..M5, M7, M8 (may be NULL),
+ *     nhits (npix) i64 (may be NULL)
  * Returns 0, or -1 on bad arguments / allocation failure.
  */
 int oracle_rasterize(const double* verts, int64_t V, const int64_t* faces, int64_t F,
@@ -224,7 +315,6 @@ int oracle_rasterize(const double* verts, int64_t V, const int64_t* faces, int64
     int64_t total = (int64_t)N * H * W;
     if (pix == NULL) npix = total;
     int bad = 0;
-    double sqrt_blur = sqrt(blur);
 #pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
     {
         int64_t cap = 256;
@@ -242,59 +332,18 @@ int oracle_rasterize(const double* verts, int64_t V, const int64_t* faces, int64
             int64_t r = rem / W, c = rem % W;
             double px, py;
             pixel_center(r, c, H, W, &px, &py);
-            int64_t nh = 0;
             uint8_t am = 0;
             if (n < 0 || n >= N) {
                 bad = 1;
                 continue;
             }
-            for (int64_t f = first[n]; f < first[n] + nfaces[n]; ++f) {
-                double a[3], b[3], cc[3];
-                load_vert(verts, faces[3 * f + 0], a);
-                load_vert(verts, faces[3 * f + 1], b);
-                load_vert(verts, faces[3 * f + 2], cc);
-                eval_t ev;
-                int ok = eval_face(a, b, cc, px, py, opts, &ev);
-                if (fabs(fabs(ev.E) - ORC_EPS_AREA) < 1e-3 * ORC_EPS_AREA) am |= AMB_M5;
-                if (!ok) continue;
-                if ((opts & ORC_CULL) && ev.E > 0.0) continue;
-                double dist = sqrt(ev.d2);
-                if (blur == 0.0) {
-                    if (dist < ORC_TAU) am |= AMB_M1;
-                } else if (!ev.inside && fabs(dist - sqrt_blur) < ORC_TAU) {
-                    am |= AMB_M2;
-                }
-                int covers = ev.inside || (ev.d2 < blur);
-                if (!covers) continue;
-                if (opts & ORC_PERSPECTIVE) {
-                    if (fabs(a[2]) < ORC_TAU || fabs(b[2]) < ORC_TAU || fabs(cc[2]) < ORC_TAU ||
-                        fabs(ev.D) < ORC_TAU)
-                        am |= AMB_M7;
-                }
-                if (!ev.opts_ok) continue;
-                if (fabs(ev.zf) < ORC_TAU) am |= AMB_M4;
-                if (ev.zf < 0.0) continue;
-                if (nh == cap) {
-                    cap *= 2;
-                    hit_t* nhp = (hit_t*)realloc(hits, sizeof(hit_t) * cap);
-                    if (!nhp) {
-                        bad = 1;
-                        break;
-                    }
-                    hits = nhp;
-                }
-                hit_t* h = &hits[nh++];
-                h->z = ev.zf;
-                h->f = f;
-                h->w[0] = ev.wf[0];
-                h->w[1] = ev.wf[1];
-                h->w[2] = ev.wf[2];
-                h->sd = ev.inside ? -ev.d2 : ev.d2;
+            int64_t nh = pixel_hits(verts, faces, first, nfaces, n, px, py, blur, opts, 0, &hits, &cap, &am);
+            if (nh < 0) {
+                bad = 1;
+                continue;
             }
             qsort(hits, (size_t)nh, sizeof(hit_t), hit_cmp);
-            int64_t lim = nh < (int64_t)K + 1 ? nh : (int64_t)K + 1;
-            for (int64_t j = 0; j + 1 < lim; ++j)
-                if (fabs(hits[j + 1].z - hits[j].z) < ORC_TAU) am |= AMB_M3;
+            am |= tie_bits(hits, nh, K);
             for (int k = 0; k < K; ++k) {
                 int64_t o = i * K + k;
                 if (k < nh) {
@@ -318,6 +367,75 @@ int oracle_rasterize(const double* verts, int64_t V, const int64_t* faces, int64
     }
     (void)V;
     (void)F;
+    return bad ? -1 : 0;
+}
+
+/*
+ * Every face that counts for a listed pixel, or lies within a margin of
+ * counting (M1, M2, M4, M5, M7 of that face), sorted by (z, face id): the
+ * material to decide whether some other answer than oracle_rasterize's is
+ * also correct for a flagged pixel.  Per pixel i, up to cap records:
+ *   cf (npix,cap) i64 face id (-1 past the end), cz (npix,cap) z,
+ *   cw (npix,cap,3) barycentrics, cd (npix,cap) signed squared distance,
+ *   ccls (npix,cap) u8 class (CLS_COUNTS, CLS_BORDER_IN, CLS_BORDER_OUT),
+ *   ncand (npix) i64 the number of such faces (may exceed cap: then only
+ *   the first cap are listed).
+ * Returns 0, or -1 on bad arguments / allocation failure.
+ */
+int oracle_candidates(const double* verts, const int64_t* faces, const int64_t* first, const int64_t* nfaces,
+                      int N, int H, int W, double blur, const int64_t* pix, int64_t npix, int cap_out,
+                      int64_t* cf, double* cz, double* cw, double* cd, uint8_t* ccls, int64_t* ncand, int opts,
+                      int nthreads) {
+    if (N < 0 || H <= 0 || W <= 0 || cap_out <= 0 || blur < 0.0 || pix == NULL) return -1;
+    int bad = 0;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
+    {
+        int64_t cap = 256;
+        hit_t* hits = (hit_t*)malloc(sizeof(hit_t) * cap);
+        if (!hits) {
+#pragma omp atomic write
+            bad = 1;
+        }
+#pragma omp for schedule(dynamic, 8)
+        for (int64_t i = 0; i < npix; ++i) {
+            if (!hits) continue;
+            int64_t lin = pix[i];
+            int64_t n = lin / ((int64_t)H * W);
+            int64_t rem = lin % ((int64_t)H * W);
+            double px, py;
+            pixel_center(rem / W, rem % W, H, W, &px, &py);
+            if (n < 0 || n >= N) {
+                bad = 1;
+                continue;
+            }
+            uint8_t am = 0;
+            int64_t nh = pixel_hits(verts, faces, first, nfaces, n, px, py, blur, opts, 1, &hits, &cap, &am);
+            if (nh < 0) {
+                bad = 1;
+                continue;
+            }
+            qsort(hits, (size_t)nh, sizeof(hit_t), hit_cmp);
+            for (int k = 0; k < cap_out; ++k) {
+                int64_t o = i * cap_out + k;
+                if (k < nh) {
+                    cf[o] = hits[k].f;
+                    cz[o] = hits[k].z;
+                    cw[3 * o + 0] = hits[k].w[0];
+                    cw[3 * o + 1] = hits[k].w[1];
+                    cw[3 * o + 2] = hits[k].w[2];
+                    cd[o] = hits[k].sd;
+                    ccls[o] = (uint8_t)hits[k].cls;
+                } else {
+                    cf[o] = -1;
+                    cz[o] = cd[o] = -1.0;
+                    cw[3 * o + 0] = cw[3 * o + 1] = cw[3 * o + 2] = -1.0;
+                    ccls[o] = 255;
+                }
+            }
+            ncand[i] = nh;
+        }
+        free(hits);
+    }
     return bad ? -1 : 0;
 }
 

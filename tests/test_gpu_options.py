@@ -30,7 +30,7 @@ def test_options_forward_vs_oracle(opts, bs):
     out, _ = run_fwd(b, bs, options=opts)
     o = oracle.rasterize(b.verts, b.faces, b.first_idx, b.num_faces, b.image_size, b.blur_radius,
                          b.faces_per_pixel, nthreads=threads(), options=opts)
-    st = compare_fwd(frag_numpy(out), o, b.verts, b.faces, b.blur_radius, f"opts {opts:#x} bs {bs}")
+    st = compare_fwd(frag_numpy(out), o, b, f"opts {opts:#x} bs {bs}", options=opts)
     assert st["slots"] > 1000
     p2f = out.pix_to_face.cpu().numpy()
     if opts & CL:

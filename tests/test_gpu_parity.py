@@ -37,7 +37,7 @@ def test_cfg1_naive_vs_oracle():
     log("cfg1 naive", b.image_size, b.faces.shape)
     out, _ = run_fwd(b, 0)
     o = oracle_full(b)
-    st = compare_fwd(frag_numpy(out), o, b.verts, b.faces, b.blur_radius, "cfg1")
+    st = compare_fwd(frag_numpy(out), o, b, "cfg1")
     log("cfg1", st)
     assert st["slots"] > 1000
 
@@ -61,7 +61,7 @@ def test_reduced_cfg2_vs_oracle_ragged():
     log("cfg2 reduced ragged")
     out, _ = run_fwd(b, 32)
     o = oracle_full(b)
-    st = compare_fwd(frag_numpy(out), o, b.verts, b.faces, b.blur_radius, "cfg2-reduced")
+    st = compare_fwd(frag_numpy(out), o, b, "cfg2-reduced")
     log(st)
 
 
@@ -71,7 +71,7 @@ def test_reduced_cfg3_heterogeneous_vs_oracle():
     for bs, sched in ((0, 0), (16, 1), (24, 0)):
         out, _ = run_fwd(b, bs, sched=sched)
         o = oracle_full(b)
-        st = compare_fwd(frag_numpy(out), o, b.verts, b.faces, b.blur_radius, f"cfg3-reduced bs{bs}")
+        st = compare_fwd(frag_numpy(out), o, b, f"cfg3-reduced bs{bs}")
         log(bs, sched, st)
 
 
@@ -80,7 +80,7 @@ def test_reduced_cfg5_K50_vs_oracle():
     log("cfg5 reduced K=50")
     out, _ = run_fwd(b, 16)
     o = oracle_full(b)
-    st = compare_fwd(frag_numpy(out), o, b.verts, b.faces, b.blur_radius, "cfg5-reduced")
+    st = compare_fwd(frag_numpy(out), o, b, "cfg5-reduced")
     log(st)
 
 
@@ -91,7 +91,7 @@ def test_every_K_bucket(K):
     out, _ = run_fwd(b, 8, K=K)
     o = oracle.rasterize(b.verts, b.faces, b.first_idx, b.num_faces, b.image_size, b.blur_radius, K,
                          nthreads=threads())
-    compare_fwd(frag_numpy(out), o, b.verts, b.faces, b.blur_radius, f"K={K}")
+    compare_fwd(frag_numpy(out), o, b, f"K={K}")
 
 
 def test_batch_equals_per_mesh_bitwise():
@@ -136,7 +136,7 @@ def sampled_check(i, bs, n_pix=1500, seed=0):
     pix = np.unique(np.random.default_rng(seed).integers(0, N * H * W, n_pix))
     o = oracle.rasterize(b.verts, b.faces, b.first_idx, b.num_faces, b.image_size, b.blur_radius,
                          b.faces_per_pixel, pixels=pix, nthreads=threads())
-    st = compare_fwd(frag_numpy(out, pix), o, b.verts, b.faces, b.blur_radius, f"cfg{i}-sampled")
+    st = compare_fwd(frag_numpy(out, pix), o, b, f"cfg{i}-sampled", pixels=pix)
     log(st)
     return b, d, out, pix, o
 
@@ -253,7 +253,7 @@ def test_empty_and_offscreen_meshes():
         assert (out.pix_to_face[1:] == -1).all()
         assert (out.pix_to_face[0] >= 0).any()
         o = oracle_full(b)
-        compare_fwd(frag_numpy(out), o, b.verts, b.faces, b.blur_radius, f"empty bs{bs}")
+        compare_fwd(frag_numpy(out), o, b, f"empty bs{bs}")
 
 
 def test_bin_larger_than_image_and_K_above_hits():
@@ -261,7 +261,7 @@ def test_bin_larger_than_image_and_K_above_hits():
     b.blur_radius = float(np.float32(1e-3))
     out, _ = run_fwd(b, 128, K=12)   # one bin covers the whole 64x64 image
     o = oracle_full(b, K=12)
-    compare_fwd(frag_numpy(out), o, b.verts, b.faces, b.blur_radius, "bin>image")
+    compare_fwd(frag_numpy(out), o, b, "bin>image")
     assert (out.pix_to_face[..., -1] == -1).any() and (out.pix_to_face[..., 0] >= 0).any()
 
 
@@ -279,7 +279,7 @@ def test_degenerate_and_behind_camera_faces():
     for bs in (0, 8):
         out, _ = run_fwd(b, bs)
         o = oracle_full(b)
-        compare_fwd(frag_numpy(out), o, v, f, b.blur_radius, f"degenerate bs{bs}")
+        compare_fwd(frag_numpy(out), o, b, f"degenerate bs{bs}", verts=v, faces=f)
         assert not (out.pix_to_face == 1).any() and not (out.pix_to_face == 2).any()
 
 
