@@ -24,23 +24,29 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRCS = [os.path.join(_HERE, "oracle_rast.c"), os.path.join(_HERE, "oracle_points.c")]
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB_PATH names another build of the same sources (the sanitized
+# build of the CPU checks); by default the in-tree liboracle.so
+_LIB = os.environ.get("ORACLE_LIB_PATH") or os.path.join(_HERE, "liboracle.so")
 _lib = None
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
 
 
 def _stale() -> bool:
     return not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(s) for s in _SRCS)
 
 
-def build(force: bool = True) -> str:
-    """Compile oracle_rast.c into liboracle.so (gcc, -O2, OpenMP, no fast-math)."""
-    if force or _stale():
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
-               "-fno-fast-math", "-ffp-contract=off"] + _SRCS + ["-o", tmp, "-lm"]
+def build(force: bool = True, sanitize: bool = False, out: Optional[str] = None) -> str:
+    """Compile the C oracles into liboracle.so (gcc, -O2, OpenMP, no
+    fast-math), or with AddressSanitizer and UndefinedBehaviorSanitizer into
+    `out`."""
+    path = out or _LIB
+    if force or sanitize or out or _stale():
+        tmp = path + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O1" if sanitize else "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+               "-fno-fast-math", "-ffp-contract=off"] + (SANITIZE if sanitize else []) + _SRCS + ["-o", tmp, "-lm"]
         subprocess.check_call(cmd)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, path)
+    return path
 
 
 def _load():

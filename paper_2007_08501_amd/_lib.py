@@ -13,7 +13,9 @@ import threading
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librast.so")
+# RAST_LIB_PATH names another build of the same sources (the sanitized host
+# build of the CPU checks); by default the in-tree librast.so
+LIB_PATH = os.environ.get("RAST_LIB_PATH") or os.path.join(_HERE, "librast.so")
 
 RAST_OK = 0
 RAST_EINVAL = -1

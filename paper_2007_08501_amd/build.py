@@ -36,17 +36,27 @@ def flags():
             "-I" + os.path.join(HERE, "..", "include")]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link librast.so; always rebuilds."""
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer (the CPU checks of
+# the argument validation and workspace layout); the device code is built as
+# usual.  Each flag is scoped to the host pass.
+SANITIZE_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-Xarch_host",
+                 "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host",
+                 "-shared-libsan"]
+
+
+def build(verbose: bool = False, sanitize_host: bool = False, out: str = None) -> str:
+    """Compile every source and link librast.so (or `out`); always rebuilds."""
     cc = hipcc()
-    objdir = os.path.join(HERE, "_build")
+    lib_path = out or LIB
+    objdir = os.path.join(HERE, "_build" if not sanitize_host else "_build_san")
     os.makedirs(objdir, exist_ok=True)
+    extra = SANITIZE_HOST if sanitize_host else []
     procs = []
     objs = []
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = [cc] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc] + flags() + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -62,11 +72,11 @@ def build(verbose: bool = False) -> str:
             print("\n".join(lines))
     if failed:
         raise RuntimeError("hipcc failed:\n" + "\n\n".join(f"[{s}]\n{t}" for s, t in failed))
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC"] + objs + ["-o", tmp]
+    tmp = lib_path + ".tmp%d" % os.getpid()
+    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC"] + extra + objs + ["-o", tmp]
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":

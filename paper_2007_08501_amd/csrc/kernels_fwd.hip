@@ -14,6 +14,7 @@
 // this is that scheme laid out for 64-wide waves.
 #include "device.hpp"
 #include "launch.hpp"
+#include "tile_layout.hpp"
 
 namespace rast {
 
@@ -201,8 +202,7 @@ struct FineArgs {
 // chunk is exactly one wave wide.  The per-lane lists are bytes: a smaller LDS
 // block lets more tile waves share a CU, and the fine pass is latency-bound
 // enough for that to pay (measured).
-constexpr int kChunk = 64;
-static_assert(kChunk == 64, "the chunk gather takes one list entry per lane of a wave64");
+constexpr int kChunk = tile_layout::kChunk;
 
 // A face as the tile pass keeps it in LDS: the geometry the pixel tests read
 // (the fields of FaceRec that the evaluation uses), the face id, and the
@@ -215,12 +215,13 @@ struct TileRec {
     int fid;
     uint64_t mask;
 };
-static_assert(sizeof(TileRec) == 6 * sizeof(float4), "tile record layout");
+static_assert(sizeof(TileRec) == tile_layout::kTileRecBytes, "tile record layout");
 
 struct TileLds {
     TileRec rec[kChunk];
-    unsigned char lst[kChunk * 64];  // entry i of lane l at [i * 64 + l]
+    unsigned char lst[tile_layout::kListBytes];  // entry i of lane l at [i * 64 + l]
 };
+static_assert(sizeof(TileLds) == tile_layout::kLdsBytes, "tile LDS layout");
 
 // Writes the tile's fragments from the per-lane queues.  Values are staged in
 // LDS per pixel and then stored by consecutive lanes to consecutive
@@ -230,8 +231,8 @@ struct TileLds {
 // separate instructions with loads in between and could be evicted half
 // written.  Ids and depths come straight from the keys; barycentrics and
 // distances are recomputed from the face records.
-constexpr int kStageG1 = 16;  // slots per pass for ids and depths
-constexpr int kStageG2 = 8;   // slots per pass for barycentrics and distances
+constexpr int kStageG1 = tile_layout::kStageG1;  // slots per pass for ids and depths
+constexpr int kStageG2 = tile_layout::kStageG2;  // slots per pass for barycentrics and distances
 
 // EXACT: K equals the bucket size KB, so every group width, stride and index
 // below is a compile-time constant (the common case); otherwise K < KB is a
