@@ -137,6 +137,40 @@ def measured_valu(kernel, config, K, bs, path=None):
         return None
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.partition(":")[2].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_threads() -> int:
+    """Host threads for the oracle: the process's CPUs, at most 16 (a
+    one-GPU share of the host)."""
+    import oracle
+    return min(16, oracle.default_threads())
+
+
+def single_core_rate(b, pix, K):
+    """The oracle's forward+backward rate on one thread, over a slice of the
+    sampled pixels (Mpixel*K/s)."""
+    import numpy as np
+
+    import oracle
+    N, (H, W) = b.N, b.image_size
+    sub = pix[:: max(1, pix.size // 256)]
+    tq = time.perf_counter()
+    o = oracle.rasterize(b.verts, b.faces, b.first_idx, b.num_faces, (H, W), b.blur_radius, K, pixels=sub, nthreads=1)
+    zeros = np.zeros((sub.size, K), np.float32)
+    oracle.backward(b.verts, b.faces, (H, W), o["p2f"], zeros + 1, None, None, nthreads=1, pixels=sub, N=N)
+    dt = time.perf_counter() - tq
+    return {"value": round(sub.size * K / dt / 1e6, 6), "pixels": int(sub.size), "seconds": round(dt, 2)}
+
+
 def cpu_baseline_leg(b, cpu_seconds, v, f, fi, nf, out, gz_np, gb_np, gd_np, bs, M, bws):
     """The FP64 oracle on a bounded seeded sample of the workload's pixels,
     timed on the host cores (forward over every face of each pixel's mesh,
@@ -151,7 +185,7 @@ def cpu_baseline_leg(b, cpu_seconds, v, f, fi, nf, out, gz_np, gb_np, gd_np, bs,
 
     N, (H, W), K = b.N, b.image_size, b.faces_per_pixel
     dev = v.device
-    nthr = min(16, oracle.default_threads())
+    nthr = oracle_threads()
     rng = np.random.default_rng(1234)
     probe = np.sort(rng.choice(N * H * W, size=64, replace=False))
     tq = time.perf_counter()
@@ -177,20 +211,24 @@ def cpu_baseline_leg(b, cpu_seconds, v, f, fi, nf, out, gz_np, gb_np, gd_np, bs,
     t_b = time.perf_counter() - tq
     cpu = {"value": round(P * K / (t_f + t_b) / 1e6, 6), "unit": UNIT, "cores": nthr, "kind": "oracle",
            "sample": f"{P} of {N * H * W} pixels (seeded uniform), FP64 brute force forward over every face "
-                     f"of the pixel's mesh + analytic backward of their slots; fwd {t_f:.2f}s, bwd {t_b:.2f}s"}
+                     f"of the pixel's mesh + analytic backward of their slots; fwd {t_f:.2f}s, bwd {t_b:.2f}s",
+           "cpu_model": cpu_model(), "host_cpus_visible": oracle.default_threads(),
+           "single_core": single_core_rate(b, pix, K)}
 
-    # forward parity on the sampled pixels
+    # forward parity on the sampled pixels: exact ids where the oracle flags
+    # nothing, a correct answer by the oracle's candidates where it does, and
+    # the values within tolerance (oracle.validity)
+    from oracle import validity
     pix_t = torch.from_numpy(pix).to(dev)
     g = {k: t.reshape((N * H * W,) + tuple(t.shape[3:]))[pix_t].cpu().numpy()
          for k, t in zip(("p2f", "zbuf", "bary", "dists"), out)}
+    try:
+        st = validity.compare_fragments(g, o, b.verts, b.faces, b.first_idx, b.num_faces, (H, W), b.blur_radius,
+                                        where=b.name, pixels=pix, nthreads=nthr)
+        fwd_ok, fwd_err = True, None
+    except AssertionError as e:
+        st, fwd_ok, fwd_err = None, False, str(e)[:300]
     amb = o["amb"] != 0
-    p_ok = bool(((g["p2f"] == o["p2f"]).all(-1) | amb).all())
-    same = (g["p2f"] == o["p2f"]) & (o["p2f"] >= 0)
-    wv = o["bary"][same]
-    v_ok = bool((np.abs(g["bary"][same] - wv) <= 1e-5 * np.maximum(1, np.abs(wv))).all()
-                and (np.abs(g["dists"][same] - o["dists"][same]) <= 1e-5).all())
-    fz = b.verts.astype(np.float64)[b.faces[o["p2f"][same]]][..., 2]
-    z_ok = bool((np.abs(g["zbuf"][same] - o["zbuf"][same]) <= 1e-5 * np.maximum(1, np.abs(wv * fz).sum(-1))).all())
     # backward parity: the oracle's selection on the sampled pixels, on both sides
     p2f_s = torch.full_like(out.pix_to_face, -1).view(N * H * W, K)
     p2f_s[pix_t] = torch.from_numpy(o["p2f"].astype(np.int32)).to(dev)
@@ -200,8 +238,14 @@ def cpu_baseline_leg(b, cpu_seconds, v, f, fi, nf, out, gz_np, gb_np, gd_np, bs,
                               t(gb_np), t(gd_m), gv_s, bws)
     gvs = gv_s.cpu().numpy().astype(np.float64)
     gerr = float(np.abs(gvs - ref).max() / max(1e-30, np.abs(ref).max()))
-    parity = {"pixels": int(pix.size), "pix_to_face_ok": p_ok, "values_ok": v_ok and z_ok,
-              "ambiguous_frac": round(float(amb.mean()), 5), "grad_max_rel_err": gerr, "grad_ok": gerr <= 1e-3}
+    parity = {"pixels": int(pix.size), "fragments_ok": fwd_ok, "ambiguous_frac": round(float(amb.mean()), 5),
+              "grad_max_rel_err": gerr, "grad_ok": gerr <= 1e-3}
+    if st is not None:
+        parity.update(flagged_checked=st["checked_flagged"], order_only=st["order_only"],
+                      ambiguous_by_bit={k: round(v, 5) for k, v in st["amb_bits"].items() if v > 0},
+                      max_err={"bary": st["bary_err"], "zbuf": st["z_err"], "dists": st["d_err"]})
+    else:
+        parity["error"] = fwd_err
     return cpu, parity
 
 
@@ -626,7 +670,7 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu, "per_mesh": per_mesh, "parity": parity,
     }
     print(json.dumps(res), flush=True)
-    if parity is not None and not (parity["pix_to_face_ok"] and parity["values_ok"] and parity["grad_ok"]):
+    if parity is not None and not (parity["fragments_ok"] and parity["grad_ok"]):
         sys.exit(3)
 
 

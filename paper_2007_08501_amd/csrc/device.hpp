@@ -150,6 +150,7 @@ struct Eval {
     int edge;      // nearest edge: 0 = (a,b), 1 = (b,c), 2 = (c,a); lowest index on ties
     bool inside;   // all three barycentrics > 0
     float sx, sy;  // p - a (rounded): the pixel relative to vertex a
+    double dx, dy; // p - a, exact
     float f0, f1, f2;  // the edge functions e0, e1, e2 rounded to FP32
 };
 
@@ -176,6 +177,8 @@ __device__ __forceinline__ void eval_bary(const Rec& R, const Pix& p, Eval& o) {
     o.inside = fminf(o.w0, fminf(o.w1, o.w2)) > 0.0f;
     o.sx = (float)dx;
     o.sy = (float)dy;
+    o.dx = dx;
+    o.dy = dy;
 }
 
 // Squared distances from the pixel to the three boundary segments.  For
@@ -191,9 +194,12 @@ struct EdgeD {
 template <class Rec>
 __device__ __forceinline__ void eval_edges(const Rec& R, const Eval& b, EdgeD& o) {
     const float abx = (float)R.ab.x, aby = (float)R.ab.y, acx = (float)R.ac.x, acy = (float)R.ac.y;
-    const float pax = b.sx, pay = b.sy;              // p - a
-    const float pbx = pax - abx, pby = pay - aby;    // p - b
-    const float pcx = pax - acx, pcy = pay - acy;    // p - c
+    // the pixel's offsets from the three vertices, each formed exactly in
+    // FP64 and rounded once: a difference of rounded offsets would lose the
+    // relative accuracy of the distance to b or c close to that vertex
+    const float pax = b.sx, pay = b.sy;                                   // p - a
+    const float pbx = (float)(b.dx - R.ab.x), pby = (float)(b.dy - R.ab.y);  // p - b
+    const float pcx = (float)(b.dx - R.ac.x), pcy = (float)(b.dy - R.ac.y);  // p - c
     const float bcx = acx - abx, bcy = acy - aby;    // c - b
     const float da = fmaf(pax, pax, pay * pay), db = fmaf(pbx, pbx, pby * pby), dc = fmaf(pcx, pcx, pcy * pcy);
     o.t[0] = fmaf(pax, abx, pay * aby) * R.il0;
@@ -308,22 +314,26 @@ __device__ __forceinline__ void pix_range(float vmin, float vmax, int size, int&
     if (hi > size - 1) hi = size - 1;
 }
 
-// Bins [bx0, bx1] x [by0, by1] (bin_size bs) whose pixels may count face R;
-// false when the face counts nowhere on the H x W image.  The binning pass
-// and the backward use this same function, so they agree on every face's
-// bins.
-__device__ __forceinline__ bool face_bins(const FaceRec& R, int H, int W, int bs, int& bx0, int& bx1, int& by0,
-                                          int& by1) {
-    if (!R.ok()) return false;
+// Bins [bx0, bx1] x [by0, by1] (bin_size bs) whose pixels may count a face
+// with grown box bb; false when the face counts nowhere on the H x W image
+// (a face that never counts has an empty box).  The binning pass and the
+// backward use this same function, so they agree on every face's bins.
+__device__ __forceinline__ bool face_bins_of_box(const float4 bb, int H, int W, int bs, int& bx0, int& bx1, int& by0,
+                                                 int& by1) {
     int c0, c1, r0, r1;
-    pix_range(R.bb.x, R.bb.y, W, c0, c1);
-    pix_range(R.bb.z, R.bb.w, H, r0, r1);
+    pix_range(bb.x, bb.y, W, c0, c1);
+    pix_range(bb.z, bb.w, H, r0, r1);
     if (c1 < c0 || r1 < r0) return false;
     bx0 = c0 / bs;
     bx1 = c1 / bs;
     by0 = r0 / bs;
     by1 = r1 / bs;
     return true;
+}
+__device__ __forceinline__ bool face_bins(const FaceRec& R, int H, int W, int bs, int& bx0, int& bx1, int& by0,
+                                          int& by1) {
+    if (!R.ok()) return false;
+    return face_bins_of_box(R.bb, H, W, bs, bx0, bx1, by0, by1);
 }
 
 // Sort key: ascending z, then ascending face id, as one unsigned 64-bit
@@ -464,6 +474,77 @@ __device__ __forceinline__ uint64_t tile_mask(const float4 bb, int H, int W, int
     const uint64_t cols = (uint64_t)((0xffu >> (kTile - 1 - (c1 - c0))) << c0) * 0x0101010101010101ull;
     const uint64_t rows = (~0ull >> (8 * (kTile - 1 - r1))) & (~0ull << (8 * r0));
     return cols & rows;
+}
+
+// Pixels of the 8x8 tile (x0, y0) that a face may count for, by its three
+// edge lines: a pixel counts only inside the triangle or within sqrt(blur)
+// of it, and the triangle lies on the inner side of each edge line, so a
+// pixel more than rg = sqrt(blur) (1 + 1e-4) + 1e-6 outside any one line
+// cannot count (rg is the box pad's radius: it covers the FP32 error of the
+// distance test).  Per line i the edge function at pixel (r, c) of the tile
+// is e_i(r, c) = e_i(0, 0) - c (2/W) A_i - r (2/H) B_i (A_i, B_i its x and y
+// coefficients), and the kept columns of row r are those with
+// sgn(E) e_i > -rg |edge_i|, a half-line in c.  e_i(0, 0), the thresholds
+// the row terms and the column bounds are FP64 (their rounding is far below
+// the margin rg leaves over the test's own error); only the clamped bound is
+// converted.  Conservative: every pixel the test accepts is kept.
+struct EdgeGeo {
+    double2 pa, ab, ac;
+    double E;
+};
+__device__ __forceinline__ double2 f4_as_d2(const float4 v) {
+    return make_double2(__hiloint2double(__float_as_int(v.y), __float_as_int(v.x)),
+                        __hiloint2double(__float_as_int(v.w), __float_as_int(v.z)));
+}
+template <class Rec>
+__device__ __forceinline__ uint64_t edge_mask(const Rec& R, double rg, int H, int W, int x0, int y0) {
+    const double px = 1.0 - (double)(2 * x0 + 1) / (double)W, py = 1.0 - (double)(2 * y0 + 1) / (double)H;
+    const double dx = px - R.pa.x, dy = py - R.pa.y;
+    const double sg = R.E > 0.0 ? 1.0 : -1.0;
+    // e1 = cross(p - a, c - a), e2 = cross(b - a, p - a), e0 = E - e1 - e2
+    const double e1 = dx * R.ac.y - dy * R.ac.x;
+    const double e2 = R.ab.x * dy - R.ab.y * dx;
+    const double e0 = (R.E - e1) - e2;
+    const double A1 = R.ac.y, B1 = -R.ac.x, A2 = -R.ab.y, B2 = R.ab.x;
+    const double A0 = -(A1 + A2), B0 = -(B1 + B2);
+    // edge lengths: e0 <-> (b, c), e1 <-> (c, a), e2 <-> (a, b)
+    const double bcx = R.ac.x - R.ab.x, bcy = R.ac.y - R.ab.y;
+    const double l0 = sqrt(bcx * bcx + bcy * bcy), l1 = sqrt(R.ac.x * R.ac.x + R.ac.y * R.ac.y),
+                 l2 = sqrt(R.ab.x * R.ab.x + R.ab.y * R.ab.y);
+    const double sx = 2.0 / (double)W, sy = 2.0 / (double)H;
+    // keep (r, c) iff c * g_i < k_i - r * h_i for all i, with
+    //   g_i = sg sx A_i,  k_i = sg e_i(0,0) + rg l_i,  h_i = sg sy B_i
+    const double g[3] = {sg * sx * A0, sg * sx * A1, sg * sx * A2};
+    const double k[3] = {sg * e0 + rg * l0, sg * e1 + rg * l1, sg * e2 + rg * l2};
+    const double h[3] = {sg * sy * B0, sg * sy * B1, sg * sy * B2};
+    double ig[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) ig[i] = g[i] != 0.0 ? 1.0 / g[i] : 0.0;
+    uint64_t m = 0ull;
+#pragma unroll
+    for (int r = 0; r < kTile; ++r) {
+        float lo = 0.0f, hi = (float)(kTile - 1);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const double kr = k[i] - (double)r * h[i];
+            if (g[i] == 0.0) {
+                if (!(kr > 0.0)) hi = -1.0f;  // the whole row is outside this line
+            } else {
+                // the row's bound on c, clamped to [-2, 9] before the conversion
+                const float b = (float)fmin(fmax(kr * ig[i], -2.0), 9.0);
+                if (g[i] > 0.0)
+                    hi = fminf(hi, floorf(b));  // c <= k / g (c = k / g kept: conservative)
+                else
+                    lo = fmaxf(lo, ceilf(b));
+            }
+        }
+        if (lo <= hi) {
+            const int a = (int)lo, z = (int)hi;
+            const uint32_t row = (0xffu >> (kTile - 1 - z)) & (0xffu << a);
+            m |= (uint64_t)row << (8 * r);
+        }
+    }
+    return m;
 }
 
 }  // namespace rast

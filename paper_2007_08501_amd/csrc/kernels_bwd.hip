@@ -50,7 +50,6 @@ struct BwdArgs {
     const int* counts;
     const int* lists;
     float* partial;    // (F, 4, 9): a face's nine coordinate sums in the i-th bin of its range
-    float fix_limit;   // contributions below this magnitude use the fixed-point sums
     int bs, nby, nbx, M;
     int reuse;         // records and bins come from the forward: check its signature first
     BinSig sig;        // the signature this call expects
@@ -72,20 +71,30 @@ struct FaceGrad {
     float gx[3], gy[3], gzv[3];
 };
 
-// Adds the contribution of slot s (pixel p) of face R to g.
+// Upstream gradients of slot s (zero for an absent array).
+struct SlotUp {
+    float gz, gb0, gb1, gb2, gd;
+};
+__device__ __forceinline__ SlotUp load_up(const BwdArgs& a, int64_t s) {
+    SlotUp u;
+    u.gz = a.gz ? a.gz[s] : 0.0f;
+    u.gb0 = u.gb1 = u.gb2 = 0.0f;
+    if (a.gb) {
+        u.gb0 = a.gb[3 * s + 0];
+        u.gb1 = a.gb[3 * s + 1];
+        u.gb2 = a.gb[3 * s + 2];
+    }
+    u.gd = a.gd ? a.gd[s] : 0.0f;
+    return u;
+}
+
+// Adds the contribution of a slot of face R at pixel p, with upstream gradients up, to g.
 template <class Rec>
-__device__ __forceinline__ void slot_grad(const BwdArgs& a, const Rec& R, const float (&vz)[3], const Pix& p,
-                                          int64_t s, FaceGrad& g) {
+__device__ __forceinline__ void slot_grad_up(const BwdArgs& a, const Rec& R, const float (&vz)[3], const Pix& p,
+                                             const SlotUp& up, FaceGrad& g) {
     Eval ev;
     eval_full(R, p, ev);
-    float gzs = a.gz ? a.gz[s] : 0.0f;
-    float gb0 = 0.0f, gb1 = 0.0f, gb2 = 0.0f;
-    if (a.gb) {
-        gb0 = a.gb[3 * s + 0];
-        gb1 = a.gb[3 * s + 1];
-        gb2 = a.gb[3 * s + 2];
-    }
-    float gds = a.gd ? a.gd[s] : 0.0f;
+    const float gzs = up.gz, gb0 = up.gb0, gb1 = up.gb1, gb2 = up.gb2, gds = up.gd;
     // dL/dw for the output barycentrics; z = sum_i w_i z_i adds gz z_i
     float G0 = gb0 + gzs * vz[0];
     float G1 = gb1 + gzs * vz[1];
@@ -173,6 +182,12 @@ __device__ __forceinline__ void slot_grad(const BwdArgs& a, const Rec& R, const 
             g.gy[j] += k * Qy;
         }
     }
+}
+
+template <class Rec>
+__device__ __forceinline__ void slot_grad(const BwdArgs& a, const Rec& R, const float (&vz)[3], const Pix& p,
+                                          int64_t s, FaceGrad& g) {
+    slot_grad_up(a, R, vz, p, load_up(a, s), g);
 }
 
 // Scans the K slots of pixel (n, r, c) for face f and accumulates every match.
@@ -357,25 +372,42 @@ __global__ __launch_bounds__(kBwdBlock) void bwd_big_faces_kernel(BwdArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Binned form.  Pass 1: one workgroup per bin streams the slots of the bin's
-// pixels once (coalesced reads of pix_to_face and the gradients), maps each
-// slot's face to its index in the bin's face list through an LDS hash table,
-// and accumulates the nine coordinate sums per listed face in LDS as 64-bit
-// fixed-point integers (scale 2^32): integer LDS atomics are far cheaper than
-// float ones on this hardware, and the per-bin sums become exact and
-// independent of the order of the additions.  A contribution too large for
-// the fixed-point headroom goes to grad_verts directly.  Each listed face's
-// nine sums are then written to the face's own slot for this bin,
-// partial[f][i] for the i-th bin of its range (no global atomic).  Pass 2:
-// one thread per face reads its (at most four) partials, contiguous, merges
-// per vertex in LDS and issues one atomic per (vertex, coordinate).  Faces
-// spanning more than four bins take global atomics directly.
+// Binned form.  Pass 1: one 256-thread workgroup per bin.  The bin's face
+// list is taken in chunks of kP1Chunk faces: the chunk's records go to LDS
+// (one coalesced gather) with a hash table from face id to chunk index; then
+// every thread streams its slots of the bin, kP1Unroll at a time with their
+// id loads issued together, and the slots whose face is in the chunk read
+// their upstream gradients, recompute barycentrics,
+// depth and nearest edge from the record and add their nine vertex-coordinate
+// terms to the face's LDS sums.
+//
+// The sums are 64-bit fixed point: integer LDS atomics cost next to nothing
+// on this hardware, float LDS atomics a great deal (measured at config 4:
+// 2.3 ms for the pass with float LDS atomics, 0.95 ms with integer ones), and
+// integer sums are exact and independent of the order of the additions.  The
+// fixed-point scale is set per bin from the largest upstream gradient of its
+// first round of filled slots (every term is such a gradient times a
+// geometric factor), leaving kGeomBits of headroom for the factor and keeping
+// the at most bin_size^2 terms of one face below 2^60 in total: the grid sits
+// 2^-(60 - 2 log2(bin size) - kGeomBits) below the largest upstream gradient,
+// whatever its size, not at a fixed absolute unit.  A term too large for the
+// scale (a factor beyond 2^kGeomBits, or a later round's larger gradient)
+// goes to grad_verts with a float atomic.
+//
+// At the end of a chunk each listed face writes its nine sums to its own
+// partial row for this bin, partial[f][i] for the i-th bin of its range (no
+// global atomic).  Pass 2: one thread per face reads its (at most four)
+// partials, contiguous, merges per vertex in LDS and issues one atomic per
+// (vertex, coordinate).  Faces spanning more than four bins take global
+// atomics directly.
 // ---------------------------------------------------------------------------
 constexpr int kP1Threads = 256;
 constexpr int kP1Chunk = 160;    // faces staged in LDS per pass over a bin's slots
 constexpr int kP1Table = 512;    // LDS hash entries (>= 2 * kP1Chunk)
 constexpr int kP1Unroll = 4;     // slots per thread whose loads are issued together
 constexpr int kMaxPartials = 4;
+constexpr int kNoScale = -100000;  // the bin's fixed-point scale is not set yet
+constexpr int kGeomBits = 24;      // headroom of the scale for a term's geometric factor
 
 __device__ __forceinline__ uint32_t fhash(int f) { return ((uint32_t)f * 2654435761u) >> (32 - 9); }
 
@@ -418,36 +450,26 @@ __device__ __forceinline__ void store_bin_rec(BinRec& d, const FaceRec& R) {
     d.pad_ = 0.0f;
 }
 
-// One 256-thread workgroup per bin.  The bin's face list is taken in chunks
-// of kP1Chunk faces: the chunk's records go to LDS (one coalesced gather) with
-// a hash table from face id to chunk index, then every thread streams its
-// slots of the bin (kP1Unroll at a time, loads issued together), and the slots
-// whose face is in the chunk add their nine coordinate sums into the chunk's
-// LDS accumulators, as exact 64-bit fixed point; the rare contribution too
-// large for that goes straight to grad_verts with a float atomic.  The LDS
-// block (about 30 KB) lets five workgroups share a CU.  A bin of up to
-// kP1Chunk faces -- most of them -- is one chunk and reads its slots once.
-constexpr double kFixScale = 4294967296.0;  // 2^32
-
-// v * 2^32 as a two's-complement 64-bit fixed-point integer, for abs(v) <
-// 2^30, rounded toward zero.  The magnitude's integer part and fraction are
-// split exactly in FP32 (m - floor(m) is exact for m >= 0) and the fraction
-// scaled by 2^32 (exact), so only fractions below 2^-32 are lost; far
-// cheaper than a conversion through FP64.
-__device__ __forceinline__ unsigned long long to_fix32(float v) {
-    const float m = fabsf(v);
-    const float fm = floorf(m);
-    const unsigned long long q =
-        ((unsigned long long)(unsigned)fm << 32) | (unsigned long long)(unsigned)((m - fm) * 4294967296.0f);
-    return v < 0.0f ? (unsigned long long)(-(long long)q) : q;
+// n / d for n < 2^32, d >= 1, with m = ceil(2^32 / d): the high half of n * m
+// is the quotient or one more; one correction makes it exact.  (d = 1 has no
+// 32-bit m and is passed through.)
+__device__ __forceinline__ uint32_t udiv_magic(uint32_t n, uint32_t d, uint32_t m) {
+    uint32_t q = d == 1u ? n : __umulhi(n, m);
+    if (q * d > n) --q;
+    return q;
+}
+__device__ __forceinline__ uint32_t magic_for(uint32_t d) {
+    return d <= 1u ? 0u : (uint32_t)((0x100000000ull + d - 1) / d);
 }
 
-__global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a) {
+__global__ __launch_bounds__(kP1Threads, 5) void bwd_bins_kernel(BwdArgs a) {
     __shared__ BinRec srec[kP1Chunk];
     __shared__ unsigned long long acci[kP1Chunk * 9];
     __shared__ int tkey[kP1Table];
     __shared__ int tval[kP1Table];
+    __shared__ int umax;  // largest abs upstream gradient of the first filled round (float bits)
     if (!bins_usable(a)) return;
+    const int lane = threadIdx.x & 63;
     const int64_t bin = blockIdx.x;
     const int per_img = a.nby * a.nbx;
     const int n = (int)(bin / per_img);
@@ -457,7 +479,19 @@ __global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a) {
     const int* list = a.lists + bin * a.M;
     const int r0 = by * a.bs, c0 = bx * a.bs;
     const int rows = min(a.bs, a.H - r0), cols = min(a.bs, a.W - c0);
-    const int nslots = rows * cols * a.K;
+    // a row of the bin is rowL contiguous slots: slot e of the bin is slot
+    // q = e mod rowL of bin row e / rowL, pixel column q / K of that row
+    const uint32_t rowL = (uint32_t)cols * (uint32_t)a.K;
+    const uint32_t nslots = (uint32_t)rows * rowL;
+    const uint32_t mrow = magic_for(rowL), mK = magic_for((uint32_t)a.K);
+    const int64_t img_row0 = ((int64_t)n * a.H + r0) * a.W;  // the bin's first row, as a pixel index
+    // a face has at most bs^2 slots in a bin: terms scaled below 2^tbits keep its sum below 2^60
+    int lgbs = 0;
+    while ((1 << lgbs) < a.bs) ++lgbs;
+    const int tbits = 60 - 2 * lgbs;
+    const float tlimit = ldexpf(1.0f, tbits);
+    int scale = kNoScale;  // uniform: every thread derives it from the same LDS word
+    if (threadIdx.x == 0) umax = 0;
     for (int base = 0; base < cnt; base += kP1Chunk) {
         const int m = min(kP1Chunk, cnt - base);
         for (int i = threadIdx.x; i < kP1Table; i += kP1Threads) tkey[i] = -1;
@@ -476,22 +510,43 @@ __global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a) {
             }
         }
         __syncthreads();
-        for (int q0 = 0; q0 < nslots; q0 += kP1Unroll * kP1Threads) {
+        for (uint32_t q0 = 0; q0 < nslots; q0 += kP1Unroll * kP1Threads) {
             int fq[kP1Unroll];
             int64_t sq[kP1Unroll];
-            int rq[kP1Unroll], cq[kP1Unroll];
+            uint32_t rq[kP1Unroll], cq[kP1Unroll];
 #pragma unroll
             for (int u = 0; u < kP1Unroll; ++u) {
-                const int q = q0 + u * kP1Threads + threadIdx.x;
+                const uint32_t e = q0 + (uint32_t)(u * kP1Threads) + threadIdx.x;
                 fq[u] = -1;
-                if (q < nslots) {
-                    const int pl = q / a.K, k = q - pl * a.K;
-                    const int pr = pl / cols;
-                    rq[u] = r0 + pr;
-                    cq[u] = c0 + (pl - pr * cols);
-                    sq[u] = (((int64_t)n * a.H + rq[u]) * a.W + cq[u]) * a.K + k;
+                if (e < nslots) {
+                    rq[u] = udiv_magic(e, rowL, mrow);
+                    const uint32_t q = e - rq[u] * rowL;
+                    cq[u] = udiv_magic(q, (uint32_t)a.K, mK);
+                    sq[u] = (img_row0 + (int64_t)rq[u] * a.W + c0) * a.K + q;
                     fq[u] = a.p2f[sq[u]];
                 }
+            }
+            if (scale == kNoScale) {
+                // the largest upstream gradient of this round's filled slots
+                // (read again, from the cache, by the slots' own terms below)
+                float um = 0.0f;
+#pragma unroll
+                for (int u = 0; u < kP1Unroll; ++u) {
+                    if (fq[u] < 0) continue;
+                    const SlotUp up = load_up(a, sq[u]);
+                    um = fmaxf(um, fmaxf(fmaxf(fabsf(up.gz), fabsf(up.gd)),
+                                         fmaxf(fabsf(up.gb0), fmaxf(fabsf(up.gb1), fabsf(up.gb2)))));
+                }
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) um = fmaxf(um, __shfl_xor(um, o));
+                // non-negative floats order as their bit patterns
+                if (lane == 0 && um > 0.0f) atomicMax(&umax, __float_as_int(um));
+                __syncthreads();
+                const int ub = umax;
+                __syncthreads();  // every thread has read umax before any next-round update
+                // upstream gradients < 2^eb; terms < 2^(eb + kGeomBits) scale below 2^tbits.
+                // While unset, every term of the bin so far is zero.
+                if (ub > 0) scale = tbits - kGeomBits - (((ub >> 23) & 0xff) - 126);
             }
 #pragma unroll
             for (int u = 0; u < kP1Unroll; ++u) {
@@ -514,18 +569,25 @@ __global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a) {
                 FaceGrad g;
 #pragma unroll
                 for (int jj = 0; jj < 3; ++jj) g.gx[jj] = g.gy[jj] = g.gzv[jj] = 0.0f;
-                slot_grad(a, R, vz, make_pix(rq[u], cq[u], a.H, a.W), sq[u], g);
-                const float g9[9] = {g.gx[0], g.gy[0], g.gzv[0], g.gx[1], g.gy[1], g.gzv[1], g.gx[2], g.gy[2],
+                slot_grad(a, R, vz, make_pix(r0 + (int)rq[u], c0 + (int)cq[u], a.H, a.W), sq[u], g);
+                const float t9[9] = {g.gx[0], g.gy[0], g.gzv[0], g.gx[1], g.gy[1], g.gzv[1], g.gx[2], g.gy[2],
                                      g.gzv[2]};
+                bool spill = false;
 #pragma unroll
                 for (int x = 0; x < 9; ++x) {
-                    const float v = g9[x];
-                    if (fabsf(v) < a.fix_limit) {
-                        atomicAdd(&acci[9 * j + x], to_fix32(v));
-                    } else {
-                        // too large for the fixed-point sums (never for sane inputs): straight to the vertex
-                        const int vtx = a.faces[3 * (int64_t)list[base + j] + x / 3];
-                        if (vtx >= 0 && vtx < a.V) atomicAdd(a.grad + 3 * (int64_t)vtx + x % 3, v);
+                    const float sv = ldexpf(t9[x], scale);
+                    const bool fits = fabsf(sv) < tlimit;
+                    spill = spill || !fits;
+                    atomicAdd(&acci[9 * j + x], fits ? (unsigned long long)__float2ll_rn(sv) : 0ull);
+                }
+                if (spill) {
+                    // terms the scale cannot hold go straight to the vertices
+                    const int32_t* fv = a.faces + 3 * (int64_t)f;
+#pragma unroll
+                    for (int x = 0; x < 9; ++x) {
+                        if (fabsf(ldexpf(t9[x], scale)) < tlimit) continue;
+                        const int vtx = fv[x / 3];
+                        if (vtx >= 0 && vtx < a.V) atomicAdd(a.grad + 3 * (int64_t)vtx + x % 3, t9[x]);
                     }
                 }
             }
@@ -538,13 +600,14 @@ __global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a) {
             const int f = list[base + j];
             int bx0, bx1, by0, by1;
             if (!face_bins(a.recs[f], a.H, a.W, a.bs, bx0, bx1, by0, by1)) continue;
+            if (bx < bx0 || bx > bx1 || by < by0 || by > by1) continue;  // only a stale list could do this
             const int nb = (bx1 - bx0 + 1) * (by1 - by0 + 1);
             float g9[9];
 #pragma unroll
-            for (int x = 0; x < 9; ++x) g9[x] = (float)((double)(long long)acci[9 * j + x] * (1.0 / kFixScale));
+            for (int x = 0; x < 9; ++x)
+                g9[x] = scale == kNoScale ? 0.0f : (float)ldexp((double)(long long)acci[9 * j + x], -scale);
             if (nb <= kMaxPartials) {
                 const int i = (by - by0) * (bx1 - bx0 + 1) + (bx - bx0);  // this bin within the face's range
-                if (bx < bx0 || bx > bx1 || by < by0 || by > by1) continue;  // only a stale list could do this
                 float* dst = a.partial + ((int64_t)f * kMaxPartials + i) * 9;
 #pragma unroll
                 for (int x = 0; x < 9; ++x) dst[x] = g9[x];
@@ -568,9 +631,9 @@ __global__ __launch_bounds__(kBwdBlock) void bwd_face_sum_kernel(BwdArgs a) {
     const int64_t f = (int64_t)blockIdx.x * kBwdBlock + threadIdx.x;
     const bool overflowed = (a.hdr[kHdrStatus] & kStatOverflow) != 0;
     if (f < a.F && !overflowed) {
-        const FaceRec R = a.recs[f];
+        // only the grown box of the record decides the face's bins
         int bx0, bx1, by0, by1;
-        if (face_bins(R, a.H, a.W, a.bs, bx0, bx1, by0, by1)) {
+        if (face_bins_of_box(a.recs[f].bb, a.H, a.W, a.bs, bx0, bx1, by0, by1)) {
             const int nbw = bx1 - bx0 + 1;
             const int nb = nbw * (by1 - by0 + 1);
             if (nb <= kMaxPartials) {
@@ -638,13 +701,6 @@ hipError_t launch_backward(const float* verts, int64_t V, const int32_t* faces, 
     a.lists = lists;
     a.partial = partial;
     a.bs = bs;
-    // a face appears in at most bs*bs slots of a bin, each below fix_limit, so
-    // a 64-bit sum of fixed-point values (scale 2^32) stays below 2^62
-    {
-        int lg = 0;
-        while ((1 << lg) < bs) ++lg;
-        a.fix_limit = ldexpf(1.0f, 30 - 2 * lg);
-    }
     a.nby = bs > 0 ? (H + bs - 1) / bs : 0;
     a.nbx = bs > 0 ? (W + bs - 1) / bs : 0;
     a.M = M;

@@ -417,6 +417,8 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
     const float tx_hi = pix_x(tx * kTile, a.W) + mx, tx_lo = pix_x(c_last, a.W) - mx;
     const float ty_hi = pix_y(ty * kTile, a.H) + my, ty_lo = pix_y(r_last, a.H) - my;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    // radius beyond which a pixel outside an edge line cannot count (see edge_mask)
+    const double rg = (double)sqrtf(a.blur) * (1.0 + 1e-4) + 1e-6;
 
     TopK<KB> top;
     top.init();
@@ -447,8 +449,12 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
         const float4* rsrc = reinterpret_cast<const float4*>(a.recs + (in_list ? fid : (BINNED ? list[0] : (int)base)));
         const float4 rv0 = rsrc[0], rv1 = rsrc[1], rv2 = rsrc[2], rv3 = rsrc[3], rv4 = rsrc[4], rv5 = rsrc[5];
         const float4 rv6 = rsrc[6];
-        const uint64_t pm =
-            in_list ? tile_mask(rv6, a.H, a.W, tx * kTile, ty * kTile, tx_lo, tx_hi, ty_lo, ty_hi) : 0ull;
+        uint64_t pm = in_list ? tile_mask(rv6, a.H, a.W, tx * kTile, ty * kTile, tx_lo, tx_hi, ty_lo, ty_hi) : 0ull;
+        if (pm != 0ull) {
+            // narrow the box's pixels to those near or inside the triangle
+            const EdgeGeo G{f4_as_d2(rv0), f4_as_d2(rv1), f4_as_d2(rv2), f4_as_d2(rv3).x};
+            pm &= edge_mask(G, rg, a.H, a.W, tx * kTile, ty * kTile);
+        }
         const bool keep = pm != 0ull;
         const uint64_t kept = __ballot(keep);
         const int m = __popcll(kept);

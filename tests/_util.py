@@ -19,7 +19,7 @@ import numpy as np
 import torch
 
 import oracle
-import _validity
+from oracle import validity as _validity
 from paper_2007_08501_amd import _lib
 from paper_2007_08501_amd.raster import empty_fragments
 
@@ -98,91 +98,16 @@ def frag_numpy(out, pix=None):
             N, H, W = t.shape[:3]
             flat = t.reshape((N * H * W,) + tuple(t.shape[3:]))
             t = flat[torch.from_numpy(np.asarray(pix)).to(t.device)]
-        res[name] = t.cpu().numpy()
+        res[name] = t.detach().cpu().numpy()
     return res
 
 
 def compare_fwd(g, o, b, where="", pixels=None, options=0, verts=None, faces=None):
-    """GPU fragments g against the oracle's o (dicts of arrays, rows of the
-    same pixels: full images, or the listed `pixels`), for batch b (its
-    verts/faces unless given).  Returns stats.
-
-    Face ids: exactly the oracle's on unflagged pixels; up to permutations
-    inside runs of tied depths where the only flag is such a tie (M8); and on
-    every flagged pixel, a correct answer by the oracle's candidate list
-    (tests/_validity.py).  Values of every filled slot against the oracle's
-    FP64 values of the same face at the same pixel:
-      bary   abs(dw_i) <= 1e-5 * max(1, abs(w_i))
-      zbuf   abs(dz)   <= 1e-5, or 1e-5 * sum_i abs(w_i z_i) where some abs(w_i) > 1
-      dists  abs(dd)   <= 1e-5 and <= 1e-5 * abs(d) + 1e-12
-    """
-    verts = b.verts if verts is None else verts
-    faces = b.faces if faces is None else faces
-    K = o["p2f"].shape[-1]
-    amb = o["amb"].reshape(-1).astype(np.int64)
-    pg = g["p2f"].astype(np.int64).reshape(-1, K)
-    po = o["p2f"].reshape(-1, K)
-    npix = pg.shape[0]
-    # pixel ids of the rows, for the candidate lists of flagged rows
-    if pixels is None:
-        rows_pix = np.arange(npix, dtype=np.int64)
-    else:
-        rows_pix = np.asarray(pixels, np.int64).reshape(-1)
-    M8 = oracle.AMB_M8
-    strict = amb == 0
-    bad = (pg != po).any(-1) & strict
-    nbad = int(bad.sum())
-    assert nbad == 0, f"{where}: pix_to_face differs at {nbad} unambiguous pixels, e.g. {np.argwhere(bad)[:5]}"
-    flagged = np.nonzero(~strict)[0]
-    # reference values per row: the oracle's top-K rows for unflagged pixels,
-    # the candidate records of the GPU's own faces for flagged ones
-    ref_f, ref_z, ref_w, ref_d, ref_ok = po.copy(), o["zbuf"].reshape(-1, K).copy(), \
-        o["bary"].reshape(-1, K, 3).copy(), o["dists"].reshape(-1, K).copy(), po >= 0
-    n_order_only = 0
-    if flagged.size:
-        cap = 2 * K + 32
-        c = oracle.candidates(verts, faces, b.first_idx, b.num_faces, b.image_size, b.blur_radius,
-                              rows_pix[flagged], cap=cap, nthreads=threads(), options=options)
-        for j, i in enumerate(flagged):
-            why = _validity.valid_choice(pg[i], c["f"][j], c["z"][j], c["cls"][j], c["n"][j], K)
-            assert why is None, f"{where}: row {i} (pixel {rows_pix[i]}, flags {amb[i]:#x}) GPU ids {pg[i]}: {why}"
-            if amb[i] == M8:
-                n_order_only += 1
-                nf = int((po[i] >= 0).sum())
-                assert _validity.equal_up_to_ties(pg[i], po[i], o["zbuf"].reshape(-1, K)[i, :nf]), \
-                    f"{where}: row {i} ids {pg[i]} differ from the oracle's {po[i]} beyond tied runs"
-            pos = {int(f): q for q, f in enumerate(c["f"][j]) if f >= 0}
-            for k in range(K):
-                f = int(pg[i, k])
-                q = pos.get(f)
-                ok = q is not None and int(c["cls"][j][q]) != _validity.CLS_BORDER_OUT
-                ref_f[i, k] = f
-                ref_ok[i, k] = ok
-                if ok:
-                    ref_z[i, k], ref_w[i, k], ref_d[i, k] = c["z"][j][q], c["bary"][j][q], c["dists"][j][q]
-    gz, gw, gd = g["zbuf"].reshape(-1, K), g["bary"].reshape(-1, K, 3), g["dists"].reshape(-1, K)
-    # empty slots are exactly -1
-    emp = pg < 0
-    assert (gz[emp] == -1).all() and (gd[emp] == -1).all() and (gw[emp] == -1).all(), f"{where}: empty slot values"
-    valid = ref_ok & (pg >= 0)
-    wv = ref_w[valid]
-    dw = np.abs(gw[valid] - wv)
-    assert (dw <= TOL_VAL * np.maximum(1.0, np.abs(wv))).all(), f"{where}: bary max err {dw.max()}"
-    fz = np.asarray(verts, np.float64)[np.asarray(faces)[pg[valid]]][..., 2]  # (n,3) vertex z
-    big_w = (np.abs(wv) > 1).any(-1)
-    zscale = np.where(big_w, np.abs(wv * fz).sum(-1), 1.0)
-    dz = np.abs(gz[valid] - ref_z[valid])
-    assert (dz <= TOL_VAL * zscale).all(), f"{where}: zbuf max err {(dz / zscale).max()}"
-    dref = ref_d[valid]
-    dd = np.abs(gd[valid] - dref)
-    assert (dd <= TOL_VAL).all(), f"{where}: dists max err {dd.max()}"
-    assert (dd <= TOL_VAL * np.abs(dref) + 1e-12).all(), \
-        f"{where}: dists max relative err {(dd / np.maximum(np.abs(dref), 1e-30)).max()}"
-    per_bit = {k: float(((amb & v) != 0).mean()) for k, v in oracle.AMB_BITS.items()}
-    return dict(amb_frac=float((~strict).mean()), amb_bits=per_bit, checked_flagged=int(flagged.size),
-                order_only=n_order_only, slots=int(valid.sum()), rel_branch=int(big_w.sum()),
-                bary_err=float(dw.max()) if dw.size else 0.0, z_err=float(dz.max()) if dz.size else 0.0,
-                d_err=float(dd.max()) if dd.size else 0.0)
+    """GPU fragments g against the oracle's o for batch b (the checks of
+    oracle.validity.compare_fragments, with this module's thread count)."""
+    return _validity.compare_fragments(g, o, b.verts if verts is None else verts, b.faces if faces is None else faces,
+                                       b.first_idx, b.num_faces, b.image_size, b.blur_radius, where=where,
+                                       pixels=pixels, options=options, nthreads=threads())
 
 
 def compare_grad(g, ref, where=""):

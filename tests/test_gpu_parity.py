@@ -13,7 +13,7 @@ import torch
 
 import oracle
 from paper_2007_08501_amd import _lib, meshgen
-from paper_2007_08501_amd.raster import empty_fragments
+from paper_2007_08501_amd.raster import empty_fragments, round_up
 
 from _util import (bin_capacity, compare_fwd, compare_grad, frag_numpy, invariants_torch, log, run_bwd, run_fwd,
                    threads, tie_masked_grads, to_dev)
@@ -124,11 +124,11 @@ def test_forward_deterministic():
 
 # ----------------------------------------------------------------- full-size samples
 
-def sampled_check(i, bs, n_pix=1500, seed=0):
+def sampled_check(i, bs, n_pix=1500, seed=0, sched=1, M=None):
     b = meshgen.make_config(i)
-    log(f"cfg{i} full size", b.image_size, b.faces.shape, "bs", bs)
+    log(f"cfg{i} full size", b.image_size, b.faces.shape, "bs", bs, "M", M, "sched", sched)
     d = to_dev(b)
-    out, _ = run_fwd(b, bs, sched=1, dev_inputs=d)
+    out, _ = run_fwd(b, bs, M=M, sched=sched, dev_inputs=d)
     torch.cuda.synchronize()
     invariants_torch(out, d[2], d[3], b.blur_radius)
     N, (H, W) = b.N, b.image_size
@@ -185,6 +185,18 @@ def test_cfg4_full_size_sampled_and_backward():
     full_backward_check(*sampled_check(4, 16, n_pix=800), bins=(0, 8, 16))
 
 
+def test_cfg4_bench_launch_config_sampled():
+    """Config 4 in the launch configuration the benchmark times (8-pixel
+    bins, capacity rounded up to 32 from the exact count, grid scheduler) on
+    8,192 seeded pixels: exact ids on unflagged pixels, a correct answer by
+    the oracle's candidates on every flagged one, values within tolerance;
+    the fraction flagged per ambiguity bit is logged."""
+    b = meshgen.make_config(4)
+    M = round_up(bin_capacity(b, 8), 32)
+    b, d, out, pix, o = sampled_check(4, 8, n_pix=8192, seed=77, sched=0, M=M)
+    assert pix.size >= 8000
+
+
 # ----------------------------------------------------------------- backward
 
 @pytest.mark.parametrize("bs", [0, 8, 16, 32])
@@ -199,6 +211,22 @@ def test_backward_vs_oracle_small(which, bs):
     gv = run_bwd(b, torch.from_numpy(p2f.astype(np.int32)).cuda(), *sel, bs=bs).cpu().numpy()
     ref = oracle.backward(b.verts, b.faces, b.image_size, p2f, *sel, nthreads=threads())
     compare_grad(gv, ref, which)
+
+
+@pytest.mark.parametrize("bs", [0, 8, 16])
+def test_backward_tiny_upstream_gradients(bs):
+    """Upstream gradients of a mean over every slot of a large image (about
+    1e-8 each, as for config 4's 67 M slots): the binned sums carry no
+    absolute rounding grid, so the result keeps the relative tolerance."""
+    b = meshgen.make_config(2, n_override=3, level_override=3, image_override=64)
+    p2f = oracle_full(b)["p2f"]
+    gz, gb, gd = meshgen.upstream_grads(b)
+    gz, gb, gd = tie_masked_grads(b, p2f, gz, gb, gd)
+    scale = np.float32(1.5e-8)
+    gz, gb, gd = gz * scale, gb * scale, gd * scale
+    gv = run_bwd(b, torch.from_numpy(p2f.astype(np.int32)).cuda(), gz, gb, gd, bs=bs).cpu().numpy()
+    ref = oracle.backward(b.verts, b.faces, b.image_size, p2f, gz, gb, gd, nthreads=threads())
+    log(f"bs{bs} tiny-gradient rel err", compare_grad(gv, ref, f"tiny upstream bs{bs}"))
 
 
 def test_backward_hand_case():

@@ -15,7 +15,7 @@ import math
 import numpy as np
 import pytest
 
-import _validity
+from oracle import validity as _validity
 import oracle
 
 T_VERTS = np.array([[-1.0, -1.0, 1.0], [1.0, -1.0, 2.0], [-1.0, 1.0, 3.0]])
