@@ -64,6 +64,7 @@ enum rast_status {
     RAST_EOVERFLOW = -4,   /* device: a bin received more than max_faces_per_bin faces */
     RAST_EMESH = -5,       /* device: mesh face ranges out of [0, F) or not ascending */
     RAST_EREUSE = -6,      /* device: a backward asked to reuse bins that the workspace does not hold */
+    RAST_ESCRATCH = -7,    /* rasterize_meshes_fwd_static: the problem needs more than RAST_STATIC_SCRATCH_BYTES */
 };
 
 #define RAST_KMAX 64     /* largest faces_per_pixel */
@@ -133,6 +134,32 @@ int rasterize_meshes_fwd(const float* verts_packed, int64_t V, const int32_t* fa
                          int N, int H, int W, float blur_radius, int faces_per_pixel, int bin_size,
                          int max_faces_per_bin, int sched, int options, int32_t* pix_to_face, float* zbuf,
                          float* bary, float* dists, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the forward
+ * above with the library's own scratch array in place of a caller workspace.
+ * Same arguments, outputs and results as rasterize_meshes_fwd, except:
+ *   - no workspace: the face records, bins and status word live in one
+ *     static device array of RAST_STATIC_SCRATCH_BYTES per GPU, held from
+ *     the first call on that GPU until the process ends; a problem whose
+ *     rast_workspace_size() exceeds it is refused with RAST_ESCRATCH before
+ *     any launch.  Nothing is allocated (no hipMalloc, no allocating library
+ *     call); the scratch keeps the last call's contents and every call clears
+ *     what it needs.
+ *   - status_out: device int32[2], written at the end of the call on the
+ *     stream: [0] the device-detected status (RAST_OK, RAST_EOVERFLOW,
+ *     RAST_EMESH), [1] the largest bin count seen.  NULL: not written.
+ *   - calls that overlap on one GPU (other streams or host threads) share the
+ *     array and race: serialise them.  The scratch holds no bins for
+ *     rasterize_meshes_bwd to reuse (use the workspace forms for training).
+ */
+#define RAST_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int rasterize_meshes_fwd_static(const float* verts_packed, int64_t V, const int32_t* faces_packed, int64_t F,
+                                const int64_t* mesh_to_face_first_idx, const int64_t* num_faces_per_mesh,
+                                int N, int H, int W, float blur_radius, int faces_per_pixel, int bin_size,
+                                int max_faces_per_bin, int sched, int options, int32_t* pix_to_face, float* zbuf,
+                                float* bary, float* dists, int32_t* status_out, void* stream);
 
 /*
  * Backward (paper, Section 3.2: gradients with respect to the inputs, from the

@@ -24,6 +24,8 @@ RAST_EHIP = -3
 RAST_EOVERFLOW = -4
 RAST_EMESH = -5
 RAST_EREUSE = -6
+RAST_ESCRATCH = -7
+RAST_STATIC_SCRATCH_BYTES = 64 << 20
 RAST_BWD_REUSE_FORWARD = 1
 RAST_KMAX = 64
 RAST_TILE = 8
@@ -63,6 +65,8 @@ def lib() -> ctypes.CDLL:
         sz = ctypes.c_size_t
         L.rast_workspace_size.argtypes = [ci, ci, ci, i64, ci, ci, ctypes.POINTER(sz)]
         L.rasterize_meshes_fwd.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, cf, ci, ci, ci, ci, ci, P, P, P, P, P, sz, P]
+        L.rasterize_meshes_fwd_static.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, cf, ci, ci, ci, ci, ci, P, P, P, P,
+                                                  P, P]
         L.rasterize_meshes_bwd.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, cf, ci, ci, ci, ci, P, P, P, P, P, P, sz, P]
         L.rast_bin_count.argtypes = [P, i64, P, i64, P, P, ci, ci, ci, cf, ci, P, sz, P]
         L.rast_query_status.argtypes = [P, ctypes.POINTER(ci), ctypes.POINTER(ci), P]
@@ -78,7 +82,8 @@ def lib() -> ctypes.CDLL:
         L.rasterize_points_bwd.argtypes = [P, i64, P, P, ci, ci, ci, cf, ci, ci, P, P, P, P, P, sz, P]
         L.points_composite_fwd.argtypes = [P, P, P, i64, i64, ci, ci, ci, cf, P, P]
         L.points_composite_bwd.argtypes = [P, P, P, i64, i64, ci, ci, ci, cf, P, P, P, P]
-        for fn in ("rast_workspace_size", "rasterize_meshes_fwd", "rasterize_meshes_bwd", "rast_bin_count",
+        for fn in ("rast_workspace_size", "rasterize_meshes_fwd", "rasterize_meshes_fwd_static", "rasterize_meshes_bwd",
+                   "rast_bin_count",
                    "rast_query_status", "silhouette_blend_fwd", "silhouette_blend_bwd", "rast_set_kernel_events",
                    "softmax_blend_fwd", "softmax_blend_bwd", "rast_points_workspace_size", "rasterize_points_fwd",
                    "rasterize_points_bwd", "points_composite_fwd", "points_composite_bwd"):
@@ -87,7 +92,8 @@ def lib() -> ctypes.CDLL:
         return L
 
 
-EXPORTS = ("rast_workspace_size", "rasterize_meshes_fwd", "rasterize_meshes_bwd", "rast_bin_count",
+EXPORTS = ("rast_workspace_size", "rasterize_meshes_fwd", "rasterize_meshes_fwd_static", "rasterize_meshes_bwd",
+           "rast_bin_count",
            "rast_query_status", "rast_status_string", "silhouette_blend_fwd", "silhouette_blend_bwd",
            "rast_set_kernel_events", "softmax_blend_fwd", "softmax_blend_bwd", "rast_points_workspace_size",
            "rasterize_points_fwd", "rasterize_points_bwd", "points_composite_fwd", "points_composite_bwd")
@@ -177,6 +183,33 @@ def rasterize_meshes_fwd(verts, faces, first_idx, num_faces, H, W, blur_radius, 
                                     int(max_faces_per_bin or 0), int(sched), int(options), _p(pix_to_face), _p(zbuf),
                                     _p(bary), _p(dists), _p(workspace), workspace.numel(), _stream(dev))
     _check("rasterize_meshes_fwd", rc)
+
+
+def rasterize_meshes_fwd_static(verts, faces, first_idx, num_faces, H, W, blur_radius, K, bin_size,
+                                max_faces_per_bin, sched, pix_to_face, zbuf, bary, dists, status_out, options=0):
+    """The forward on the library's static scratch (no workspace argument);
+    status_out: int32 device tensor of 2 (device status, largest bin count) or None."""
+    dev = verts.device
+    _require(verts, "verts", torch.float32, dev)
+    _require(faces, "faces", torch.int32, dev)
+    _require(first_idx, "mesh_to_face_first_idx", torch.int64, dev)
+    _require(num_faces, "num_faces_per_mesh", torch.int64, dev)
+    for t, n, d in ((pix_to_face, "pix_to_face", torch.int32), (zbuf, "zbuf", torch.float32),
+                    (bary, "bary", torch.float32), (dists, "dists", torch.float32),
+                    (status_out, "status_out", torch.int32)):
+        _require(t, n, d, dev)
+    if status_out is not None and status_out.numel() < 2:
+        raise ValueError("status_out must hold 2 int32")
+    N = _mesh_shapes(verts, faces, first_idx, num_faces)
+    shp = (N, int(H), int(W), int(K))
+    _same_shape("N,H,W,K", shp, (pix_to_face, "pix_to_face"), (zbuf, "zbuf"), (dists, "dists"))
+    _same_shape("N,H,W,K", shp + (3,), (bary, "bary"))
+    rc = lib().rasterize_meshes_fwd_static(_p(verts), verts.shape[0], _p(faces), faces.shape[0], _p(first_idx),
+                                           _p(num_faces), int(N), int(H), int(W), float(blur_radius), int(K),
+                                           int(bin_size), int(max_faces_per_bin or 0), int(sched), int(options),
+                                           _p(pix_to_face), _p(zbuf), _p(bary), _p(dists), _p(status_out),
+                                           _stream(dev))
+    _check("rasterize_meshes_fwd_static", rc)
 
 
 def rasterize_meshes_bwd(verts, faces, first_idx, num_faces, H, W, blur_radius, K, bin_size, max_faces_per_bin,

@@ -7,6 +7,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <atomic>
+
 #include <hip/hip_runtime.h>
 
 #include "../../include/rast.h"
@@ -101,6 +103,30 @@ thread_local KernelEvents tl_events;
 
 }  // namespace
 
+// The scratch of rasterize_meshes_fwd_static: one per GPU, for the life of the
+// process.  In host code its name is only a stand-in: kernels get the
+// device address from hipGetSymbolAddress, taken once per device.
+static __device__ __align__(256) unsigned char scratch[RAST_STATIC_SCRATCH_BYTES];
+
+namespace {
+std::atomic<void*> g_scratch_addr[kMaxDevices];
+
+// Device address of the current device's scratch (looked up on the first
+// call on that device); nullptr if the device or the lookup fails.
+void* static_scratch_ptr() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    void* p = g_scratch_addr[dev].load(std::memory_order_acquire);
+    if (p == nullptr) {
+        void* q = nullptr;
+        if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || q == nullptr) return nullptr;
+        g_scratch_addr[dev].store(q, std::memory_order_release);
+        p = q;
+    }
+    return p;
+}
+}  // namespace
+
 static rast::BinSig bin_signature(int64_t F, int N, int H, int W, int bs, int M, float blur, int opts) {
     rast::BinSig g;
     uint32_t bb;
@@ -111,24 +137,13 @@ static rast::BinSig bin_signature(int64_t F, int N, int H, int W, int bs, int M,
     return g;
 }
 
-extern "C" {
-
-int rast_workspace_size(int N, int H, int W, int64_t F, int bin_size, int max_faces_per_bin, size_t* bytes_out) {
-    if (bytes_out == nullptr) return RAST_EINVAL;
-    if (N < 1 || H < 1 || W < 1 || F < 0 || F > INT32_MAX) return RAST_EINVAL;
-    if (bin_size < 0 || bin_size > RAST_MAX_BIN || (bin_size % RAST_TILE) != 0) return RAST_EINVAL;
-    if (bin_size > 0 && max_faces_per_bin < 1) return RAST_EINVAL;
-    Layout L;
-    if (!make_layout(N, H, W, F, bin_size, max_faces_per_bin, &L)) return RAST_EINVAL;
-    *bytes_out = L.total;
-    return RAST_OK;
-}
-
-int rasterize_meshes_fwd(const float* verts_packed, int64_t V, const int32_t* faces_packed, int64_t F,
-                         const int64_t* mesh_to_face_first_idx, const int64_t* num_faces_per_mesh, int N, int H,
-                         int W, float blur_radius, int faces_per_pixel, int bin_size, int max_faces_per_bin,
-                         int sched, int options, int32_t* pix_to_face, float* zbuf, float* bary, float* dists,
-                         void* workspace, size_t workspace_bytes, void* stream) {
+// The forward on a caller workspace or the static scratch.  status_out
+// (device, nullable) receives the device status at the end of the call.
+static int fwd_impl(const float* verts_packed, int64_t V, const int32_t* faces_packed, int64_t F,
+                    const int64_t* mesh_to_face_first_idx, const int64_t* num_faces_per_mesh, int N, int H, int W,
+                    float blur_radius, int faces_per_pixel, int bin_size, int max_faces_per_bin, int sched,
+                    int options, int32_t* pix_to_face, float* zbuf, float* bary, float* dists, void* workspace,
+                    size_t workspace_bytes, bool static_scratch, int32_t* status_out, void* stream) {
     if (bad_dims(N, H, W, faces_per_pixel)) return RAST_EINVAL;
     if ((options & ~rast::kOptMask) != 0) return RAST_EINVAL;
     if (V < 0 || V > INT32_MAX || F < 0 || F > INT32_MAX) return RAST_EINVAL;
@@ -141,6 +156,12 @@ int rasterize_meshes_fwd(const float* verts_packed, int64_t V, const int32_t* fa
     if (sched != RAST_SCHED_GRID && sched != RAST_SCHED_PERSISTENT) return RAST_EINVAL;
     Layout L;
     if (!make_layout(N, H, W, F, bin_size, max_faces_per_bin, &L)) return RAST_EINVAL;
+    if (static_scratch) {
+        if (L.total > RAST_STATIC_SCRATCH_BYTES) return RAST_ESCRATCH;
+        workspace = static_scratch_ptr();
+        workspace_bytes = RAST_STATIC_SCRATCH_BYTES;
+        if (workspace == nullptr) return RAST_EHIP;
+    }
     if (workspace == nullptr || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < L.total)
         return RAST_EWORKSPACE;
 
@@ -170,7 +191,42 @@ int rasterize_meshes_fwd(const float* verts_packed, int64_t V, const int32_t* fa
                           (int*)(ws + L.order),
                           (int*)(ws + L.hist), hdr, n_workers, pix_to_face, zbuf, bary, dists, s,
                           tl_events.begin[RAST_KERNEL_FINE], tl_events.end[RAST_KERNEL_FINE]);
+    if (e != hipSuccess) return RAST_EHIP;
+    if (status_out != nullptr) e = rast::launch_status_out(hdr, status_out, s);
     return hip_rc(e);
+}
+
+extern "C" {
+
+int rast_workspace_size(int N, int H, int W, int64_t F, int bin_size, int max_faces_per_bin, size_t* bytes_out) {
+    if (bytes_out == nullptr) return RAST_EINVAL;
+    if (N < 1 || H < 1 || W < 1 || F < 0 || F > INT32_MAX) return RAST_EINVAL;
+    if (bin_size < 0 || bin_size > RAST_MAX_BIN || (bin_size % RAST_TILE) != 0) return RAST_EINVAL;
+    if (bin_size > 0 && max_faces_per_bin < 1) return RAST_EINVAL;
+    Layout L;
+    if (!make_layout(N, H, W, F, bin_size, max_faces_per_bin, &L)) return RAST_EINVAL;
+    *bytes_out = L.total;
+    return RAST_OK;
+}
+
+int rasterize_meshes_fwd(const float* verts_packed, int64_t V, const int32_t* faces_packed, int64_t F,
+                         const int64_t* mesh_to_face_first_idx, const int64_t* num_faces_per_mesh, int N, int H,
+                         int W, float blur_radius, int faces_per_pixel, int bin_size, int max_faces_per_bin,
+                         int sched, int options, int32_t* pix_to_face, float* zbuf, float* bary, float* dists,
+                         void* workspace, size_t workspace_bytes, void* stream) {
+    return fwd_impl(verts_packed, V, faces_packed, F, mesh_to_face_first_idx, num_faces_per_mesh, N, H, W,
+                    blur_radius, faces_per_pixel, bin_size, max_faces_per_bin, sched, options, pix_to_face, zbuf,
+                    bary, dists, workspace, workspace_bytes, false, nullptr, stream);
+}
+
+int rasterize_meshes_fwd_static(const float* verts_packed, int64_t V, const int32_t* faces_packed, int64_t F,
+                                const int64_t* mesh_to_face_first_idx, const int64_t* num_faces_per_mesh, int N,
+                                int H, int W, float blur_radius, int faces_per_pixel, int bin_size,
+                                int max_faces_per_bin, int sched, int options, int32_t* pix_to_face, float* zbuf,
+                                float* bary, float* dists, int32_t* status_out, void* stream) {
+    return fwd_impl(verts_packed, V, faces_packed, F, mesh_to_face_first_idx, num_faces_per_mesh, N, H, W,
+                    blur_radius, faces_per_pixel, bin_size, max_faces_per_bin, sched, options, pix_to_face, zbuf,
+                    bary, dists, nullptr, 0, true, status_out, stream);
 }
 
 int rasterize_meshes_bwd(const float* verts_packed, int64_t V, const int32_t* faces_packed, int64_t F,
@@ -267,6 +323,7 @@ const char* rast_status_string(int status) {
         case RAST_EOVERFLOW: return "a bin received more faces than max_faces_per_bin";
         case RAST_EMESH: return "mesh face ranges or vertex ids out of range";
         case RAST_EREUSE: return "the workspace does not hold the bins of a matching forward";
+        case RAST_ESCRATCH: return "the problem needs more than the static scratch (RAST_STATIC_SCRATCH_BYTES)";
         default: return "unknown status";
     }
 }

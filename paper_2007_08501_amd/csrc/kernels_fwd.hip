@@ -12,6 +12,7 @@
 // The paper's rasterizer (Section 3.2) first works on image tiles to drop
 // faces and then on pixels, keeping per-pixel queues of the K nearest faces;
 // this is that scheme laid out for 64-wide waves.
+#include "../../include/rast.h"
 #include "device.hpp"
 #include "launch.hpp"
 #include "tile_layout.hpp"
@@ -51,6 +52,21 @@ __global__ void header_init_kernel(int* __restrict__ hdr, BinSig sig) {
 
 hipError_t launch_header_init(int* hdr, const BinSig& sig, hipStream_t s) {
     hipLaunchKernelGGL(header_init_kernel, dim3(1), dim3(64), 0, s, hdr, sig);
+    return hipGetLastError();
+}
+
+// The header's status bits as a rast_status code (the same precedence as
+// rast_query_status) and its largest bin count, for a caller without a workspace.
+__global__ void status_out_kernel(const int* __restrict__ hdr, int32_t* __restrict__ out) {
+    if (threadIdx.x == 0) {
+        const int h = hdr[kHdrStatus];
+        out[0] = (h & kStatMesh) ? RAST_EMESH : ((h & kStatOverflow) ? RAST_EOVERFLOW : RAST_OK);
+        out[1] = hdr[kHdrMaxCount];
+    }
+}
+
+hipError_t launch_status_out(const int* hdr, int32_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(status_out_kernel, dim3(1), dim3(64), 0, s, hdr, out);
     return hipGetLastError();
 }
 

@@ -11,6 +11,8 @@ namespace rast {
 hipError_t launch_fill_i32(int* p, int64_t n, int v, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_header_init(int* hdr, const BinSig& sig, hipStream_t s);
+// out[0] = the header's device status as a rast_status code, out[1] = its largest bin count
+hipError_t launch_status_out(const int* hdr, int32_t* out, hipStream_t s);
 
 hipError_t launch_face_setup(const float* verts, int64_t V, const int32_t* faces, int64_t F, const int64_t* first,
                              const int64_t* nf, int N, float rb, int opts, FaceRec* recs, int* hdr, hipStream_t s);

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     for code in (_lib.RAST_OK, _lib.RAST_EINVAL, _lib.RAST_EWORKSPACE, _lib.RAST_EHIP, _lib.RAST_EOVERFLOW,
-                 _lib.RAST_EMESH, _lib.RAST_EREUSE):
+                 _lib.RAST_EMESH, _lib.RAST_EREUSE, _lib.RAST_ESCRATCH):
         s = _lib.status_string(code)
         assert s and s != "unknown status"
     assert _lib.status_string(12345) == "unknown status"
@@ -232,3 +232,23 @@ def test_points_composite_rejects_bad_arguments():
     bad = list(gb)
     bad[4], bad[10] = 10, None
     assert L.points_composite_bwd(*bad) == _lib.RAST_EINVAL
+
+
+def test_static_forward_refuses_oversize_before_any_launch():
+    """rasterize_meshes_fwd_static: a problem whose workspace would exceed the
+    static scratch is refused on the host (no device is touched: the
+    pointers below are never dereferenced)."""
+    L = _lib.lib()
+    dummy = ctypes.c_void_p(256)
+    H = W = 64
+    nbins = (H // 8) * (W // 8)
+    M = _lib.RAST_STATIC_SCRATCH_BYTES // (4 * nbins) + 1
+    rc, need = ws_size(1, H, W, 320, 8, M)
+    assert rc == 0 and need > _lib.RAST_STATIC_SCRATCH_BYTES
+    args = [dummy, 162, dummy, 320, dummy, dummy, 1, H, W, 0.0, 1, 8, M, 0, 0, dummy, dummy, dummy, dummy, None, None]
+    assert L.rasterize_meshes_fwd_static(*args) == _lib.RAST_ESCRATCH
+    # argument checks come first, as for the workspace form
+    bad = list(args)
+    bad[10] = 0  # K
+    assert L.rasterize_meshes_fwd_static(*bad) == _lib.RAST_EINVAL
+
