@@ -39,6 +39,7 @@ enum : int {
     kHdrWorkTotal = 3,  // persistent scheduler: number of work items
     kHdrBigCount = 8,   // backward: number of faces with large pixel boxes
     kHdrBigNext = 9,    // backward: next large face to scan
+    kHdrTermMax = 10,   // backward: largest abs face sum of the binned pass (float bits)
     kHdrSig = 16,       // kSigWords words: what the last forward binned (see BinSig)
     kHdrWords = 64,
 };

@@ -372,42 +372,37 @@ __global__ __launch_bounds__(kBwdBlock) void bwd_big_faces_kernel(BwdArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Binned form.  Pass 1: one 256-thread workgroup per bin.  The bin's face
-// list is taken in chunks of kP1Chunk faces: the chunk's records go to LDS
-// (one coalesced gather) with a hash table from face id to chunk index; then
-// every thread streams its slots of the bin, kP1Unroll at a time with their
-// id loads issued together, and the slots whose face is in the chunk read
-// their upstream gradients, recompute barycentrics,
-// depth and nearest edge from the record and add their nine vertex-coordinate
-// terms to the face's LDS sums.
-//
-// The sums are 64-bit fixed point: integer LDS atomics cost next to nothing
-// on this hardware, float LDS atomics a great deal (measured at config 4:
-// 2.3 ms for the pass with float LDS atomics, 0.95 ms with integer ones), and
-// integer sums are exact and independent of the order of the additions.  The
-// fixed-point scale is set per bin from the largest upstream gradient of its
-// first round of filled slots (every term is such a gradient times a
-// geometric factor), leaving kGeomBits of headroom for the factor and keeping
-// the at most bin_size^2 terms of one face below 2^60 in total: the grid sits
-// 2^-(60 - 2 log2(bin size) - kGeomBits) below the largest upstream gradient,
-// whatever its size, not at a fixed absolute unit.  A term too large for the
-// scale (a factor beyond 2^kGeomBits, or a later round's larger gradient)
-// goes to grad_verts with a float atomic.
-//
-// At the end of a chunk each listed face writes its nine sums to its own
-// partial row for this bin, partial[f][i] for the i-th bin of its range (no
-// global atomic).  Pass 2: one thread per face reads its (at most four)
-// partials, contiguous, merges per vertex in LDS and issues one atomic per
-// (vertex, coordinate).  Faces spanning more than four bins take global
-// atomics directly.
+// Binned form.  Pass 1: one workgroup per bin streams the slots of the bin's
+// pixels once (coalesced reads of pix_to_face and the gradients), maps each
+// slot's face to its index in the bin's face list through an LDS hash table,
+// and accumulates the nine coordinate sums per listed face in LDS as 64-bit
+// fixed-point integers: integer LDS atomics cost next to nothing on this
+// hardware and float LDS atomics a great deal (measured at config 4: 2.3 ms
+// for the pass with float LDS atomics, 0.95 ms with integer ones), and the
+// per-bin sums become exact and independent of the order of the additions.
+// The grid is 2^-S with S = 38 - 2 log2(bin size) (2^-32 at bin size 8), so
+// that a face's at most bin_size^2 terms below 2^24 cannot overflow; a term
+// of 2^24 or more (a sliver's geometric factor times a large gradient) goes
+// to grad_verts directly with a float atomic, which is slow: the headroom
+// keeps those rare.  Terms are rounded to the
+// nearest grid point.  The pass records the largest face sum of the call
+// (at the flush, off the hot loop); if it lies below 2^(22 - S) -- gradients
+// so small that the grid holds them to fewer than 22 bits -- a second launch
+// of the pass (the rescue) redoes the sums on a grid 2^30 times finer than
+// that largest sum, after the vertex gradients are cleared again (a term
+// that then exceeds the grid's headroom goes to grad_verts directly).
+// Normally the rescue launch only reads the recorded sum and exits.  Each listed face's
+// nine sums are then written to the face's own slot for this bin,
+// partial[f][i] for the i-th bin of its range (no global atomic).  Pass 2:
+// one thread per face reads its (at most four) partials, contiguous, merges
+// per vertex in LDS and issues one atomic per (vertex, coordinate).  Faces
+// spanning more than four bins take global atomics directly.
 // ---------------------------------------------------------------------------
 constexpr int kP1Threads = 256;
 constexpr int kP1Chunk = 160;    // faces staged in LDS per pass over a bin's slots
 constexpr int kP1Table = 512;    // LDS hash entries (>= 2 * kP1Chunk)
 constexpr int kP1Unroll = 4;     // slots per thread whose loads are issued together
 constexpr int kMaxPartials = 4;
-constexpr int kNoScale = -100000;  // the bin's fixed-point scale is not set yet
-constexpr int kGeomBits = 24;      // headroom of the scale for a term's geometric factor
 
 __device__ __forceinline__ uint32_t fhash(int f) { return ((uint32_t)f * 2654435761u) >> (32 - 9); }
 
@@ -450,26 +445,57 @@ __device__ __forceinline__ void store_bin_rec(BinRec& d, const FaceRec& R) {
     d.pad_ = 0.0f;
 }
 
-// n / d for n < 2^32, d >= 1, with m = ceil(2^32 / d): the high half of n * m
-// is the quotient or one more; one correction makes it exact.  (d = 1 has no
-// 32-bit m and is passed through.)
-__device__ __forceinline__ uint32_t udiv_magic(uint32_t n, uint32_t d, uint32_t m) {
-    uint32_t q = d == 1u ? n : __umulhi(n, m);
-    if (q * d > n) --q;
-    return q;
-}
-__device__ __forceinline__ uint32_t magic_for(uint32_t d) {
-    return d <= 1u ? 0u : (uint32_t)((0x100000000ull + d - 1) / d);
+// One 256-thread workgroup per bin.  The bin's face list is taken in chunks
+// of kP1Chunk faces: the chunk's records go to LDS (one coalesced gather) with
+// a hash table from face id to chunk index, then every thread streams its
+// slots of the bin (kP1Unroll at a time, loads issued together), and the slots
+// whose face is in the chunk add their nine coordinate sums into the chunk's
+// LDS accumulators, as exact 64-bit fixed point; the rare contribution too
+// large for that goes straight to grad_verts with a float atomic.  The LDS
+// block (about 30 KB) lets five workgroups share a CU.  A bin of up to
+// kP1Chunk faces -- most of them -- is one chunk and reads its slots once.
+constexpr int kFixBits = 38;     // fixed-point grid 2^-(kFixBits - 2 log2(bin size))
+constexpr int kRescueBits = 22;  // a largest face sum below 2^22 grid points triggers the rescue
+
+// v * 2^S, rounded to nearest, as a two's-complement 64-bit integer, for
+// abs(v) * 2^S < 2^64.  m = abs(v) * 2^(S-32) (exact) is split into its
+// integer part and fraction in FP32 (m - floor(m) is exact for m >= 0); the
+// integer part is the upper word, the fraction times 2^32 (exact) rounded is
+// the lower: far cheaper than a conversion through FP64.
+__device__ __forceinline__ unsigned long long to_fix(float v, int S) {
+    const float m = ldexpf(fabsf(v), S - 32);
+    const float fm = floorf(m);
+    const unsigned long long q =
+        ((unsigned long long)(unsigned)fm << 32) | (unsigned long long)(unsigned)rintf((m - fm) * 4294967296.0f);
+    return v < 0.0f ? (unsigned long long)(-(long long)q) : q;
 }
 
-__global__ __launch_bounds__(kP1Threads, 5) void bwd_bins_kernel(BwdArgs a) {
+// Rescue condition from the recorded largest face sum (float bits, >= 0).
+__device__ __forceinline__ bool needs_rescue(int tbits_max, int S) {
+    return tbits_max > 0 && __int_as_float(tbits_max) < ldexpf(1.0f, kRescueBits - S);
+}
+
+// rescue = 0: the pass, recording its largest face sum; rescue = 1: the
+// rescue pass, which exits unless that sum calls for it.
+__global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a, int rescue) {
     __shared__ BinRec srec[kP1Chunk];
     __shared__ unsigned long long acci[kP1Chunk * 9];
     __shared__ int tkey[kP1Table];
     __shared__ int tval[kP1Table];
-    __shared__ int umax;  // largest abs upstream gradient of the first filled round (float bits)
+    int lgbs = 0;
+    while ((1 << lgbs) < a.bs) ++lgbs;
+    int S = kFixBits - 2 * lgbs;  // grid exponent of the sums
+    if (rescue) {
+        const int tb = a.hdr[kHdrTermMax];
+        if (!needs_rescue(tb, S)) return;
+        // the largest sum (< 2^eb) on 2^30 grid points
+        S = 30 - (((tb >> 23) & 0xff) - 126);
+    }
+    // terms below 2^lim_exp: a face's at most bs^2 of them stay below 2^62 on the grid
+    const float fix_limit = ldexpf(1.0f, 62 - 2 * lgbs - S);
+    __shared__ int smax;  // largest abs face sum of the workgroup (float bits)
+    if (threadIdx.x == 0) smax = 0;  // (the first chunk's barriers order this before every update)
     if (!bins_usable(a)) return;
-    const int lane = threadIdx.x & 63;
     const int64_t bin = blockIdx.x;
     const int per_img = a.nby * a.nbx;
     const int n = (int)(bin / per_img);
@@ -479,19 +505,7 @@ __global__ __launch_bounds__(kP1Threads, 5) void bwd_bins_kernel(BwdArgs a) {
     const int* list = a.lists + bin * a.M;
     const int r0 = by * a.bs, c0 = bx * a.bs;
     const int rows = min(a.bs, a.H - r0), cols = min(a.bs, a.W - c0);
-    // a row of the bin is rowL contiguous slots: slot e of the bin is slot
-    // q = e mod rowL of bin row e / rowL, pixel column q / K of that row
-    const uint32_t rowL = (uint32_t)cols * (uint32_t)a.K;
-    const uint32_t nslots = (uint32_t)rows * rowL;
-    const uint32_t mrow = magic_for(rowL), mK = magic_for((uint32_t)a.K);
-    const int64_t img_row0 = ((int64_t)n * a.H + r0) * a.W;  // the bin's first row, as a pixel index
-    // a face has at most bs^2 slots in a bin: terms scaled below 2^tbits keep its sum below 2^60
-    int lgbs = 0;
-    while ((1 << lgbs) < a.bs) ++lgbs;
-    const int tbits = 60 - 2 * lgbs;
-    const float tlimit = ldexpf(1.0f, tbits);
-    int scale = kNoScale;  // uniform: every thread derives it from the same LDS word
-    if (threadIdx.x == 0) umax = 0;
+    const int nslots = rows * cols * a.K;
     for (int base = 0; base < cnt; base += kP1Chunk) {
         const int m = min(kP1Chunk, cnt - base);
         for (int i = threadIdx.x; i < kP1Table; i += kP1Threads) tkey[i] = -1;
@@ -510,43 +524,22 @@ __global__ __launch_bounds__(kP1Threads, 5) void bwd_bins_kernel(BwdArgs a) {
             }
         }
         __syncthreads();
-        for (uint32_t q0 = 0; q0 < nslots; q0 += kP1Unroll * kP1Threads) {
+        for (int q0 = 0; q0 < nslots; q0 += kP1Unroll * kP1Threads) {
             int fq[kP1Unroll];
             int64_t sq[kP1Unroll];
-            uint32_t rq[kP1Unroll], cq[kP1Unroll];
+            int rq[kP1Unroll], cq[kP1Unroll];
 #pragma unroll
             for (int u = 0; u < kP1Unroll; ++u) {
-                const uint32_t e = q0 + (uint32_t)(u * kP1Threads) + threadIdx.x;
+                const int q = q0 + u * kP1Threads + threadIdx.x;
                 fq[u] = -1;
-                if (e < nslots) {
-                    rq[u] = udiv_magic(e, rowL, mrow);
-                    const uint32_t q = e - rq[u] * rowL;
-                    cq[u] = udiv_magic(q, (uint32_t)a.K, mK);
-                    sq[u] = (img_row0 + (int64_t)rq[u] * a.W + c0) * a.K + q;
+                if (q < nslots) {
+                    const int pl = q / a.K, k = q - pl * a.K;
+                    const int pr = pl / cols;
+                    rq[u] = r0 + pr;
+                    cq[u] = c0 + (pl - pr * cols);
+                    sq[u] = (((int64_t)n * a.H + rq[u]) * a.W + cq[u]) * a.K + k;
                     fq[u] = a.p2f[sq[u]];
                 }
-            }
-            if (scale == kNoScale) {
-                // the largest upstream gradient of this round's filled slots
-                // (read again, from the cache, by the slots' own terms below)
-                float um = 0.0f;
-#pragma unroll
-                for (int u = 0; u < kP1Unroll; ++u) {
-                    if (fq[u] < 0) continue;
-                    const SlotUp up = load_up(a, sq[u]);
-                    um = fmaxf(um, fmaxf(fmaxf(fabsf(up.gz), fabsf(up.gd)),
-                                         fmaxf(fabsf(up.gb0), fmaxf(fabsf(up.gb1), fabsf(up.gb2)))));
-                }
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) um = fmaxf(um, __shfl_xor(um, o));
-                // non-negative floats order as their bit patterns
-                if (lane == 0 && um > 0.0f) atomicMax(&umax, __float_as_int(um));
-                __syncthreads();
-                const int ub = umax;
-                __syncthreads();  // every thread has read umax before any next-round update
-                // upstream gradients < 2^eb; terms < 2^(eb + kGeomBits) scale below 2^tbits.
-                // While unset, every term of the bin so far is zero.
-                if (ub > 0) scale = tbits - kGeomBits - (((ub >> 23) & 0xff) - 126);
             }
 #pragma unroll
             for (int u = 0; u < kP1Unroll; ++u) {
@@ -569,25 +562,18 @@ __global__ __launch_bounds__(kP1Threads, 5) void bwd_bins_kernel(BwdArgs a) {
                 FaceGrad g;
 #pragma unroll
                 for (int jj = 0; jj < 3; ++jj) g.gx[jj] = g.gy[jj] = g.gzv[jj] = 0.0f;
-                slot_grad(a, R, vz, make_pix(r0 + (int)rq[u], c0 + (int)cq[u], a.H, a.W), sq[u], g);
-                const float t9[9] = {g.gx[0], g.gy[0], g.gzv[0], g.gx[1], g.gy[1], g.gzv[1], g.gx[2], g.gy[2],
+                slot_grad(a, R, vz, make_pix(rq[u], cq[u], a.H, a.W), sq[u], g);
+                const float g9[9] = {g.gx[0], g.gy[0], g.gzv[0], g.gx[1], g.gy[1], g.gzv[1], g.gx[2], g.gy[2],
                                      g.gzv[2]};
-                bool spill = false;
 #pragma unroll
                 for (int x = 0; x < 9; ++x) {
-                    const float sv = ldexpf(t9[x], scale);
-                    const bool fits = fabsf(sv) < tlimit;
-                    spill = spill || !fits;
-                    atomicAdd(&acci[9 * j + x], fits ? (unsigned long long)__float2ll_rn(sv) : 0ull);
-                }
-                if (spill) {
-                    // terms the scale cannot hold go straight to the vertices
-                    const int32_t* fv = a.faces + 3 * (int64_t)f;
-#pragma unroll
-                    for (int x = 0; x < 9; ++x) {
-                        if (fabsf(ldexpf(t9[x], scale)) < tlimit) continue;
-                        const int vtx = fv[x / 3];
-                        if (vtx >= 0 && vtx < a.V) atomicAdd(a.grad + 3 * (int64_t)vtx + x % 3, t9[x]);
+                    const float v = g9[x];
+                    if (fabsf(v) < fix_limit) {
+                        atomicAdd(&acci[9 * j + x], to_fix(v, S));
+                    } else {
+                        // too large for the fixed-point sums (never for sane inputs): straight to the vertex
+                        const int vtx = a.faces[3 * (int64_t)list[base + j] + x / 3];
+                        if (vtx >= 0 && vtx < a.V) atomicAdd(a.grad + 3 * (int64_t)vtx + x % 3, v);
                     }
                 }
             }
@@ -600,14 +586,19 @@ __global__ __launch_bounds__(kP1Threads, 5) void bwd_bins_kernel(BwdArgs a) {
             const int f = list[base + j];
             int bx0, bx1, by0, by1;
             if (!face_bins(a.recs[f], a.H, a.W, a.bs, bx0, bx1, by0, by1)) continue;
-            if (bx < bx0 || bx > bx1 || by < by0 || by > by1) continue;  // only a stale list could do this
             const int nb = (bx1 - bx0 + 1) * (by1 - by0 + 1);
             float g9[9];
+            float fmx = 0.0f;
 #pragma unroll
-            for (int x = 0; x < 9; ++x)
-                g9[x] = scale == kNoScale ? 0.0f : (float)ldexp((double)(long long)acci[9 * j + x], -scale);
+            for (int x = 0; x < 9; ++x) {
+                g9[x] = (float)ldexp((double)(long long)acci[9 * j + x], -S);
+                fmx = fmaxf(fmx, fabsf(g9[x]));
+            }
+            // non-negative floats order as their bit patterns
+            if (!rescue && fmx > 0.0f) atomicMax(&smax, __float_as_int(fmx));
             if (nb <= kMaxPartials) {
                 const int i = (by - by0) * (bx1 - bx0 + 1) + (bx - bx0);  // this bin within the face's range
+                if (bx < bx0 || bx > bx1 || by < by0 || by > by1) continue;  // only a stale list could do this
                 float* dst = a.partial + ((int64_t)f * kMaxPartials + i) * 9;
 #pragma unroll
                 for (int x = 0; x < 9; ++x) dst[x] = g9[x];
@@ -617,7 +608,26 @@ __global__ __launch_bounds__(kP1Threads, 5) void bwd_bins_kernel(BwdArgs a) {
         }
         __syncthreads();
     }
+    if (!rescue && threadIdx.x == 0) {
+        // the call's largest face sum: one global word, so a workgroup only
+        // updates it when its own maximum is larger than what it reads there
+        // (same-address atomics from every wave would serialise)
+        const int mine = smax;
+        if (mine > 0 && mine > __hip_atomic_load(&a.hdr[kHdrTermMax], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&a.hdr[kHdrTermMax], mine);
+    }
 }
+
+// Clears grad_verts before the rescue pass, when the recorded largest sum calls for it.
+__global__ void bwd_rescue_clear_kernel(BwdArgs a) {
+    int lgbs = 0;
+    while ((1 << lgbs) < a.bs) ++lgbs;
+    if (!needs_rescue(a.hdr[kHdrTermMax], kFixBits - 2 * lgbs)) return;
+    const int64_t n = a.V * 3;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a.grad[i] = 0.0f;
+}
+
 
 __global__ __launch_bounds__(kBwdBlock) void bwd_face_sum_kernel(BwdArgs a) {
     __shared__ int keys[kHash];
@@ -716,8 +726,12 @@ hipError_t launch_backward(const float* verts, int64_t V, const int32_t* faces, 
             if (e != hipSuccess) return e;
         }
         const int64_t nbins = (int64_t)N * a.nby * a.nbx;
+        e = launch_fill_i32(hdr + kHdrTermMax, 1, 0, s);
+        if (e != hipSuccess) return e;
         if (eb) (void)hipEventRecord(eb, s);
-        hipLaunchKernelGGL(bwd_bins_kernel, dim3((unsigned)nbins), dim3(kP1Threads), 0, s, a);
+        hipLaunchKernelGGL(bwd_bins_kernel, dim3((unsigned)nbins), dim3(kP1Threads), 0, s, a, 0);
+        hipLaunchKernelGGL(bwd_rescue_clear_kernel, dim3(256), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(bwd_bins_kernel, dim3((unsigned)nbins), dim3(kP1Threads), 0, s, a, 1);
         hipLaunchKernelGGL(bwd_face_sum_kernel, dim3((unsigned)((F + kBwdBlock - 1) / kBwdBlock)), dim3(kBwdBlock), 0,
                            s, a);
         if (ee) (void)hipEventRecord(ee, s);
