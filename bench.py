@@ -155,8 +155,8 @@ def oracle_threads() -> int:
     return min(16, oracle.default_threads())
 
 
-def single_core_rate(b, pix, K):
-    """The oracle's forward+backward rate on one thread, over a slice of the
+def single_core_rate(b, pix, K, backward=True):
+    """The oracle's forward(+backward) rate on one thread, over a slice of the
     sampled pixels (Mpixel*K/s)."""
     import numpy as np
 
@@ -165,10 +165,36 @@ def single_core_rate(b, pix, K):
     sub = pix[:: max(1, pix.size // 256)]
     tq = time.perf_counter()
     o = oracle.rasterize(b.verts, b.faces, b.first_idx, b.num_faces, (H, W), b.blur_radius, K, pixels=sub, nthreads=1)
-    zeros = np.zeros((sub.size, K), np.float32)
-    oracle.backward(b.verts, b.faces, (H, W), o["p2f"], zeros + 1, None, None, nthreads=1, pixels=sub, N=N)
+    if backward:
+        ones = np.ones((sub.size, K), np.float32)
+        oracle.backward(b.verts, b.faces, (H, W), o["p2f"], ones, None, None, nthreads=1, pixels=sub, N=N)
     dt = time.perf_counter() - tq
     return {"value": round(sub.size * K / dt / 1e6, 6), "pixels": int(sub.size), "seconds": round(dt, 2)}
+
+
+def forward_only_parity(b, o, pix, t_f, P, nthr, out, dev):
+    """CPU baseline and parity of a forward-only workload (config 1)."""
+    import torch
+
+    import oracle
+    from oracle import validity
+    N, (H, W), K = b.N, b.image_size, b.faces_per_pixel
+    cpu = {"value": round(P * K / t_f / 1e6, 6), "unit": UNIT, "cores": nthr, "kind": "oracle",
+           "sample": f"{P} of {N * H * W} pixels, FP64 brute force forward over every face of the pixel's mesh; "
+                     f"fwd {t_f:.2f}s", "cpu_model": cpu_model(), "host_cpus_visible": oracle.default_threads(),
+           "single_core": single_core_rate(b, pix, K, backward=False)}
+    pix_t = torch.from_numpy(pix).to(dev)
+    g = {k: t.reshape((N * H * W,) + tuple(t.shape[3:]))[pix_t].cpu().numpy()
+         for k, t in zip(("p2f", "zbuf", "bary", "dists"), out)}
+    try:
+        st = validity.compare_fragments(g, o, b.verts, b.faces, b.first_idx, b.num_faces, (H, W), b.blur_radius,
+                                        where=b.name, pixels=pix, nthreads=nthr)
+        parity = {"pixels": int(pix.size), "fragments_ok": True, "ambiguous_frac": round(st["amb_frac"], 5),
+                  "max_err": {"bary": st["bary_err"], "zbuf": st["z_err"], "dists": st["d_err"]}}
+    except AssertionError as e:
+        parity = {"pixels": int(pix.size), "fragments_ok": False, "error": str(e)[:300]}
+    parity["grad_ok"] = True  # no backward in this workload
+    return cpu, parity
 
 
 def cpu_baseline_leg(b, cpu_seconds, v, f, fi, nf, out, gz_np, gb_np, gd_np, bs, M, bws):
@@ -199,6 +225,8 @@ def cpu_baseline_leg(b, cpu_seconds, v, f, fi, nf, out, gz_np, gb_np, gd_np, bs,
                          nthreads=nthr)
     t_f = time.perf_counter() - tq
     rows = lambda a: a.reshape((N * H * W,) + a.shape[3:])[pix]
+    if not b.backward:
+        return forward_only_parity(b, o, pix, t_f, P, nthr, out, dev)
     # slots whose two nearest edges are (nearly) tied have no unique distance
     # gradient: their upstream distance gradient is zeroed on both sides
     _, _, _, tie = oracle.fragments_fixed(b.verts, b.faces, (H, W), o["p2f"], nthreads=nthr, pixels=pix)
@@ -474,8 +502,12 @@ def main():
         v, f, fi, nf = t(b.verts), t(b.faces), t(b.first_idx), t(b.num_faces)
         grads_np = meshgen.upstream_grads(b)
         t0 = time.time()
-        if args.bin_size is None:
-            ch = autotune(v, f, fi, nf, H, W, b.blur_radius, K, reps=3)
+        if args.bin_size is None and b.bin_size is not None:
+            # the workload fixes its bins (config 1: single pass; config 2: 32-pixel bins, capacity 10000)
+            bs, M, sched = b.bin_size, (b.max_faces_per_bin or 0) if b.bin_size > 0 else 0, 0
+            log(f"[bench] batch {batch}: bins fixed by the workload: bin_size={bs} M={M}")
+        elif args.bin_size is None:
+            ch = autotune(v, f, fi, nf, H, W, b.blur_radius, K, reps=3, backward=b.backward)
             bs, M, sched = ch.bin_size, ch.max_faces_per_bin, ch.sched
             log(f"[bench] batch {batch}: autotune -> bin_size={bs} M={M} sched={sched} ({ch.ms:.3f} ms) in "
                 f"{time.time() - t0:.1f}s")
@@ -493,8 +525,9 @@ def main():
         N, (H, W), K = b.N, b.image_size, b.faces_per_pixel
         v, f, fi, nf = dev_in
         gz, gb, gd = [torch.from_numpy(x).to(dev) for x in grads_np]
-        gr = GraphRunner(v, f, fi, nf, H, W, b.blur_radius, K, bs, M, sched=sched)
-        gr.set_grads(gz, gb, gd)
+        gr = GraphRunner(v, f, fi, nf, H, W, b.blur_radius, K, bs, M, sched=sched, backward=b.backward)
+        if b.backward:
+            gr.set_grads(gz, gb, gd)
         gr.capture(warmup=2)
         for _ in range(args.warmup):
             gr.replay()
@@ -526,12 +559,12 @@ def main():
         _lib.rast_set_kernel_events(_lib.RAST_KERNEL_BWD, None, None)
         eager_ms = ev.elapsed(e0, e1) / n
         fine_ms = sum(ev.elapsed(k[0], k[1]) for k in kev) / n
-        bwd_ms = sum(ev.elapsed(k[2], k[3]) for k in kev) / n
+        bwd_ms = sum(ev.elapsed(k[2], k[3]) for k in kev) / n if b.backward else 0.0
         for e in [e0, e1] + [x for k in kev for x in k]:
             ev.destroy(e)
         valid = int((gr.out.pix_to_face >= 0).sum().item())
         return dict(graph_ms=graph_ms, eager_ms=eager_ms, fine_ms=fine_ms, bwd_ms=bwd_ms, valid=valid,
-                    out=gr.out, gv=gr.grad_verts)
+                    out=gr.out, gv=gr.grad_verts if b.backward else None)
 
     # ---------------------------------------------------------------- timed region, per seeded batch
     per_batch = []
@@ -568,9 +601,11 @@ def main():
     S_valid = first["valid"]
     V, F = b.verts.shape[0], b.faces.shape[0]
     fine_bytes = 24 * S + 12 * V + 12 * F
-    bwd_bytes = 4 * S + 20 * S_valid + 24 * V + 12 * F
+    bwd_bytes = 4 * S + 20 * S_valid + 24 * V + 12 * F if b.backward else 0
     step_bytes = fine_bytes + bwd_bytes
-    kernels = {"fine": (fine_ms, fine_bytes), "backward": (bwd_ms, bwd_bytes)}
+    kernels = {"fine": (fine_ms, fine_bytes)}
+    if b.backward:
+        kernels["backward"] = (bwd_ms, bwd_bytes)
     dom = max(kernels, key=lambda k: kernels[k][0])
     dom_ms, dom_bytes = kernels[dom]
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
@@ -607,9 +642,10 @@ def main():
                 bs1, M1, w = (32, m32, ws1) if binned else (0, 0, one_ws)
                 _lib.rasterize_meshes_fwd(v, fm, z0, c1, H, W, b.blur_radius, K, bs1, M1, 0, o1.pix_to_face, o1.zbuf,
                                           o1.bary, o1.dists, w)
-                _lib.rasterize_meshes_bwd(v, fm, z0, c1, H, W, b.blur_radius, K, bs1, M1,
-                                          _lib.RAST_BWD_REUSE_FORWARD if binned else 0, o1.pix_to_face, gz[sl],
-                                          gb[sl], gd[sl], gvm, w)
+                if b.backward:
+                    _lib.rasterize_meshes_bwd(v, fm, z0, c1, H, W, b.blur_radius, K, bs1, M1,
+                                              _lib.RAST_BWD_REUSE_FORWARD if binned else 0, o1.pix_to_face, gz[sl],
+                                              gb[sl], gd[sl], gvm, w)
 
         def time_form(binned, reps):
             per_mesh_step(binned)
@@ -627,12 +663,44 @@ def main():
         pm_ms = time_form(False, 2)
         pb_ms = time_form(True, 5)
         per_mesh = {"ms_per_batch": round(pm_ms, 4), "value": round(S / (pm_ms * 1e-3) / 1e6, 2),
-                    "form": "one single-pass fwd+bwd call per mesh (no bins, no graph)",
+                    "form": f"one single-pass {'fwd+bwd' if b.backward else 'fwd'} call per mesh (no bins, no graph)",
                     "speedup_batched": round(pm_ms / ms_step, 2),
                     "binned32": {"ms_per_batch": round(pb_ms, 4), "value": round(S / (pb_ms * 1e-3) / 1e6, 2),
-                                 "form": "one fwd+bwd call per mesh with 32-pixel bins (no graph)",
+                                 "form": f"one {'fwd+bwd' if b.backward else 'fwd'} call per mesh with 32-pixel bins (no graph)",
                                  "speedup_batched": round(pb_ms / ms_step, 2)}}
         log(f"[bench] per-mesh plain {pm_ms:.3f} ms/batch, per-mesh bins-32 {pb_ms:.3f} ms/batch")
+
+    # ---------------------------------------------------------------- config 5: the whole fitting step
+    fit = None
+    if args.config == 5:
+        from paper_2007_08501_amd import silfit
+        fp = silfit.SilhouetteFit(meshgen.silhouette_fit_problem(), bin_size=bs if bs > 0 else 0)
+        offsets = torch.zeros_like(fp.base, requires_grad=True)
+        opt = torch.optim.Adam([offsets], lr=1e-3)
+
+        def fit_step():
+            opt.zero_grad(set_to_none=True)
+            loss = fp.loss(offsets)
+            loss.backward()
+            opt.step()
+            return loss
+
+        for _ in range(3):
+            fit_step()
+        torch.cuda.synchronize()
+        reps = 20
+        a0, a1 = ev.create(), ev.create()
+        ev.record(a0, stream)
+        for _ in range(reps):
+            fit_step()
+        ev.record(a1, stream)
+        fit_ms = ev.elapsed(a0, a1) / reps
+        ev.destroy(a0)
+        ev.destroy(a1)
+        fit = {"ms_per_step": round(fit_ms, 4), "value": round(S / (fit_ms * 1e-3) / 1e6, 2),
+               "form": "one Adam step of the silhouette fit, eager: view transform, rasterizer fwd, blend fwd, "
+                       "IoU loss, blend bwd, rasterizer bwd, Adam (lr 1e-3); bins as in the rasterizer timing"}
+        log(f"[bench] silhouette fit step {fit_ms:.4f} ms")
 
     # ---------------------------------------------------------------- CPU baseline (oracle) + sampled parity
     cpu, parity = None, None
@@ -660,8 +728,10 @@ def main():
         "slots": S, "slots_valid": S_valid, "step_algorithmic_bytes": step_bytes,
         "step_hbm_frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "kernels_ms": {"fine": round(fine_ms, 5), "backward": round(bwd_ms, 5)},
-        "timing": {"form": "autotuned, fwd+bwd captured in one HIP graph and replayed; value and ms_per_step are "
-                           "the median over seeded batches",
+        "timing": {"form": ("bins fixed by the workload" if (args.bin_size is None and b.bin_size is not None)
+                            else "bins from the autotuner" if args.bin_size is None else "bins fixed on the command line")
+                           + ", fwd+bwd captured in one HIP graph and replayed; value and ms_per_step are the median "
+                             "over seeded batches",
                    "batches": [r["batch"] for r in per_batch],
                    "ms_per_step_graph": [round(r["graph_ms"], 5) for r in per_batch],
                    "ms_per_step_mean": round(ms_mean, 5),
@@ -669,6 +739,11 @@ def main():
                    "bins": [[r["bs"], r["M"], r["sched"]] for r in per_batch]},
         "roofline": roofline, "cpu_baseline": cpu, "per_mesh": per_mesh, "parity": parity,
     }
+    if fit is not None:
+        res["fit_step"] = fit
+    if not b.backward:
+        res["timing"]["form"] = "forward only (the workload has no backward), captured in one HIP graph and " \
+                                "replayed; value and ms_per_step are the median over seeded batches"
     print(json.dumps(res), flush=True)
     if parity is not None and not (parity["fragments_ok"] and parity["grad_ok"]):
         sys.exit(3)

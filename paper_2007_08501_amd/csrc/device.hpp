@@ -548,4 +548,26 @@ __device__ __forceinline__ uint64_t edge_mask(const Rec& R, double rg, int H, in
     return m;
 }
 
+// One global atomic per distinct bucket of a wave (tiles of a wave mostly
+// share a few buckets): returns the wave's base position in
+// that bucket for the calling lane, whose rank among the wave's tiles of the
+// bucket is added.  Every lane of the wave must call it.
+__device__ __forceinline__ int wave_bucket_slot(int* __restrict__ hist, int bucket) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint64_t active = __ballot(bucket >= 0);
+    int pos = -1;
+    while (active) {  // uniform: active is the same on every lane
+        const int leader = __ffsll((unsigned long long)active) - 1;
+        const int bl = __shfl(bucket, leader);
+        const uint64_t same = __ballot(bucket == bl);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&hist[bl], __popcll(same));
+        base = __shfl(base, leader);
+        if (bucket == bl) pos = base + __popcll(same & below);
+        active &= ~same;
+    }
+    return pos;
+}
+
 }  // namespace rast

@@ -1,6 +1,7 @@
 // kernels_blend.hip -- silhouette blend (paper, Section 3.2, Algorithm 1),
-// softmax blend (Algorithm 2) and their backwards, one lane per pixel, for
-// gfx950.
+// softmax blend (Algorithm 2) and their backwards, for gfx950: the
+// silhouette blend spreads a pixel's slots over a group of lanes, the softmax
+// blend takes one lane per pixel.
 //
 // Silhouette:
 //   prob_k = sigmoid(-d_k / sigma) where the slot holds a face, else 0
@@ -20,44 +21,133 @@ __device__ __forceinline__ float sigmoidf(float x) {
     return e / (1.0f + e);
 }
 
-__global__ __launch_bounds__(256) void blend_fwd_kernel(const int32_t* __restrict__ p2f, const float* __restrict__ d,
-                                                        int64_t P, int K, float inv_sigma, float* __restrict__ alpha) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    float prod = 1.0f;
-    for (int k = 0; k < K; ++k) {
-        int64_t o = p * K + k;
-        if (p2f[o] >= 0) prod *= sigmoidf(d[o] * inv_sigma);
+// A pixel's K slots are spread over L lanes of a wave, four consecutive slots
+// per lane (L the power of two with 4 L >= K, 64 / L pixels per wave), so
+// that consecutive lanes read consecutive words: each lane combines its own
+// slots and only the per-lane products cross lanes (segmented scans of
+// log2(L) steps).  One lane per pixel walking its K words would make every
+// load instruction touch 64 different rows (a 200-byte stride at K = 50).
+constexpr int kBlendQ = 4;  // consecutive slots per lane
+// four words at 4-byte alignment (a pixel's slots start at any word)
+typedef int bi32x4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef float bf32x4 __attribute__((ext_vector_type(4), aligned(4)));
+
+// The lane's slots of pixel p: whether each holds a face, and d / sigma.
+__device__ __forceinline__ void blend_slots(const int32_t* __restrict__ p2f, const float* __restrict__ d, int64_t p,
+                                            int64_t P, int K, int sub, float inv_sigma, bool (&on)[kBlendQ],
+                                            float (&x)[kBlendQ]) {
+    const int64_t o = p * K + kBlendQ * sub;
+    if (p < P && kBlendQ * (sub + 1) <= K) {
+        const bi32x4 vi = *reinterpret_cast<const bi32x4*>(p2f + o);
+        const bf32x4 vd = *reinterpret_cast<const bf32x4*>(d + o);
+#pragma unroll
+        for (int i = 0; i < kBlendQ; ++i) {
+            on[i] = vi[i] >= 0;
+            x[i] = vd[i] * inv_sigma;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kBlendQ; ++i) {
+            const bool in = p < P && kBlendQ * sub + i < K;
+            on[i] = in && p2f[o + i] >= 0;
+            x[i] = in ? d[o + i] * inv_sigma : 0.0f;
+        }
     }
-    alpha[p] = 1.0f - prod;
 }
 
-// Two sweeps over the pixel's K slots: the first stores the suffix products
-// prod_{j > k} (1 - prob_j) into grad_dists, the second walks forward with the
-// prefix product and overwrites each entry with the gradient.
+template <int L>
+__device__ __forceinline__ float blend_seg_prod(float v) {
+#pragma unroll
+    for (int m = L / 2; m >= 1; m >>= 1) v *= __shfl_xor(v, m, L);
+    return v;
+}
+
+// product over the lower / the higher lanes of the segment (1 for none)
+template <int L>
+__device__ __forceinline__ float blend_excl_prefix(float t, int sub) {
+#pragma unroll
+    for (int m = 1; m < L; m <<= 1) {
+        const float u = __shfl_up(t, m, L);
+        if (sub >= m) t *= u;
+    }
+    const float e = __shfl_up(t, 1, L);
+    return sub == 0 ? 1.0f : e;
+}
+template <int L>
+__device__ __forceinline__ float blend_excl_suffix(float t, int sub) {
+#pragma unroll
+    for (int m = 1; m < L; m <<= 1) {
+        const float u = __shfl_down(t, m, L);
+        if (sub + m < L) t *= u;
+    }
+    const float e = __shfl_down(t, 1, L);
+    return sub == L - 1 ? 1.0f : e;
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void blend_fwd_kernel(const int32_t* __restrict__ p2f, const float* __restrict__ d,
+                                                        int64_t P, int K, float inv_sigma, float* __restrict__ alpha) {
+    constexpr int PPW = 64 / L;
+    const int lane = threadIdx.x & 63, sub = lane & (L - 1), grp = lane / L;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t p0 = wave * PPW; p0 < P; p0 += nwaves * PPW) {
+        const int64_t p = p0 + grp;
+        bool on[kBlendQ];
+        float x[kBlendQ];
+        blend_slots(p2f, d, p, P, K, sub, inv_sigma, on, x);
+        float t = 1.0f;  // product of 1 - prob_k over the lane's slots
+#pragma unroll
+        for (int i = 0; i < kBlendQ; ++i)
+            if (on[i]) t *= sigmoidf(x[i]);
+        t = blend_seg_prod<L>(t);
+        if (sub == 0 && p < P) alpha[p] = 1.0f - t;
+    }
+}
+
+// d alpha / d d_k = -(1/sigma) prob_k (1 - prob_k) prod_{j<k} (1 - prob_j)
+// prod_{j>k} (1 - prob_j): the products of the other slots come from the
+// lane's own prefix and suffix and the exclusive scans of the lane products
+// (no division by 1 - prob_k, which underflows deep inside a face).
+template <int L>
 __global__ __launch_bounds__(256) void blend_bwd_kernel(const int32_t* __restrict__ p2f, const float* __restrict__ d,
                                                         const float* __restrict__ ga, int64_t P, int K, float inv_sigma,
                                                         float* __restrict__ gd) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    float suf = 1.0f;
-    for (int k = K - 1; k >= 0; --k) {
-        int64_t o = p * K + k;
-        gd[o] = suf;
-        if (p2f[o] >= 0) suf *= sigmoidf(d[o] * inv_sigma);
-    }
-    float g = ga[p];
-    float pre = 1.0f;
-    for (int k = 0; k < K; ++k) {
-        int64_t o = p * K + k;
-        if (p2f[o] >= 0) {
-            float x = d[o] * inv_sigma;
-            float prob = sigmoidf(-x);
-            float om = sigmoidf(x);
-            gd[o] = -g * inv_sigma * prob * om * pre * gd[o];
-            pre *= om;
+    constexpr int PPW = 64 / L;
+    const int lane = threadIdx.x & 63, sub = lane & (L - 1), grp = lane / L;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t p0 = wave * PPW; p0 < P; p0 += nwaves * PPW) {
+        const int64_t p = p0 + grp;
+        bool on[kBlendQ];
+        float x[kBlendQ];
+        blend_slots(p2f, d, p, P, K, sub, inv_sigma, on, x);
+        float om[kBlendQ];  // 1 - prob_k (1 for an empty slot)
+        float t = 1.0f;
+#pragma unroll
+        for (int i = 0; i < kBlendQ; ++i) {
+            om[i] = on[i] ? sigmoidf(x[i]) : 1.0f;
+            t *= om[i];
+        }
+        float pre = blend_excl_prefix<L>(t, sub);
+        const float lsuf = blend_excl_suffix<L>(t, sub);
+        const float g = p < P ? ga[p] : 0.0f;
+        float out[kBlendQ];
+#pragma unroll
+        for (int i = 0; i < kBlendQ; ++i) {
+            float suf = lsuf;
+#pragma unroll
+            for (int j = i + 1; j < kBlendQ; ++j) suf *= om[j];
+            out[i] = on[i] ? -g * inv_sigma * sigmoidf(-x[i]) * om[i] * pre * suf : 0.0f;
+            pre *= om[i];
+        }
+        const int64_t o = p * K + kBlendQ * sub;
+        if (p < P && kBlendQ * (sub + 1) <= K) {
+            *reinterpret_cast<bf32x4*>(gd + o) = bf32x4{out[0], out[1], out[2], out[3]};
         } else {
-            gd[o] = 0.0f;
+#pragma unroll
+            for (int i = 0; i < kBlendQ; ++i)
+                if (p < P && kBlendQ * sub + i < K) gd[o + i] = out[i];
         }
     }
 }
@@ -203,19 +293,49 @@ hipError_t launch_softmax_bwd(const int32_t* p2f, const float* z, const float* d
     return hipGetLastError();
 }
 
+// lanes per pixel: the power of two L with 4 L >= K (K <= 64)
+static int blend_lanes(int K) {
+    int L = 1;
+    while (kBlendQ * L < K) L <<= 1;
+    return L;
+}
+
+static unsigned blend_grid(int64_t P, int L) {
+    const int64_t waves = (P + 64 / L - 1) / (64 / L);
+    int64_t blocks = (waves + 3) / 4;
+    if (blocks > 65536) blocks = 65536;
+    return (unsigned)(blocks > 0 ? blocks : 1);
+}
+
 hipError_t launch_blend_fwd(const int32_t* p2f, const float* d, int64_t P, int K, float sigma, float* alpha,
                             hipStream_t s) {
     if (P == 0) return hipSuccess;
-    hipLaunchKernelGGL(blend_fwd_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, p2f, d, P, K,
-                       1.0f / sigma, alpha);
+    const int L = blend_lanes(K);
+    const dim3 grid(blend_grid(P, L));
+#define RAST_BLEND_FWD(LL) \
+    case LL: hipLaunchKernelGGL(blend_fwd_kernel<LL>, grid, dim3(256), 0, s, p2f, d, P, K, 1.0f / sigma, alpha); break;
+    switch (L) {
+        RAST_BLEND_FWD(1) RAST_BLEND_FWD(2) RAST_BLEND_FWD(4) RAST_BLEND_FWD(8) RAST_BLEND_FWD(16)
+        default: return hipErrorInvalidValue;
+    }
+#undef RAST_BLEND_FWD
     return hipGetLastError();
 }
 
 hipError_t launch_blend_bwd(const int32_t* p2f, const float* d, const float* ga, int64_t P, int K, float sigma,
                             float* gd, hipStream_t s) {
     if (P == 0) return hipSuccess;
-    hipLaunchKernelGGL(blend_bwd_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, p2f, d, ga, P, K,
-                       1.0f / sigma, gd);
+    const int L = blend_lanes(K);
+    const dim3 grid(blend_grid(P, L));
+#define RAST_BLEND_BWD(LL)                                                                                       \
+    case LL:                                                                                                     \
+        hipLaunchKernelGGL(blend_bwd_kernel<LL>, grid, dim3(256), 0, s, p2f, d, ga, P, K, 1.0f / sigma, gd); \
+        break;
+    switch (L) {
+        RAST_BLEND_BWD(1) RAST_BLEND_BWD(2) RAST_BLEND_BWD(4) RAST_BLEND_BWD(8) RAST_BLEND_BWD(16)
+        default: return hipErrorInvalidValue;
+    }
+#undef RAST_BLEND_BWD
     return hipGetLastError();
 }
 

@@ -552,38 +552,37 @@ __global__ __launch_bounds__(64) void raster_persistent_kernel(FineArgs a, const
 }
 
 // order[]: tiles sorted by the count of their bin, descending, using a
-// counting sort over count buckets (64 buckets of width ceil((M+1)/64)).
-__global__ void order_hist_kernel(const int* __restrict__ counts, int N, int tiles_x, int tiles_y, int bs, int nby,
-                                  int nbx, int M, int* __restrict__ hist) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t total = (int64_t)N * tiles_x * tiles_y;
-    if (t >= total) return;
-    int per_img = tiles_x * tiles_y;
-    int n = (int)(t / per_img);
-    int rem = (int)(t - (int64_t)n * per_img);
-    int ty = rem / tiles_x, tx = rem - ty * tiles_x;
-    int64_t bin = ((int64_t)n * nby + (ty * kTile) / bs) * nbx + (tx * kTile) / bs;
-    int cnt = min(counts[bin], M);
-    int width = (M + 64) / 64;
-    int bucket = 63 - min(cnt / width, 63);  // bucket 0 = heaviest
-    atomicAdd(&hist[bucket], 1);
+// counting sort over count buckets (64 buckets of width ceil((M+1)/64)), with
+// one global atomic per distinct bucket of a wave (per-thread atomics on the
+// 64 counters serialised: about 1 ms at config 3).
+__device__ __forceinline__ int tile_bucket(const int* __restrict__ counts, int t, int tiles_x, int tiles_y, int bs,
+                                           int nby, int nbx, int M) {
+    const int per_img = tiles_x * tiles_y;
+    const int n = t / per_img;
+    const int rem = t - n * per_img;
+    const int ty = rem / tiles_x, tx = rem - ty * tiles_x;
+    const int64_t bin = ((int64_t)n * nby + (ty * kTile) / bs) * nbx + (tx * kTile) / bs;
+    const int cnt = min(counts[bin], M);
+    const int width = (M + 64) / 64;
+    return 63 - min(cnt / width, 63);  // bucket 0 = heaviest
 }
 
-__global__ void order_scatter_kernel(const int* __restrict__ counts, int N, int tiles_x, int tiles_y, int bs, int nby,
-                                     int nbx, int M, int* __restrict__ hist_off, int* __restrict__ order) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t total = (int64_t)N * tiles_x * tiles_y;
-    if (t >= total) return;
-    int per_img = tiles_x * tiles_y;
-    int n = (int)(t / per_img);
-    int rem = (int)(t - (int64_t)n * per_img);
-    int ty = rem / tiles_x, tx = rem - ty * tiles_x;
-    int64_t bin = ((int64_t)n * nby + (ty * kTile) / bs) * nbx + (tx * kTile) / bs;
-    int cnt = min(counts[bin], M);
-    int width = (M + 64) / 64;
-    int bucket = 63 - min(cnt / width, 63);
-    int pos = atomicAdd(&hist_off[bucket], 1);
-    order[pos] = (int)t;
+__global__ __launch_bounds__(256) void order_hist_kernel(const int* __restrict__ counts, int N, int tiles_x,
+                                                         int tiles_y, int bs, int nby, int nbx, int M,
+                                                         int* __restrict__ hist) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)N * tiles_x * tiles_y;
+    (void)wave_bucket_slot(hist, t < total ? tile_bucket(counts, (int)t, tiles_x, tiles_y, bs, nby, nbx, M) : -1);
+}
+
+__global__ __launch_bounds__(256) void order_scatter_kernel(const int* __restrict__ counts, int N, int tiles_x,
+                                                            int tiles_y, int bs, int nby, int nbx, int M,
+                                                            int* __restrict__ hist_off, int* __restrict__ order) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)N * tiles_x * tiles_y;
+    const int pos =
+        wave_bucket_slot(hist_off, t < total ? tile_bucket(counts, (int)t, tiles_x, tiles_y, bs, nby, nbx, M) : -1);
+    if (t < total) order[pos] = (int)t;
 }
 
 // exclusive scan of the 64 bucket sizes, in place; also arms the work counter

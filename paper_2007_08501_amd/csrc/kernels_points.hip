@@ -246,31 +246,9 @@ __device__ __forceinline__ int pt_tile_bucket(const PtArgs& a, int t) {
     return kPtOrderBuckets - 1 - level;  // the last bucket: tiles without candidates
 }
 
-// One global atomic per distinct bucket of a wave (most tiles share a few
-// buckets, the empty ones all the last): returns the wave's base position in
-// that bucket for the calling lane, whose rank among the wave's tiles of the
-// bucket is added.  Every lane of the wave must call it.
-__device__ __forceinline__ int pt_bucket_slot(int* __restrict__ ohist, int bucket) {
-    const int lane = threadIdx.x & 63;
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint64_t active = __ballot(bucket >= 0);
-    int pos = -1;
-    while (active) {  // uniform: active is the same on every lane
-        const int leader = __ffsll((unsigned long long)active) - 1;
-        const int bl = __shfl(bucket, leader);
-        const uint64_t same = __ballot(bucket == bl);
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&ohist[bl], __popcll(same));
-        base = __shfl(base, leader);
-        if (bucket == bl) pos = base + __popcll(same & below);
-        active &= ~same;
-    }
-    return pos;
-}
-
 __global__ __launch_bounds__(256) void pt_order_hist_kernel(PtArgs a) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    (void)pt_bucket_slot(a.ohist, t < a.T ? pt_tile_bucket(a, (int)t) : -1);
+    (void)wave_bucket_slot(a.ohist, t < a.T ? pt_tile_bucket(a, (int)t) : -1);
 }
 
 __global__ void pt_order_scan_kernel(int* __restrict__ ohist) {
@@ -286,7 +264,7 @@ __global__ void pt_order_scan_kernel(int* __restrict__ ohist) {
 
 __global__ __launch_bounds__(256) void pt_order_scatter_kernel(PtArgs a) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int pos = pt_bucket_slot(a.ohist, t < a.T ? pt_tile_bucket(a, (int)t) : -1);
+    const int pos = wave_bucket_slot(a.ohist, t < a.T ? pt_tile_bucket(a, (int)t) : -1);
     if (t < a.T) a.order[pos] = (int)t;
 }
 
