@@ -386,8 +386,8 @@ __global__ __launch_bounds__(kBwdBlock) void bwd_big_faces_kernel(BwdArgs a) {
 // to grad_verts directly with a float atomic, which is slow: the headroom
 // keeps those rare.  Terms are rounded to the
 // nearest grid point.  The pass records the largest face sum of the call
-// (at the flush, off the hot loop); if it lies below 2^(22 - S) -- gradients
-// so small that the grid holds them to fewer than 22 bits -- a second launch
+// (at the flush, off the hot loop); if it lies below 2^(18 - S) -- gradients
+// so small that the grid holds them to fewer than 18 bits -- a second launch
 // of the pass (the rescue) redoes the sums on a grid 2^30 times finer than
 // that largest sum, after the vertex gradients are cleared again (a term
 // that then exceeds the grid's headroom goes to grad_verts directly).
@@ -455,7 +455,7 @@ __device__ __forceinline__ void store_bin_rec(BinRec& d, const FaceRec& R) {
 // block (about 30 KB) lets five workgroups share a CU.  A bin of up to
 // kP1Chunk faces -- most of them -- is one chunk and reads its slots once.
 constexpr int kFixBits = 38;     // fixed-point grid 2^-(kFixBits - 2 log2(bin size))
-constexpr int kRescueBits = 22;  // a largest face sum below 2^22 grid points triggers the rescue
+constexpr int kRescueBits = 18;  // a largest face sum below 2^18 grid points triggers the rescue
 
 // v * 2^S, rounded to nearest, as a two's-complement 64-bit integer, for
 // abs(v) * 2^S < 2^64.  m = abs(v) * 2^(S-32) (exact) is split into its
