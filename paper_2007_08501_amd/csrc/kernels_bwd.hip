@@ -1,16 +1,19 @@
-// kernels_bwd.hip -- backward of the rasterizer for gfx950, organised by face.
+// kernels_bwd.hip -- backward of the rasterizer for gfx950.
 //
 // The forward stores only the face ids (paper, Section 3.2: the cached
-// Fragment data avoid recomputing face-pixel intersections).  Here every face
-// gathers its own gradient: the thread that owns face f scans the pixels of
-// f's blur-grown bounding box (the only pixels whose slots the forward can
-// fill with f), finds the slot holding f in each, recomputes barycentrics, z
-// and the nearest edge for that pixel, and sums the chain rule for its nine
-// vertex coordinates in registers -- no atomics per slot.  A workgroup then
-// merges its 256 faces' contributions per vertex in an LDS hash table and
-// issues one float atomic per (vertex, coordinate).  Faces whose box exceeds
-// kBigArea pixels are handed to a second kernel in which a whole workgroup
-// scans one face's box.
+// Fragment data avoid recomputing face-pixel intersections); the backward
+// recomputes barycentrics, z and the nearest edge of every filled slot and
+// sums the chain rule into the nine vertex coordinates of its face.  Two
+// forms.  The binned form (the forward's bins): one workgroup per bin, the
+// bin's faces in LDS, exact fixed-point sums per face (described with its
+// kernels below).  The per-face form (no bins): the thread that owns face f
+// scans the pixels of f's blur-grown bounding box (the only pixels whose
+// slots the forward can fill with f), finds the slot holding f in each and
+// sums in registers -- no atomics per slot; a workgroup then merges its 256
+// faces' contributions per vertex in an LDS hash table and issues one float
+// atomic per (vertex, coordinate).  Faces whose box exceeds kBigArea pixels
+// are handed to a second kernel in which a whole workgroup scans one face's
+// box.
 //
 // Derivatives (pixel p fixed, R_j = v_j - p, cross(u,v) = u.x v.y - u.y v.x):
 //   e0 = cross(R1,R2), e1 = cross(R2,R0), e2 = cross(R0,R1), E = e0+e1+e2,
@@ -20,6 +23,7 @@
 //   dists = s d2 (s = -1 inside, +1 outside); on the nearest edge (s0, t) with
 //   nearest point Q = R_s0 + u (R_t - R_s0) (relative to p):
 //   d d2/d s0 = 2 (1-u) Q,  d d2/d t = 2 u Q.
+#include "../../include/rast.h"
 #include "device.hpp"
 #include "launch.hpp"
 
@@ -50,6 +54,7 @@ struct BwdArgs {
     const int* counts;
     const int* lists;
     float* partial;    // (F, 4, 9): a face's nine coordinate sums in the i-th bin of its range
+    unsigned char* pmask;  // (F, 4): partial row written by this call (the binned form; shares big's memory)
     int bs, nby, nbx, M;
     int reuse;         // records and bins come from the forward: check its signature first
     BinSig sig;        // the signature this call expects
@@ -89,7 +94,8 @@ __device__ __forceinline__ SlotUp load_up(const BwdArgs& a, int64_t s) {
 }
 
 // Adds the contribution of a slot of face R at pixel p, with upstream gradients up, to g.
-template <class Rec>
+// kOpts = false compiles out the options' barycentrics (for calls without them).
+template <class Rec, bool kOpts = true>
 __device__ __forceinline__ void slot_grad_up(const BwdArgs& a, const Rec& R, const float (&vz)[3], const Pix& p,
                                              const SlotUp& up, FaceGrad& g) {
     Eval ev;
@@ -99,7 +105,7 @@ __device__ __forceinline__ void slot_grad_up(const BwdArgs& a, const Rec& R, con
     float G0 = gb0 + gzs * vz[0];
     float G1 = gb1 + gzs * vz[1];
     float G2 = gb2 + gzs * vz[2];
-    if (a.opts & (kOptPersp | kOptClip)) {
+    if (kOpts && (a.opts & (kOptPersp | kOptClip))) {
         // the outputs are the options' barycentrics: carry dL/dw back through
         // the clipping and the correction to the raw ones (and to the depths)
         const float w[3] = {ev.w0, ev.w1, ev.w2};
@@ -184,10 +190,10 @@ __device__ __forceinline__ void slot_grad_up(const BwdArgs& a, const Rec& R, con
     }
 }
 
-template <class Rec>
+template <class Rec, bool kOpts = true>
 __device__ __forceinline__ void slot_grad(const BwdArgs& a, const Rec& R, const float (&vz)[3], const Pix& p,
                                           int64_t s, FaceGrad& g) {
-    slot_grad_up(a, R, vz, p, load_up(a, s), g);
+    slot_grad_up<Rec, kOpts>(a, R, vz, p, load_up(a, s), g);
 }
 
 // Scans the K slots of pixel (n, r, c) for face f and accumulates every match.
@@ -372,39 +378,41 @@ __global__ __launch_bounds__(kBwdBlock) void bwd_big_faces_kernel(BwdArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Binned form.  Pass 1: one workgroup per bin streams the slots of the bin's
+// Binned form.  Pass 1: one workgroup per bin reads the slots of the bin's
 // pixels once (coalesced reads of pix_to_face and the gradients), maps each
-// slot's face to its index in the bin's face list through an LDS hash table,
-// and accumulates the nine coordinate sums per listed face in LDS as 64-bit
-// fixed-point integers: integer LDS atomics cost next to nothing on this
-// hardware and float LDS atomics a great deal (measured at config 4: 2.3 ms
-// for the pass with float LDS atomics, 0.95 ms with integer ones), and the
-// per-bin sums become exact and independent of the order of the additions.
-// The grid is 2^-S with S = 38 - 2 log2(bin size) (2^-32 at bin size 8), so
-// that a face's at most bin_size^2 terms below 2^24 cannot overflow; a term
-// of 2^24 or more (a sliver's geometric factor times a large gradient) goes
-// to grad_verts directly with a float atomic, which is slow: the headroom
-// keeps those rare.  Terms are rounded to the
-// nearest grid point.  The pass records the largest face sum of the call
-// (at the flush, off the hot loop); if it lies below 2^(18 - S) -- gradients
-// so small that the grid holds them to fewer than 18 bits -- a second launch
-// of the pass (the rescue) redoes the sums on a grid 2^30 times finer than
-// that largest sum, after the vertex gradients are cleared again (a term
-// that then exceeds the grid's headroom goes to grad_verts directly).
-// Normally the rescue launch only reads the recorded sum and exits.  Each listed face's
-// nine sums are then written to the face's own slot for this bin,
-// partial[f][i] for the i-th bin of its range (no global atomic).  Pass 2:
-// one thread per face reads its (at most four) partials, contiguous, merges
-// per vertex in LDS and issues one atomic per (vertex, coordinate).  Faces
-// spanning more than four bins take global atomics directly.
+// slot's face to a chunk index through an LDS hash table, and accumulates the
+// nine coordinate sums per face in LDS as 64-bit fixed-point integers: integer
+// LDS atomics cost next to nothing on this hardware and float LDS atomics a
+// great deal (measured at config 4: 2.3 ms for the pass with float LDS
+// atomics, 0.95 ms with integer ones), and the per-bin sums become exact and
+// independent of the order of the additions.  The grid is 2^-S with
+// S = 38 - 2 log2(bin size) (2^-32 at bin size 8); a term must lie below
+// 2^min(51 - S, 62 - 2 log2(bin size) - S) (2^19 at bin size 8), where the
+// conversion is exact and a face's at most bin_size^2 terms cannot overflow;
+// a larger term (a sliver's geometric factor times a large gradient) goes to
+// grad_verts directly with a float atomic.  Terms are rounded to the nearest
+// grid point.  The pass records the largest face sum of the call (at the
+// flush, off the hot loop); if it lies below 2^(18 - S) -- gradients so small
+// that the grid holds them to fewer than 18 bits -- a second launch of the
+// pass (the rescue) redoes the sums on a grid 2^30 times finer than that
+// largest sum, after the vertex gradients are cleared again.  Normally the
+// rescue launch only reads the recorded sum and exits.  A face's nine sums
+// from a bin go to its own row partial[f][i] for the i-th bin of its range (no
+// global atomic), and the row's byte in an (F, 4) mask is set.  Pass 2: one
+// thread per face adds the rows the mask names and merges per vertex in LDS;
+// one float atomic per (vertex, coordinate) per workgroup.  Faces spanning
+// more than four bins take global atomics directly.
 // ---------------------------------------------------------------------------
 constexpr int kP1Threads = 256;
 constexpr int kP1Chunk = 160;    // faces staged in LDS per pass over a bin's slots
+static_assert(kP1Chunk <= 256, "chunk indices are kept as bytes");
 constexpr int kP1Table = 512;    // LDS hash entries (>= 2 * kP1Chunk)
-constexpr int kP1Unroll = 4;     // slots per thread whose loads are issued together
-constexpr int kMaxPartials = 4;
+constexpr int kP1Unroll = 4;     // slots per thread in one group of the bin's slots
+constexpr int kP1Group = kP1Unroll * kP1Threads;  // slots looked up before the found ones are recomputed
+constexpr int kMaxPartials = 4;  // (the row masks are read as one uchar4)
 
 __device__ __forceinline__ uint32_t fhash(int f) { return ((uint32_t)f * 2654435761u) >> (32 - 9); }
+static_assert(kP1Table == 512, "fhash yields 9 bits");
 
 __device__ __forceinline__ void atomic_face(const BwdArgs& a, int f, const float* g9) {
     const int32_t* fv = a.faces + 3 * (int64_t)f;
@@ -426,11 +434,12 @@ struct Dbl2 {  // a pair of doubles at 8-byte alignment (double2 would pad the r
 struct BinRec {
     Dbl2 pa, ab, ac;
     double E;
-    float az, dz1, dz2, invE, il0, il1, il2, pad_;
+    float az, dz1, dz2, invE, il0, il1, il2;
+    int face;  // the face's id
 };
 static_assert(sizeof(BinRec) == 88, "bin record layout");
 
-__device__ __forceinline__ void store_bin_rec(BinRec& d, const FaceRec& R) {
+__device__ __forceinline__ void store_bin_rec(BinRec& d, const FaceRec& R, int f) {
     d.pa = {R.pa.x, R.pa.y};
     d.ab = {R.ab.x, R.ab.y};
     d.ac = {R.ac.x, R.ac.y};
@@ -442,32 +451,20 @@ __device__ __forceinline__ void store_bin_rec(BinRec& d, const FaceRec& R) {
     d.il0 = R.il0;
     d.il1 = R.il1;
     d.il2 = R.il2;
-    d.pad_ = 0.0f;
+    d.face = f;
 }
 
-// One 256-thread workgroup per bin.  The bin's face list is taken in chunks
-// of kP1Chunk faces: the chunk's records go to LDS (one coalesced gather) with
-// a hash table from face id to chunk index, then every thread streams its
-// slots of the bin (kP1Unroll at a time, loads issued together), and the slots
-// whose face is in the chunk add their nine coordinate sums into the chunk's
-// LDS accumulators, as exact 64-bit fixed point; the rare contribution too
-// large for that goes straight to grad_verts with a float atomic.  The LDS
-// block (about 30 KB) lets five workgroups share a CU.  A bin of up to
-// kP1Chunk faces -- most of them -- is one chunk and reads its slots once.
 constexpr int kFixBits = 38;     // fixed-point grid 2^-(kFixBits - 2 log2(bin size))
 constexpr int kRescueBits = 18;  // a largest face sum below 2^18 grid points triggers the rescue
 
-// v * 2^S, rounded to nearest, as a two's-complement 64-bit integer, for
-// abs(v) * 2^S < 2^64.  m = abs(v) * 2^(S-32) (exact) is split into its
-// integer part and fraction in FP32 (m - floor(m) is exact for m >= 0); the
-// integer part is the upper word, the fraction times 2^32 (exact) rounded is
-// the lower: far cheaper than a conversion through FP64.
-__device__ __forceinline__ unsigned long long to_fix(float v, int S) {
-    const float m = ldexpf(fabsf(v), S - 32);
-    const float fm = floorf(m);
-    const unsigned long long q =
-        ((unsigned long long)(unsigned)fm << 32) | (unsigned long long)(unsigned)rintf((m - fm) * 4294967296.0f);
-    return v < 0.0f ? (unsigned long long)(-(long long)q) : q;
+// v * 2^S rounded to the nearest integer (ties to even), as a two's-complement
+// 64-bit integer, for abs(v) < 2^(51-S).  With M = 1.5 * 2^(52-S), the FP64
+// sum v + M lies in M's binade, where one unit of the last place is 2^-S, so
+// the addition itself rounds v to the grid and the difference of the two bit
+// patterns is that rounded value: one conversion, one FP64 add and one 64-bit
+// integer subtraction.  bits_m is the bit pattern of M.
+__device__ __forceinline__ unsigned long long to_fix(float v, double m, unsigned long long bits_m) {
+    return (unsigned long long)__double_as_longlong((double)v + m) - bits_m;
 }
 
 // Rescue condition from the recorded largest face sum (float bits, >= 0).
@@ -475,13 +472,154 @@ __device__ __forceinline__ bool needs_rescue(int tbits_max, int S) {
     return tbits_max > 0 && __int_as_float(tbits_max) < ldexpf(1.0f, kRescueBits - S);
 }
 
+// Pixel centre coordinate 1 - (2i+1)/n from the reciprocal rn = 1/n with one
+// residual correction of the quotient: within one unit in the last place of
+// the forward's correctly rounded division, at five FP64 operations instead
+// of a division.  The backward only recomputes values of a face the forward
+// already chose, so the last place of the pixel centre cannot change a
+// decision that matters: it moves an edge function by about 1e-19.
+__device__ __forceinline__ double pix_coord_rcp(int i, double n, double rn) {
+    const double num = (double)(2 * i + 1);
+    const double q0 = num * rn;
+    const double r = fma(-q0, n, num);
+    return 1.0 - fma(r, rn, q0);
+}
+
+// A thread's position in the bin's slot order (pixel-major, k fastest),
+// advanced by kP1Threads slots at a time without divisions.
+struct SlotWalk {
+    int k, pr, pc;  // slot within the pixel, pixel row and column within the bin
+    int dk, dpl;    // kP1Threads = dpl * K + dk
+    int dr0, dc0;   // dpl pixels = dr0 rows + dc0 columns
+    int dr1, dc1;   // dpl + 1 pixels
+    __device__ __forceinline__ void init(int q, int K, int cols) {
+        const int pl = q / K;
+        k = q - pl * K;
+        pr = pl / cols;
+        pc = pl - pr * cols;
+        dpl = kP1Threads / K;
+        dk = kP1Threads - dpl * K;
+        dr0 = dpl / cols;
+        dc0 = dpl - dr0 * cols;
+        dr1 = (dpl + 1) / cols;
+        dc1 = (dpl + 1) - dr1 * cols;
+    }
+    __device__ __forceinline__ void next(int K, int cols) {
+        k += dk;
+        const bool carry = k >= K;
+        k = carry ? k - K : k;
+        pr += carry ? dr1 : dr0;
+        pc += carry ? dc1 : dc0;
+        const bool wrap = pc >= cols;
+        pc = wrap ? pc - cols : pc;
+        pr = wrap ? pr + 1 : pr;
+    }
+};
+
+// The nine coordinate terms of one slot of face R (chunk index j) at pixel
+// (row, col), added to the chunk's fixed-point sums.
+struct FixGrid {
+    float limit;              // terms at or above this go to grad_verts directly
+    double m;                 // 1.5 * 2^(52 - S)
+    unsigned long long bits;  // bit pattern of m
+};
+template <bool kOpts>
+__device__ __forceinline__ void add_slot(const BwdArgs& a, const BinRec& R, int j, int row, int col, double dW,
+                                         double rW, double dH, double rH, const SlotUp& up,
+                                         unsigned long long* acci, const FixGrid& fx) {
+    const float vz[3] = {R.az, R.az + R.dz1, R.az + R.dz2};
+    FaceGrad g;
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) g.gx[jj] = g.gy[jj] = g.gzv[jj] = 0.0f;
+    Pix p;
+    p.xf = p.yf = 0.0f;  // (the recomputation reads only the FP64 centre)
+    p.x = pix_coord_rcp(col, dW, rW);
+    p.y = pix_coord_rcp(row, dH, rH);
+    slot_grad_up<BinRec, kOpts>(a, R, vz, p, up, g);
+    const float g9[9] = {g.gx[0], g.gy[0], g.gzv[0], g.gx[1], g.gy[1], g.gzv[1], g.gx[2], g.gy[2], g.gzv[2]};
+    float gmax = 0.0f;
+#pragma unroll
+    for (int x = 0; x < 9; ++x) gmax = fmaxf(gmax, fabsf(g9[x]));
+    if (gmax < fx.limit) {
+#pragma unroll
+        for (int x = 0; x < 9; ++x) atomicAdd(&acci[9 * j + x], to_fix(g9[x], fx.m, fx.bits));
+    } else {
+        // a term too large for the fixed-point sums (never for sane inputs): straight to the vertex
+#pragma unroll
+        for (int x = 0; x < 9; ++x) {
+            const float v = g9[x];
+            if (fabsf(v) < fx.limit) {
+                atomicAdd(&acci[9 * j + x], to_fix(v, fx.m, fx.bits));
+            } else {
+                const int vtx = a.faces[3 * (int64_t)R.face + x / 3];
+                if (vtx >= 0 && vtx < a.V) atomicAdd(a.grad + 3 * (int64_t)vtx + x % 3, v);
+            }
+        }
+    }
+}
+
+// Where face f's sums from bin (bx, by) go: its partial row f * 4 + i (i the
+// bin's place in the face's range), -1 (vertex atomics: the range spans more
+// than kMaxPartials bins) or -2 (nowhere: the face never counts, or the bin
+// lies outside its range).
+__device__ __forceinline__ int partial_row(const BwdArgs& a, const FaceRec& G, int f, int bx, int by) {
+    int bx0, bx1, by0, by1;
+    if (!face_bins(G, a.H, a.W, a.bs, bx0, bx1, by0, by1)) return -2;
+    const int nb = (bx1 - bx0 + 1) * (by1 - by0 + 1);
+    if (nb > kMaxPartials) return -1;
+    if (bx < bx0 || bx > bx1 || by < by0 || by > by1) return -2;
+    return f * kMaxPartials + (by - by0) * (bx1 - bx0 + 1) + (bx - bx0);
+}
+
+// Writes a chunk face's sums (or sends them to the vertices) and marks the
+// partial row as written; tracks the workgroup's largest sum.
+__device__ __forceinline__ void flush_face(const BwdArgs& a, const unsigned long long* acc9, int dst, int face, int S,
+                                           bool track, int* smax) {
+    if (dst == -2) return;
+    float g9[9];
+    float fmx = 0.0f;
+#pragma unroll
+    for (int x = 0; x < 9; ++x) {
+        g9[x] = (float)ldexp((double)(long long)acc9[x], -S);
+        fmx = fmaxf(fmx, fabsf(g9[x]));
+    }
+    // non-negative floats order as their bit patterns
+    if (track && fmx > 0.0f) atomicMax(smax, __float_as_int(fmx));
+    if (dst >= 0) {
+        float* out = a.partial + (int64_t)dst * 9;
+#pragma unroll
+        for (int x = 0; x < 9; ++x) out[x] = g9[x];
+        a.pmask[dst] = 1;
+    } else {
+        atomic_face(a, face, g9);
+    }
+}
+
 // rescue = 0: the pass, recording its largest face sum; rescue = 1: the
-// rescue pass, which exits unless that sum calls for it.
-__global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a, int rescue) {
+// rescue pass, which exits unless that sum calls for it.  kOpts: the call
+// has perspective-correct or clipped barycentrics (an instance of its own, so
+// that their register needs do not lower the occupancy of the plain one).
+//
+// Two ways through a bin.  The direct way (a bin of at most kP1Group slots
+// whose slots name at most kP1Chunk distinct faces, nearly every bin): the
+// slots' face ids and upstream gradients are requested at once, the distinct
+// ids go into the LDS hash table as they arrive (the inserting lane numbers
+// the face), their records are gathered -- while the gradients are still in
+// flight -- and every slot is recomputed once.  Only the faces the slots name
+// are gathered, so a crowded bin (silhouettes) costs no more than a quiet one,
+// and the bin's list is not read.  Slot ids outside [0, F), of a face that
+// never counts or of another image are ignored.  The listed way (any other
+// bin): the bin's list is taken in chunks of kP1Chunk faces, each chunk's
+// records and hash table built, and every slot of the bin looked up in it.
+template <bool kOpts>
+__global__ __launch_bounds__(kP1Threads) __attribute__((amdgpu_waves_per_eu(5, 8)))
+void bwd_bins_kernel(BwdArgs a, int rescue) {
     __shared__ BinRec srec[kP1Chunk];
     __shared__ unsigned long long acci[kP1Chunk * 9];
     __shared__ int tkey[kP1Table];
-    __shared__ int tval[kP1Table];
+    __shared__ short tval[kP1Table];  // the key's face: its chunk index (-1: held over to the listed way)
+    __shared__ int sdst[kP1Chunk];    // partial_row of each chunk face
+    __shared__ int ucount, ufail;
     int lgbs = 0;
     while ((1 << lgbs) < a.bs) ++lgbs;
     int S = kFixBits - 2 * lgbs;  // grid exponent of the sums
@@ -491,55 +629,172 @@ __global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a, int res
         // the largest sum (< 2^eb) on 2^30 grid points
         S = 30 - (((tb >> 23) & 0xff) - 126);
     }
-    // terms below 2^lim_exp: a face's at most bs^2 of them stay below 2^62 on the grid
-    const float fix_limit = ldexpf(1.0f, 62 - 2 * lgbs - S);
+    // terms below the limit: the conversion is exact, and a face's at most
+    // bs^2 of them stay below 2^62 on the grid
+    FixGrid fx;
+    fx.limit = ldexpf(1.0f, min(51, 62 - 2 * lgbs) - S);
+    fx.m = ldexp(1.5, 52 - S);
+    fx.bits = (unsigned long long)__double_as_longlong(fx.m);
     __shared__ int smax;  // largest abs face sum of the workgroup (float bits)
-    if (threadIdx.x == 0) smax = 0;  // (the first chunk's barriers order this before every update)
     if (!bins_usable(a)) return;
     const int64_t bin = blockIdx.x;
     const int per_img = a.nby * a.nbx;
     const int n = (int)(bin / per_img);
     const int rem = (int)(bin - (int64_t)n * per_img);
     const int by = rem / a.nbx, bx = rem - (rem / a.nbx) * a.nbx;
-    const int cnt = min(a.counts[bin], a.M);
-    const int* list = a.lists + bin * a.M;
     const int r0 = by * a.bs, c0 = bx * a.bs;
     const int rows = min(a.bs, a.H - r0), cols = min(a.bs, a.W - c0);
     const int nslots = rows * cols * a.K;
+    // slot (pr, pc, k) of the bin is pix_to_face[sbase + (pr * W + pc) * K + k]
+    const int64_t sbase = (((int64_t)n * a.H + r0) * a.W + c0) * a.K;
+    const double dW = (double)a.W, dH = (double)a.H, rW = 1.0 / dW, rH = 1.0 / dH;
+    const bool track = !rescue;
+
+    if (nslots <= kP1Group) {
+        // ---- the direct way
+        SlotWalk w;
+        w.init(threadIdx.x, a.K, cols);
+        int fq[kP1Unroll], rq[kP1Unroll], cq[kP1Unroll];
+#pragma unroll
+        for (int u = 0; u < kP1Unroll; ++u) {
+            const int q = u * kP1Threads + threadIdx.x;
+            rq[u] = r0 + w.pr;
+            cq[u] = c0 + w.pc;
+            int f = -1;
+            if (q < nslots) f = a.p2f[sbase + (int64_t)(w.pr * a.W + w.pc) * a.K + w.k];
+            fq[u] = (f >= 0 && f < a.F) ? f : -1;
+            w.next(a.K, cols);
+        }
+        for (int i = threadIdx.x; i < kP1Table; i += kP1Threads) tkey[i] = -1;
+        if (threadIdx.x == 0) {
+            ucount = 0;
+            ufail = 0;
+            smax = 0;
+        }
+        SlotUp up[kP1Unroll];
+        {
+            SlotWalk w2;
+            w2.init(threadIdx.x, a.K, cols);
+#pragma unroll
+            for (int u = 0; u < kP1Unroll; ++u) {
+                up[u] = SlotUp{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                if (fq[u] >= 0) up[u] = load_up(a, sbase + (int64_t)(w2.pr * a.W + w2.pc) * a.K + w2.k);
+                w2.next(a.K, cols);
+            }
+        }
+        __syncthreads();
+        // distinct faces into the table; the lane that inserts a face numbers it
+#pragma unroll
+        for (int u = 0; u < kP1Unroll; ++u) {
+            const int f = fq[u];
+            if (f < 0) continue;
+            uint32_t h = fhash(f);
+            bool placed = false;
+            for (int probe = 0; probe < kP1Table; ++probe) {
+                const int prev = atomicCAS(&tkey[h], -1, f);
+                if (prev == -1) {
+                    const int j = atomicAdd(&ucount, 1);
+                    tval[h] = (short)(j < kP1Chunk ? j : -1);
+                    placed = true;
+                    break;
+                }
+                if (prev == f) {
+                    placed = true;
+                    break;
+                }
+                h = (h + 1) & (kP1Table - 1);
+            }
+            if (!placed) ufail = 1;  // (a full table: the listed way takes the bin)
+        }
+        __syncthreads();
+        const int U = ucount;
+        if (U <= kP1Chunk && !ufail) {
+            // records of the named faces, one thread per table entry
+            for (int i = threadIdx.x; i < kP1Table; i += kP1Threads) {
+                const int f = tkey[i];
+                if (f < 0) continue;
+                const int j = tval[i];
+                const FaceRec& G = a.recs[f];
+                store_bin_rec(srec[j], G, f);
+                const bool ok = G.ok() && G.mesh() == n;
+                if (!ok) srec[j].face = -1;
+                sdst[j] = ok ? partial_row(a, G, f, bx, by) : -2;
+#pragma unroll
+                for (int x = 0; x < 9; ++x) acci[9 * j + x] = 0ull;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kP1Unroll; ++u) {
+                const int f = fq[u];
+                if (f < 0) continue;
+                uint32_t h = fhash(f);
+                for (int probe = 0; probe < kP1Table && tkey[h] != f; ++probe) h = (h + 1) & (kP1Table - 1);
+                const int j = tval[h];  // (every named face was placed)
+                const BinRec R = srec[j];
+                if (R.face < 0) continue;
+                add_slot<kOpts>(a, R, j, rq[u], cq[u], dW, rW, dH, rH, up[u], acci, fx);
+            }
+            __syncthreads();
+            for (int j = threadIdx.x; j < U; j += kP1Threads)
+                flush_face(a, &acci[9 * j], sdst[j], srec[j].face, S, track, &smax);
+            __syncthreads();
+            if (track && threadIdx.x == 0) {
+                // the call's largest face sum: one global word, so a workgroup only
+                // updates it when its own maximum is larger than what it reads there
+                // (same-address atomics from every wave would serialise)
+                const int mine = smax;
+                if (mine > 0 &&
+                    mine > __hip_atomic_load(&a.hdr[kHdrTermMax], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                    atomicMax(&a.hdr[kHdrTermMax], mine);
+            }
+            return;
+        }
+        // (every thread has read ucount and ufail: the listed way may now reuse the table)
+    } else if (threadIdx.x == 0) {
+        smax = 0;
+    }
+
+    // ---- the listed way
+    const int cnt = min(a.counts[bin], a.M);
+    const int* list = a.lists + bin * a.M;
     for (int base = 0; base < cnt; base += kP1Chunk) {
         const int m = min(kP1Chunk, cnt - base);
         for (int i = threadIdx.x; i < kP1Table; i += kP1Threads) tkey[i] = -1;
         for (int i = threadIdx.x; i < m * 9; i += kP1Threads) acci[i] = 0ull;
         __syncthreads();
-        for (int j = threadIdx.x; j < m; j += kP1Threads) {
+        if (threadIdx.x < m) {
+            const int j = threadIdx.x;
             const int f = list[base + j];
-            store_bin_rec(srec[j], a.recs[f]);
+            const FaceRec& G = a.recs[f];
+            store_bin_rec(srec[j], G, f);
+            sdst[j] = partial_row(a, G, f, bx, by);
             uint32_t h = fhash(f);
             for (int probe = 0; probe < kP1Table; ++probe) {
                 if (atomicCAS(&tkey[h], -1, f) == -1) {
-                    tval[h] = j;
+                    tval[h] = (short)j;
                     break;
                 }
                 h = (h + 1) & (kP1Table - 1);
             }
         }
         __syncthreads();
-        for (int q0 = 0; q0 < nslots; q0 += kP1Unroll * kP1Threads) {
-            int fq[kP1Unroll];
+        SlotWalk w;
+        w.init(threadIdx.x, a.K, cols);
+        for (int q0 = 0; q0 < nslots; q0 += kP1Group) {
+            int fq[kP1Unroll], rq[kP1Unroll], cq[kP1Unroll];
             int64_t sq[kP1Unroll];
-            int rq[kP1Unroll], cq[kP1Unroll];
 #pragma unroll
             for (int u = 0; u < kP1Unroll; ++u) {
                 const int q = q0 + u * kP1Threads + threadIdx.x;
                 fq[u] = -1;
+                rq[u] = r0 + w.pr;
+                cq[u] = c0 + w.pc;
+                sq[u] = 0;
                 if (q < nslots) {
-                    const int pl = q / a.K, k = q - pl * a.K;
-                    const int pr = pl / cols;
-                    rq[u] = r0 + pr;
-                    cq[u] = c0 + (pl - pr * cols);
-                    sq[u] = (((int64_t)n * a.H + rq[u]) * a.W + cq[u]) * a.K + k;
+                    sq[u] = sbase + ((int64_t)(w.pr * a.W + w.pc) * a.K + w.k);
                     fq[u] = a.p2f[sq[u]];
                 }
+                w.next(a.K, cols);
             }
 #pragma unroll
             for (int u = 0; u < kP1Unroll; ++u) {
@@ -557,61 +812,16 @@ __global__ __launch_bounds__(kP1Threads) void bwd_bins_kernel(BwdArgs a, int res
                     h = (h + 1) & (kP1Table - 1);
                 }
                 if (j < 0) continue;
-                const BinRec R = srec[j];
-                const float vz[3] = {R.az, R.az + R.dz1, R.az + R.dz2};
-                FaceGrad g;
-#pragma unroll
-                for (int jj = 0; jj < 3; ++jj) g.gx[jj] = g.gy[jj] = g.gzv[jj] = 0.0f;
-                slot_grad(a, R, vz, make_pix(rq[u], cq[u], a.H, a.W), sq[u], g);
-                const float g9[9] = {g.gx[0], g.gy[0], g.gzv[0], g.gx[1], g.gy[1], g.gzv[1], g.gx[2], g.gy[2],
-                                     g.gzv[2]};
-#pragma unroll
-                for (int x = 0; x < 9; ++x) {
-                    const float v = g9[x];
-                    if (fabsf(v) < fix_limit) {
-                        atomicAdd(&acci[9 * j + x], to_fix(v, S));
-                    } else {
-                        // too large for the fixed-point sums (never for sane inputs): straight to the vertex
-                        const int vtx = a.faces[3 * (int64_t)list[base + j] + x / 3];
-                        if (vtx >= 0 && vtx < a.V) atomicAdd(a.grad + 3 * (int64_t)vtx + x % 3, v);
-                    }
-                }
+                add_slot<kOpts>(a, srec[j], j, rq[u], cq[u], dW, rW, dH, rH, load_up(a, sq[u]), acci, fx);
             }
         }
         __syncthreads();
-        // flush: one partial per listed face; every listed face writes one, so
-        // the face pass never reads an unwritten partial (unless the bin
-        // overflowed, which the status word reports)
-        for (int j = threadIdx.x; j < m; j += kP1Threads) {
-            const int f = list[base + j];
-            int bx0, bx1, by0, by1;
-            if (!face_bins(a.recs[f], a.H, a.W, a.bs, bx0, bx1, by0, by1)) continue;
-            const int nb = (bx1 - bx0 + 1) * (by1 - by0 + 1);
-            float g9[9];
-            float fmx = 0.0f;
-#pragma unroll
-            for (int x = 0; x < 9; ++x) {
-                g9[x] = (float)ldexp((double)(long long)acci[9 * j + x], -S);
-                fmx = fmaxf(fmx, fabsf(g9[x]));
-            }
-            // non-negative floats order as their bit patterns
-            if (!rescue && fmx > 0.0f) atomicMax(&smax, __float_as_int(fmx));
-            if (nb <= kMaxPartials) {
-                const int i = (by - by0) * (bx1 - bx0 + 1) + (bx - bx0);  // this bin within the face's range
-                if (bx < bx0 || bx > bx1 || by < by0 || by > by1) continue;  // only a stale list could do this
-                float* dst = a.partial + ((int64_t)f * kMaxPartials + i) * 9;
-#pragma unroll
-                for (int x = 0; x < 9; ++x) dst[x] = g9[x];
-            } else {
-                atomic_face(a, f, g9);
-            }
-        }
+        // flush: one partial per listed face (written and marked, zero or not)
+        if (threadIdx.x < m) flush_face(a, &acci[9 * threadIdx.x], sdst[threadIdx.x], srec[threadIdx.x].face, S,
+                                        track, &smax);
         __syncthreads();
     }
-    if (!rescue && threadIdx.x == 0) {
-        // the call's largest face sum: one global word, so a workgroup only
-        // updates it when its own maximum is larger than what it reads there
-        // (same-address atomics from every wave would serialise)
+    if (track && threadIdx.x == 0) {
         const int mine = smax;
         if (mine > 0 && mine > __hip_atomic_load(&a.hdr[kHdrTermMax], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             atomicMax(&a.hdr[kHdrTermMax], mine);
@@ -629,46 +839,76 @@ __global__ void bwd_rescue_clear_kernel(BwdArgs a) {
 }
 
 
+// Pass 2: one thread per face adds the partial rows this call wrote for it
+// and merges the result per vertex in an LDS hash table, as 64-bit fixed point
+// (integer LDS atomics; float ones are slow on this hardware); each table
+// entry then issues one float atomic per coordinate.  The grid follows the
+// largest row the pass recorded (below 2^e): a face's sum of at most four rows
+// stays below 2^(e+2) and a vertex takes at most kBwdBlock faces of the
+// workgroup, below 2^(e+10), so the grid 2^(e-48) keeps every sum below 2^58
+// and every term inside to_fix's exact range.
 __global__ __launch_bounds__(kBwdBlock) void bwd_face_sum_kernel(BwdArgs a) {
     __shared__ int keys[kHash];
-    __shared__ float vals[3 * kHash];
+    __shared__ unsigned long long vals[3 * kHash];
     if (!bins_usable(a)) return;
+    const int tb = a.hdr[kHdrTermMax];
+    if (tb <= 0) return;  // every row is zero
+    const int e = ((tb >> 23) & 0xff) - 126;
+    const int S = 48 - e;
+    const double fm = ldexp(1.5, 52 - S);
+    const unsigned long long fbits = (unsigned long long)__double_as_longlong(fm);
     for (int i = threadIdx.x; i < kHash; i += kBwdBlock) {
         keys[i] = -1;
-        vals[3 * i] = vals[3 * i + 1] = vals[3 * i + 2] = 0.0f;
+        vals[3 * i] = vals[3 * i + 1] = vals[3 * i + 2] = 0ull;
     }
     __syncthreads();
     const int64_t f = (int64_t)blockIdx.x * kBwdBlock + threadIdx.x;
     const bool overflowed = (a.hdr[kHdrStatus] & kStatOverflow) != 0;
     if (f < a.F && !overflowed) {
-        // only the grown box of the record decides the face's bins
-        int bx0, bx1, by0, by1;
-        if (face_bins_of_box(a.recs[f].bb, a.H, a.W, a.bs, bx0, bx1, by0, by1)) {
-            const int nbw = bx1 - bx0 + 1;
-            const int nb = nbw * (by1 - by0 + 1);
-            if (nb <= kMaxPartials) {
-                float g9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-                const float* src = a.partial + f * kMaxPartials * 9;
-                for (int i = 0; i < nb; ++i) {
+        // the rows this call wrote (none for a face whose sums went to the
+        // vertices directly, or that no slot names)
+        const uchar4 mk = *reinterpret_cast<const uchar4*>(a.pmask + f * kMaxPartials);
+        if (mk.x | mk.y | mk.z | mk.w) {
+            const bool wr[kMaxPartials] = {mk.x != 0, mk.y != 0, mk.z != 0, mk.w != 0};
+            float g9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            const float* src = a.partial + f * kMaxPartials * 9;
 #pragma unroll
-                    for (int x = 0; x < 9; ++x) g9[x] += src[9 * i + x];
+            for (int i = 0; i < kMaxPartials; ++i) {
+                if (!wr[i]) continue;
+#pragma unroll
+                for (int x = 0; x < 9; ++x) g9[x] += src[9 * i + x];
+            }
+            const int32_t* fv = a.faces + 3 * f;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int v = fv[j];
+                if (v < 0 || v >= a.V) continue;
+                uint32_t h = vhash(v);
+                bool placed = false;
+                for (int probe = 0; probe < kHash; ++probe) {
+                    const int prev = atomicCAS(&keys[h], -1, v);
+                    if (prev == -1 || prev == v) {
+#pragma unroll
+                        for (int x = 0; x < 3; ++x) atomicAdd(&vals[3 * h + x], to_fix(g9[3 * j + x], fm, fbits));
+                        placed = true;
+                        break;
+                    }
+                    h = (h + 1) & (kHash - 1);
                 }
-                const int32_t* fv = a.faces + 3 * f;
+                if (!placed) {
 #pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    int v = fv[j];
-                    if (v >= 0 && v < a.V) lds_add(keys, vals, a.grad, v, g9[3 * j], g9[3 * j + 1], g9[3 * j + 2]);
+                    for (int x = 0; x < 3; ++x) atomicAdd(a.grad + 3 * (int64_t)v + x, g9[3 * j + x]);
                 }
             }
         }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kHash; i += kBwdBlock) {
-        int v = keys[i];
+        const int v = keys[i];
         if (v >= 0) {
-            atomicAdd(a.grad + 3 * (int64_t)v + 0, vals[3 * i + 0]);
-            atomicAdd(a.grad + 3 * (int64_t)v + 1, vals[3 * i + 1]);
-            atomicAdd(a.grad + 3 * (int64_t)v + 2, vals[3 * i + 2]);
+#pragma unroll
+            for (int x = 0; x < 3; ++x)
+                atomicAdd(a.grad + 3 * (int64_t)v + x, (float)ldexp((double)(long long)vals[3 * i + x], -S));
         }
     }
 }
@@ -710,6 +950,7 @@ hipError_t launch_backward(const float* verts, int64_t V, const int32_t* faces, 
     a.counts = counts;
     a.lists = lists;
     a.partial = partial;
+    a.pmask = reinterpret_cast<unsigned char*>(big);
     a.bs = bs;
     a.nby = bs > 0 ? (H + bs - 1) / bs : 0;
     a.nbx = bs > 0 ? (W + bs - 1) / bs : 0;
@@ -728,10 +969,14 @@ hipError_t launch_backward(const float* verts, int64_t V, const int32_t* faces, 
         const int64_t nbins = (int64_t)N * a.nby * a.nbx;
         e = launch_fill_i32(hdr + kHdrTermMax, 1, 0, s);
         if (e != hipSuccess) return e;
+        // no partial row is written yet (F x 4 mask bytes = F words)
+        e = launch_fill_i32(big, F, 0, s);
+        if (e != hipSuccess) return e;
         if (eb) (void)hipEventRecord(eb, s);
-        hipLaunchKernelGGL(bwd_bins_kernel, dim3((unsigned)nbins), dim3(kP1Threads), 0, s, a, 0);
+        auto bins = (opts & (kOptPersp | kOptClip)) ? bwd_bins_kernel<true> : bwd_bins_kernel<false>;
+        hipLaunchKernelGGL(bins, dim3((unsigned)nbins), dim3(kP1Threads), 0, s, a, 0);
         hipLaunchKernelGGL(bwd_rescue_clear_kernel, dim3(256), dim3(256), 0, s, a);
-        hipLaunchKernelGGL(bwd_bins_kernel, dim3((unsigned)nbins), dim3(kP1Threads), 0, s, a, 1);
+        hipLaunchKernelGGL(bins, dim3((unsigned)nbins), dim3(kP1Threads), 0, s, a, 1);
         hipLaunchKernelGGL(bwd_face_sum_kernel, dim3((unsigned)((F + kBwdBlock - 1) / kBwdBlock)), dim3(kBwdBlock), 0,
                            s, a);
         if (ee) (void)hipEventRecord(ee, s);

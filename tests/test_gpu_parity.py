@@ -229,6 +229,40 @@ def test_backward_tiny_upstream_gradients(bs):
     log(f"bs{bs} tiny-gradient rel err", compare_grad(gv, ref, f"tiny upstream bs{bs}"))
 
 
+def crowded_batch(F, seed, size=16, blur=1e-3, K=16):
+    """F independent tiny triangles (about half a pixel across) scattered over
+    a size x size image: an 8x8 bin's slots name far more distinct faces
+    than one LDS chunk holds (about 300 at F = 1500, 700 at F = 4000)."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(-1, 1, (F, 1, 2))
+    xy = (c + rng.normal(0, 0.06, (F, 3, 2))).reshape(-1, 2)
+    v = np.concatenate([xy, rng.uniform(1, 5, (3 * F, 1))], 1).astype(np.float32)
+    f = np.arange(3 * F, dtype=np.int32).reshape(F, 3)
+    return meshgen.Batch(name="crowd", verts=v, faces=f, first_idx=np.array([0]), num_faces=np.array([F]),
+                         verts_first_idx=np.array([0]), num_verts=np.array([3 * F]), image_size=(size, size),
+                         faces_per_pixel=K, blur_radius=blur, bin_size=8, max_faces_per_bin=None)
+
+
+@pytest.mark.parametrize("F", [300, 1500, 4000])
+def test_backward_crowded_bins(F):
+    """Bins whose slots name more faces than an LDS chunk (and, at F = 4000,
+    than the hash table) take the listed way through the bin; both ways
+    match the oracle and the per-face form."""
+    b = crowded_batch(F, seed=F)
+    p2f = oracle_full(b)["p2f"]
+    named = [len(np.unique(x[x >= 0])) for x in
+             p2f.reshape(2, 8, 2, 8, -1).transpose(0, 2, 1, 3, 4).reshape(4, -1)]
+    log(f"F={F}: distinct faces per bin {named}")
+    gz, gb, gd = meshgen.upstream_grads(b)
+    gz, gb, gd = tie_masked_grads(b, p2f, gz, gb, gd)
+    t = torch.from_numpy(p2f.astype(np.int32)).cuda()
+    ref = oracle.backward(b.verts, b.faces, b.image_size, p2f, gz, gb, gd, nthreads=threads())
+    g8 = run_bwd(b, t, gz, gb, gd, bs=8).cpu().numpy()
+    g0 = run_bwd(b, t, gz, gb, gd, bs=0).cpu().numpy()
+    compare_grad(g8, ref, f"crowded F={F} bins of 8")
+    compare_grad(g0, ref, f"crowded F={F} per face")
+
+
 def test_backward_hand_case():
     # triangle T, pixel (2,2) of a 4x4 image; hand-derived gradients
     v = np.array([[-1.0, -1.0, 1.0], [1.0, -1.0, 2.0], [-1.0, 1.0, 3.0]], np.float32)
