@@ -456,6 +456,7 @@ __device__ __forceinline__ void store_bin_rec(BinRec& d, const FaceRec& R, int f
 
 constexpr int kFixBits = 38;     // fixed-point grid 2^-(kFixBits - 2 log2(bin size))
 constexpr int kRescueBits = 18;  // a largest face sum below 2^18 grid points triggers the rescue
+constexpr int kRescueGrid = 2048;  // workgroups of the rescue launch
 
 // v * 2^S rounded to the nearest integer (ties to even), as a two's-complement
 // 64-bit integer, for abs(v) < 2^(51-S).  With M = 1.5 * 2^(52-S), the FP64
@@ -611,7 +612,7 @@ __device__ __forceinline__ void flush_face(const BwdArgs& a, const unsigned long
 // never counts or of another image are ignored.  The listed way (any other
 // bin): the bin's list is taken in chunks of kP1Chunk faces, each chunk's
 // records and hash table built, and every slot of the bin looked up in it.
-template <bool kOpts>
+template <bool kOpts, bool kLoop>
 __global__ __launch_bounds__(kP1Threads) __attribute__((amdgpu_waves_per_eu(5, 8)))
 void bwd_bins_kernel(BwdArgs a, int rescue) {
     __shared__ BinRec srec[kP1Chunk];
@@ -637,191 +638,190 @@ void bwd_bins_kernel(BwdArgs a, int rescue) {
     fx.bits = (unsigned long long)__double_as_longlong(fx.m);
     __shared__ int smax;  // largest abs face sum of the workgroup (float bits)
     if (!bins_usable(a)) return;
-    const int64_t bin = blockIdx.x;
-    const int per_img = a.nby * a.nbx;
-    const int n = (int)(bin / per_img);
-    const int rem = (int)(bin - (int64_t)n * per_img);
-    const int by = rem / a.nbx, bx = rem - (rem / a.nbx) * a.nbx;
-    const int r0 = by * a.bs, c0 = bx * a.bs;
-    const int rows = min(a.bs, a.H - r0), cols = min(a.bs, a.W - c0);
-    const int nslots = rows * cols * a.K;
-    // slot (pr, pc, k) of the bin is pix_to_face[sbase + (pr * W + pc) * K + k]
-    const int64_t sbase = (((int64_t)n * a.H + r0) * a.W + c0) * a.K;
-    const double dW = (double)a.W, dH = (double)a.H, rW = 1.0 / dW, rH = 1.0 / dH;
+    if (threadIdx.x == 0) smax = 0;  // (ordered before every update by the first bin's barriers)
     const bool track = !rescue;
+    const int per_img = a.nby * a.nbx;
+    const int64_t nbins = (int64_t)a.N * per_img;
+    // kLoop: a grid smaller than the bin count (the rescue launch) walks the
+    // bins; otherwise the grid is one workgroup per bin (either way
+    // blockIdx.x < nbins)
+    int64_t bin = blockIdx.x;
+    do {
+        const int n = (int)(bin / per_img);
+        const int rem = (int)(bin - (int64_t)n * per_img);
+        const int by = rem / a.nbx, bx = rem - (rem / a.nbx) * a.nbx;
+        const int r0 = by * a.bs, c0 = bx * a.bs;
+        const int rows = min(a.bs, a.H - r0), cols = min(a.bs, a.W - c0);
+        const int nslots = rows * cols * a.K;
+        // slot (pr, pc, k) of the bin is pix_to_face[sbase + (pr * W + pc) * K + k]
+        const int64_t sbase = (((int64_t)n * a.H + r0) * a.W + c0) * a.K;
+        const double dW = (double)a.W, dH = (double)a.H, rW = 1.0 / dW, rH = 1.0 / dH;
 
-    if (nslots <= kP1Group) {
-        // ---- the direct way
-        SlotWalk w;
-        w.init(threadIdx.x, a.K, cols);
-        int fq[kP1Unroll], rq[kP1Unroll], cq[kP1Unroll];
-#pragma unroll
-        for (int u = 0; u < kP1Unroll; ++u) {
-            const int q = u * kP1Threads + threadIdx.x;
-            rq[u] = r0 + w.pr;
-            cq[u] = c0 + w.pc;
-            int f = -1;
-            if (q < nslots) f = a.p2f[sbase + (int64_t)(w.pr * a.W + w.pc) * a.K + w.k];
-            fq[u] = (f >= 0 && f < a.F) ? f : -1;
-            w.next(a.K, cols);
-        }
-        for (int i = threadIdx.x; i < kP1Table; i += kP1Threads) tkey[i] = -1;
-        if (threadIdx.x == 0) {
-            ucount = 0;
-            ufail = 0;
-            smax = 0;
-        }
-        SlotUp up[kP1Unroll];
-        {
-            SlotWalk w2;
-            w2.init(threadIdx.x, a.K, cols);
-#pragma unroll
-            for (int u = 0; u < kP1Unroll; ++u) {
-                up[u] = SlotUp{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-                if (fq[u] >= 0) up[u] = load_up(a, sbase + (int64_t)(w2.pr * a.W + w2.pc) * a.K + w2.k);
-                w2.next(a.K, cols);
-            }
-        }
-        __syncthreads();
-        // distinct faces into the table; the lane that inserts a face numbers it
-#pragma unroll
-        for (int u = 0; u < kP1Unroll; ++u) {
-            const int f = fq[u];
-            if (f < 0) continue;
-            uint32_t h = fhash(f);
-            bool placed = false;
-            for (int probe = 0; probe < kP1Table; ++probe) {
-                const int prev = atomicCAS(&tkey[h], -1, f);
-                if (prev == -1) {
-                    const int j = atomicAdd(&ucount, 1);
-                    tval[h] = (short)(j < kP1Chunk ? j : -1);
-                    placed = true;
-                    break;
-                }
-                if (prev == f) {
-                    placed = true;
-                    break;
-                }
-                h = (h + 1) & (kP1Table - 1);
-            }
-            if (!placed) ufail = 1;  // (a full table: the listed way takes the bin)
-        }
-        __syncthreads();
-        const int U = ucount;
-        if (U <= kP1Chunk && !ufail) {
-            // records of the named faces, one thread per table entry
-            for (int i = threadIdx.x; i < kP1Table; i += kP1Threads) {
-                const int f = tkey[i];
-                if (f < 0) continue;
-                const int j = tval[i];
-                const FaceRec& G = a.recs[f];
-                store_bin_rec(srec[j], G, f);
-                const bool ok = G.ok() && G.mesh() == n;
-                if (!ok) srec[j].face = -1;
-                sdst[j] = ok ? partial_row(a, G, f, bx, by) : -2;
-#pragma unroll
-                for (int x = 0; x < 9; ++x) acci[9 * j + x] = 0ull;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int u = 0; u < kP1Unroll; ++u) {
-                const int f = fq[u];
-                if (f < 0) continue;
-                uint32_t h = fhash(f);
-                for (int probe = 0; probe < kP1Table && tkey[h] != f; ++probe) h = (h + 1) & (kP1Table - 1);
-                const int j = tval[h];  // (every named face was placed)
-                const BinRec R = srec[j];
-                if (R.face < 0) continue;
-                add_slot<kOpts>(a, R, j, rq[u], cq[u], dW, rW, dH, rH, up[u], acci, fx);
-            }
-            __syncthreads();
-            for (int j = threadIdx.x; j < U; j += kP1Threads)
-                flush_face(a, &acci[9 * j], sdst[j], srec[j].face, S, track, &smax);
-            __syncthreads();
-            if (track && threadIdx.x == 0) {
-                // the call's largest face sum: one global word, so a workgroup only
-                // updates it when its own maximum is larger than what it reads there
-                // (same-address atomics from every wave would serialise)
-                const int mine = smax;
-                if (mine > 0 &&
-                    mine > __hip_atomic_load(&a.hdr[kHdrTermMax], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                    atomicMax(&a.hdr[kHdrTermMax], mine);
-            }
-            return;
-        }
-        // (every thread has read ucount and ufail: the listed way may now reuse the table)
-    } else if (threadIdx.x == 0) {
-        smax = 0;
-    }
-
-    // ---- the listed way
-    const int cnt = min(a.counts[bin], a.M);
-    const int* list = a.lists + bin * a.M;
-    for (int base = 0; base < cnt; base += kP1Chunk) {
-        const int m = min(kP1Chunk, cnt - base);
-        for (int i = threadIdx.x; i < kP1Table; i += kP1Threads) tkey[i] = -1;
-        for (int i = threadIdx.x; i < m * 9; i += kP1Threads) acci[i] = 0ull;
-        __syncthreads();
-        if (threadIdx.x < m) {
-            const int j = threadIdx.x;
-            const int f = list[base + j];
-            const FaceRec& G = a.recs[f];
-            store_bin_rec(srec[j], G, f);
-            sdst[j] = partial_row(a, G, f, bx, by);
-            uint32_t h = fhash(f);
-            for (int probe = 0; probe < kP1Table; ++probe) {
-                if (atomicCAS(&tkey[h], -1, f) == -1) {
-                    tval[h] = (short)j;
-                    break;
-                }
-                h = (h + 1) & (kP1Table - 1);
-            }
-        }
-        __syncthreads();
-        SlotWalk w;
-        w.init(threadIdx.x, a.K, cols);
-        for (int q0 = 0; q0 < nslots; q0 += kP1Group) {
+        if (nslots <= kP1Group) {
+            // ---- the direct way
+            SlotWalk w;
+            w.init(threadIdx.x, a.K, cols);
             int fq[kP1Unroll], rq[kP1Unroll], cq[kP1Unroll];
-            int64_t sq[kP1Unroll];
 #pragma unroll
             for (int u = 0; u < kP1Unroll; ++u) {
-                const int q = q0 + u * kP1Threads + threadIdx.x;
-                fq[u] = -1;
+                const int q = u * kP1Threads + threadIdx.x;
                 rq[u] = r0 + w.pr;
                 cq[u] = c0 + w.pc;
-                sq[u] = 0;
-                if (q < nslots) {
-                    sq[u] = sbase + ((int64_t)(w.pr * a.W + w.pc) * a.K + w.k);
-                    fq[u] = a.p2f[sq[u]];
-                }
+                int f = -1;
+                if (q < nslots) f = a.p2f[sbase + (int64_t)(w.pr * a.W + w.pc) * a.K + w.k];
+                fq[u] = (f >= 0 && f < a.F) ? f : -1;
                 w.next(a.K, cols);
             }
+            for (int i = threadIdx.x; i < kP1Table; i += kP1Threads) tkey[i] = -1;
+            if (threadIdx.x == 0) {
+                ucount = 0;
+                ufail = 0;
+            }
+            SlotUp up[kP1Unroll];
+            {
+                SlotWalk w2;
+                w2.init(threadIdx.x, a.K, cols);
+#pragma unroll
+                for (int u = 0; u < kP1Unroll; ++u) {
+                    up[u] = SlotUp{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                    if (fq[u] >= 0) up[u] = load_up(a, sbase + (int64_t)(w2.pr * a.W + w2.pc) * a.K + w2.k);
+                    w2.next(a.K, cols);
+                }
+            }
+            __syncthreads();
+            // distinct faces into the table; the lane that inserts a face numbers it
 #pragma unroll
             for (int u = 0; u < kP1Unroll; ++u) {
                 const int f = fq[u];
                 if (f < 0) continue;
-                int j = -1;
                 uint32_t h = fhash(f);
+                bool placed = false;
                 for (int probe = 0; probe < kP1Table; ++probe) {
-                    const int key = tkey[h];
-                    if (key == f) {
-                        j = tval[h];
+                    const int prev = atomicCAS(&tkey[h], -1, f);
+                    if (prev == -1) {
+                        const int j = atomicAdd(&ucount, 1);
+                        tval[h] = (short)(j < kP1Chunk ? j : -1);
+                        placed = true;
                         break;
                     }
-                    if (key == -1) break;
+                    if (prev == f) {
+                        placed = true;
+                        break;
+                    }
                     h = (h + 1) & (kP1Table - 1);
                 }
-                if (j < 0) continue;
-                add_slot<kOpts>(a, srec[j], j, rq[u], cq[u], dW, rW, dH, rH, load_up(a, sq[u]), acci, fx);
+                if (!placed) ufail = 1;  // (a full table: the listed way takes the bin)
             }
+            __syncthreads();
+            const int U = ucount;
+            if (U <= kP1Chunk && !ufail) {
+                // records of the named faces, one thread per table entry
+                for (int i = threadIdx.x; i < kP1Table; i += kP1Threads) {
+                    const int f = tkey[i];
+                    if (f < 0) continue;
+                    const int j = tval[i];
+                    const FaceRec& G = a.recs[f];
+                    store_bin_rec(srec[j], G, f);
+                    const bool ok = G.ok() && G.mesh() == n;
+                    if (!ok) srec[j].face = -1;
+                    sdst[j] = ok ? partial_row(a, G, f, bx, by) : -2;
+#pragma unroll
+                    for (int x = 0; x < 9; ++x) acci[9 * j + x] = 0ull;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < kP1Unroll; ++u) {
+                    const int f = fq[u];
+                    if (f < 0) continue;
+                    uint32_t h = fhash(f);
+                    for (int probe = 0; probe < kP1Table && tkey[h] != f; ++probe) h = (h + 1) & (kP1Table - 1);
+                    const int j = tval[h];  // (every named face was placed)
+                    const BinRec R = srec[j];
+                    if (R.face < 0) continue;
+                    add_slot<kOpts>(a, R, j, rq[u], cq[u], dW, rW, dH, rH, up[u], acci, fx);
+                }
+                __syncthreads();
+                for (int j = threadIdx.x; j < U; j += kP1Threads)
+                    flush_face(a, &acci[9 * j], sdst[j], srec[j].face, S, track, &smax);
+                __syncthreads();
+                continue;
+            }
+            // (every thread has read ucount and ufail: the listed way may now reuse the table)
         }
-        __syncthreads();
-        // flush: one partial per listed face (written and marked, zero or not)
-        if (threadIdx.x < m) flush_face(a, &acci[9 * threadIdx.x], sdst[threadIdx.x], srec[threadIdx.x].face, S,
-                                        track, &smax);
-        __syncthreads();
-    }
+
+        // ---- the listed way
+        const int cnt = min(a.counts[bin], a.M);
+        const int* list = a.lists + bin * a.M;
+        for (int base = 0; base < cnt; base += kP1Chunk) {
+            const int m = min(kP1Chunk, cnt - base);
+            for (int i = threadIdx.x; i < kP1Table; i += kP1Threads) tkey[i] = -1;
+            for (int i = threadIdx.x; i < m * 9; i += kP1Threads) acci[i] = 0ull;
+            __syncthreads();
+            if (threadIdx.x < m) {
+                const int j = threadIdx.x;
+                const int f = list[base + j];
+                const FaceRec& G = a.recs[f];
+                store_bin_rec(srec[j], G, f);
+                sdst[j] = partial_row(a, G, f, bx, by);
+                uint32_t h = fhash(f);
+                for (int probe = 0; probe < kP1Table; ++probe) {
+                    if (atomicCAS(&tkey[h], -1, f) == -1) {
+                        tval[h] = (short)j;
+                        break;
+                    }
+                    h = (h + 1) & (kP1Table - 1);
+                }
+            }
+            __syncthreads();
+            SlotWalk w;
+            w.init(threadIdx.x, a.K, cols);
+            for (int q0 = 0; q0 < nslots; q0 += kP1Group) {
+                int fq[kP1Unroll], rq[kP1Unroll], cq[kP1Unroll];
+                int64_t sq[kP1Unroll];
+#pragma unroll
+                for (int u = 0; u < kP1Unroll; ++u) {
+                    const int q = q0 + u * kP1Threads + threadIdx.x;
+                    fq[u] = -1;
+                    rq[u] = r0 + w.pr;
+                    cq[u] = c0 + w.pc;
+                    sq[u] = 0;
+                    if (q < nslots) {
+                        sq[u] = sbase + ((int64_t)(w.pr * a.W + w.pc) * a.K + w.k);
+                        fq[u] = a.p2f[sq[u]];
+                    }
+                    w.next(a.K, cols);
+                }
+#pragma unroll
+                for (int u = 0; u < kP1Unroll; ++u) {
+                    const int f = fq[u];
+                    if (f < 0) continue;
+                    int j = -1;
+                    uint32_t h = fhash(f);
+                    for (int probe = 0; probe < kP1Table; ++probe) {
+                        const int key = tkey[h];
+                        if (key == f) {
+                            j = tval[h];
+                            break;
+                        }
+                        if (key == -1) break;
+                        h = (h + 1) & (kP1Table - 1);
+                    }
+                    if (j < 0) continue;
+                    add_slot<kOpts>(a, srec[j], j, rq[u], cq[u], dW, rW, dH, rH, load_up(a, sq[u]), acci, fx);
+                }
+            }
+            __syncthreads();
+            // flush: one partial per listed face (written and marked, zero or not)
+            if (threadIdx.x < m) flush_face(a, &acci[9 * threadIdx.x], sdst[threadIdx.x], srec[threadIdx.x].face, S,
+                                            track, &smax);
+            __syncthreads();
+        }
+        __syncthreads();  // (a bin without chunks has no barrier of its own)
+    } while (kLoop && (bin += gridDim.x) < nbins);
     if (track && threadIdx.x == 0) {
+        // the call's largest face sum: one global word, so a workgroup only
+        // updates it when its own maximum is larger than what it reads there
+        // (same-address atomics from every wave would serialise)
         const int mine = smax;
         if (mine > 0 && mine > __hip_atomic_load(&a.hdr[kHdrTermMax], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             atomicMax(&a.hdr[kHdrTermMax], mine);
@@ -973,10 +973,14 @@ hipError_t launch_backward(const float* verts, int64_t V, const int32_t* faces, 
         e = launch_fill_i32(big, F, 0, s);
         if (e != hipSuccess) return e;
         if (eb) (void)hipEventRecord(eb, s);
-        auto bins = (opts & (kOptPersp | kOptClip)) ? bwd_bins_kernel<true> : bwd_bins_kernel<false>;
+        const bool o = (opts & (kOptPersp | kOptClip)) != 0;
+        auto bins = o ? bwd_bins_kernel<true, false> : bwd_bins_kernel<false, false>;
+        auto rescue = o ? bwd_bins_kernel<true, true> : bwd_bins_kernel<false, true>;
         hipLaunchKernelGGL(bins, dim3((unsigned)nbins), dim3(kP1Threads), 0, s, a, 0);
         hipLaunchKernelGGL(bwd_rescue_clear_kernel, dim3(256), dim3(256), 0, s, a);
-        hipLaunchKernelGGL(bins, dim3((unsigned)nbins), dim3(kP1Threads), 0, s, a, 1);
+        // the rescue launch normally exits at once: a small grid that walks the bins when it does not
+        hipLaunchKernelGGL(rescue, dim3((unsigned)(nbins < kRescueGrid ? nbins : kRescueGrid)), dim3(kP1Threads), 0,
+                           s, a, 1);
         hipLaunchKernelGGL(bwd_face_sum_kernel, dim3((unsigned)((F + kBwdBlock - 1) / kBwdBlock)), dim3(kBwdBlock), 0,
                            s, a);
         if (ee) (void)hipEventRecord(ee, s);
