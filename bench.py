@@ -507,7 +507,7 @@ def main():
             bs, M, sched = b.bin_size, (b.max_faces_per_bin or 0) if b.bin_size > 0 else 0, 0
             log(f"[bench] batch {batch}: bins fixed by the workload: bin_size={bs} M={M}")
         elif args.bin_size is None:
-            ch = autotune(v, f, fi, nf, H, W, b.blur_radius, K, reps=3, backward=b.backward)
+            ch = autotune(v, f, fi, nf, H, W, b.blur_radius, K, reps=5, backward=b.backward)
             bs, M, sched = ch.bin_size, ch.max_faces_per_bin, ch.sched
             log(f"[bench] batch {batch}: autotune -> bin_size={bs} M={M} sched={sched} ({ch.ms:.3f} ms) in "
                 f"{time.time() - t0:.1f}s")

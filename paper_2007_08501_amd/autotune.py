@@ -3,7 +3,8 @@
 For each candidate bin size the counting pass gives the exact largest bin
 count, which sizes max_faces_per_bin (rounded up to 32); each candidate
 (bin size, scheduler) is then timed forward+backward with HIP events on the
-current stream, and the fastest is cached per device and problem signature
+current stream, all candidates in turn in each of several rounds (the median
+per candidate), and the fastest is cached per device and problem signature
 (image size, K, blur, face count, spread of faces per mesh).  The
 single-pass form (bin_size 0) is a candidate when its work is small.
 """
@@ -67,12 +68,10 @@ def signature(verts, faces, first_idx, num_faces, H, W, blur, K) -> str:
     return f"{dev}|N{first_idx.shape[0]}|{H}x{W}|K{K}|b{blur:.3e}|F{faces.shape[0]}|h{bucket[0]}.{bucket[1]}"
 
 
-def _time_candidate(verts, faces, first_idx, num_faces, H, W, blur, K, bs, M, sched, grads, reps) -> float:
-    N = first_idx.shape[0]
-    out = empty_fragments(N, H, W, K, verts.device)
-    ws = workspace(verts.device, _lib.rast_workspace_size(N, H, W, faces.shape[0], bs, M))
-    gv = torch.empty_like(verts)
-
+def _prepare_candidate(verts, faces, first_idx, num_faces, H, W, blur, K, bs, M, sched, grads, out, gv, ws):
+    """One forward(+backward) step of a candidate into the given outputs and
+    workspace, run once (None if the candidate reports an error, e.g. a bin
+    overflow)."""
     def step():
         forward_into(verts, faces, first_idx, num_faces, H, W, blur, K, bs, M, sched, out, ws)
         if grads is not None:
@@ -82,19 +81,43 @@ def _time_candidate(verts, faces, first_idx, num_faces, H, W, blur, K, bs, M, sc
 
     step()
     st, _ = _lib.rast_query_status(ws)
-    if st != _lib.RAST_OK:
-        return float("inf")
-    times = []
+    return step if st == _lib.RAST_OK else None
+
+
+def _time_step(step) -> float:
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    step()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b)
+
+
+def _time_candidates(verts, faces, first_idx, num_faces, H, W, blur, K, cands, grads, reps):
+    """Median time of each candidate (inf if it fails), the candidates timed in
+    turn within each of reps rounds, after one untimed round: a drift of the
+    clock over the tuning (the GPU ramping up) then affects every candidate
+    alike instead of penalising the first ones.  The steps run one after the
+    other on the current stream, so they share the output buffers (and the
+    device's scratch workspace, while it is large enough)."""
+    N = first_idx.shape[0]
+    out = empty_fragments(N, H, W, K, verts.device)
+    gv = torch.empty_like(verts)
+    steps = []
+    for bs, M, sc in cands:
+        ws = workspace(verts.device, _lib.rast_workspace_size(N, H, W, faces.shape[0], bs, M))
+        steps.append(_prepare_candidate(verts, faces, first_idx, num_faces, H, W, blur, K, bs, M, sc, grads, out, gv,
+                                        ws))
+    for step in steps:
+        if step is not None:
+            step()
+    times = [[] for _ in cands]
     for _ in range(reps):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        step()
-        b.record()
-        b.synchronize()
-        times.append(a.elapsed_time(b))
-    times.sort()
-    return times[len(times) // 2]
+        for i, step in enumerate(steps):
+            if step is not None:
+                times[i].append(_time_step(step))
+    return [sorted(t)[len(t) // 2] if t else float("inf") for t in times]
 
 
 def autotune(verts, faces, first_idx, num_faces, H, W, blur, K, bin_sizes: Iterable[int] = DEFAULT_BIN_SIZES,
@@ -134,8 +157,8 @@ def autotune(verts, faces, first_idx, num_faces, H, W, blur, K, bin_sizes: Itera
             continue
         for sc in scheds:
             cands.append((bs, M, sc))
-    for bs, M, sc in cands:
-        ms = _time_candidate(verts, faces, first_idx, num_faces, H, W, blur, K, bs, M, sc, grads, reps)
+    for (bs, M, sc), ms in zip(cands, _time_candidates(verts, faces, first_idx, num_faces, H, W, blur, K, cands,
+                                                        grads, reps)):
         if best is None or ms < best.ms:
             best = Choice(bs, M, sc, ms)
     if best is None:

@@ -115,45 +115,95 @@ hipError_t launch_face_setup(const float* verts, int64_t V, const int32_t* faces
     return hipGetLastError();
 }
 
-// One thread per face appends the face to every bin of its range.  Lanes of a
-// wave hold consecutive faces, which are usually neighbours on the mesh and
-// share bins, so the appends are aggregated per wave: for each distinct bin
-// among the active lanes one lane reserves room for all of them with a single
-// atomic and each lane takes its rank among them.
+// One thread per face appends the face to every bin of its range.  The
+// workgroup's 256 consecutive faces (usually neighbours on the mesh, sharing
+// bins) first count their appends per distinct bin in an LDS hash table; one
+// global atomic per distinct bin then reserves room for all of the
+// workgroup's appends to it, and a second walk over the ranges hands out the
+// positions.  An append whose bin finds the table full reserves its own
+// position with a global atomic.
+constexpr int kBinHash = 1024;  // LDS hash entries of the binning workgroup
+__device__ __forceinline__ uint32_t bin_hash(int64_t b) {
+    return ((uint32_t)b * 2654435761u ^ (uint32_t)(b >> 32)) >> (32 - 10);
+}
+static_assert(kBinHash == 1024, "bin_hash yields 10 bits");
+
 __global__ __launch_bounds__(256) void bin_faces_kernel(const FaceRec* __restrict__ recs, int64_t F, int H, int W,
                                                         int bs, int nby, int nbx, int M, int* __restrict__ counts,
                                                         int* __restrict__ lists) {
+    __shared__ unsigned long long hkey[kBinHash];  // bin + 1 (0: empty)
+    __shared__ int hcnt[kBinHash];   // appends per bin, then the next rank to hand out
+    __shared__ int hbase[kBinHash];  // the workgroup's reserved start in the bin
+    for (int i = threadIdx.x; i < kBinHash; i += blockDim.x) {
+        hkey[i] = 0ull;
+        hcnt[i] = 0;
+    }
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
     int n = 0, bx0 = 0, by0 = 0, nbw = 1, nb = 0;
     if (f < F) {
-        FaceRec R = recs[f];
+        const FaceRec& R = recs[f];
         int bx1, by1;
-        if (face_bins(R, H, W, bs, bx0, bx1, by0, by1)) {
+        if (R.ok() && face_bins_of_box(R.bb, H, W, bs, bx0, bx1, by0, by1)) {
             n = R.mesh();
             nbw = bx1 - bx0 + 1;
             nb = nbw * (by1 - by0 + 1);
         }
     }
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int i = 0;; ++i) {
-        const bool act = i < nb;
-        uint64_t pending = __ballot(act);
-        if (pending == 0) break;
-        int64_t bin = -1;
-        if (act) bin = ((int64_t)n * nby + by0 + i / nbw) * nbx + bx0 + i % nbw;
-        while (pending) {
-            const int leader = __ffsll((unsigned long long)pending) - 1;
-            const int64_t lb = __shfl(bin, leader);
-            const uint64_t same = __ballot(act && bin == lb);
-            int base = 0;
-            if (lane == leader) base = atomicAdd(&counts[lb], __popcll(same));
-            base = __shfl(base, leader);
-            if (act && bin == lb) {
-                const int pos = base + __popcll(same & lt_mask);
-                if (lists != nullptr && pos < M) lists[lb * M + pos] = (int)f;
+    __syncthreads();
+    // 1. count per distinct bin
+    {
+        int ri = 0, rj = 0;
+        for (int i = 0; i < nb; ++i) {
+            const long long bin = ((int64_t)n * nby + by0 + ri) * nbx + bx0 + rj;
+            if (++rj == nbw) {
+                rj = 0;
+                ++ri;
             }
-            pending &= ~same;
+            const unsigned long long key = (unsigned long long)bin + 1ull;
+            uint32_t h = bin_hash(bin);
+            for (int probe = 0; probe < kBinHash; ++probe) {
+                const unsigned long long prev = atomicCAS(&hkey[h], 0ull, key);
+                if (prev == 0ull || prev == key) {
+                    atomicAdd(&hcnt[h], 1);
+                    break;
+                }
+                h = (h + 1) & (kBinHash - 1);
+            }
+        }
+    }
+    __syncthreads();
+    // 2. one reservation per distinct bin
+    for (int i = threadIdx.x; i < kBinHash; i += blockDim.x) {
+        const unsigned long long key = hkey[i];
+        if (key != 0ull) {
+            hbase[i] = atomicAdd(&counts[key - 1], hcnt[i]);
+            hcnt[i] = 0;
+        }
+    }
+    __syncthreads();
+    // 3. positions
+    {
+        int ri = 0, rj = 0;
+        for (int i = 0; i < nb; ++i) {
+            const long long bin = ((int64_t)n * nby + by0 + ri) * nbx + bx0 + rj;
+            if (++rj == nbw) {
+                rj = 0;
+                ++ri;
+            }
+            const unsigned long long want = (unsigned long long)bin + 1ull;
+            uint32_t h = bin_hash(bin);
+            int pos = -1;
+            for (int probe = 0; probe < kBinHash; ++probe) {
+                const unsigned long long key = hkey[h];
+                if (key == want) {
+                    pos = hbase[h] + atomicAdd(&hcnt[h], 1);
+                    break;
+                }
+                if (key == 0ull) break;
+                h = (h + 1) & (kBinHash - 1);
+            }
+            if (pos < 0) pos = atomicAdd(&counts[bin], 1);  // (the table was full)
+            if (lists != nullptr && pos < M) lists[bin * M + pos] = (int)f;
         }
     }
 }

@@ -52,7 +52,7 @@ def test_autotune_choice_is_cached_per_signature(monkeypatch):
     def no_timing(*a, **k):
         raise AssertionError("the cached choice was not used")
 
-    monkeypatch.setattr(autotune, "_time_candidate", no_timing)
+    monkeypatch.setattr(autotune, "_time_step", no_timing)
     assert autotune.autotune(v, f, fi, nf, H, W, b.blur_radius, K) is ch
     # moved vertices with the same statistics share the signature (the recount covers them)
     assert autotune.autotune(v * 0.5, f, fi, nf, H, W, b.blur_radius, K) is ch
