@@ -2,8 +2,8 @@
 //
 //   face_setup      one thread per face: mesh id, 112-byte record, padded bbox
 //   bin_faces       one thread per face: append the face to every bin its bbox
-//                   touches (counting only when lists == nullptr)
-//   bin_max         largest bin count -> workspace header, overflow flag
+//                   touches (counting only when lists == nullptr); largest bin
+//                   count -> workspace header, overflow flag
 //   raster_tiles    one wave per 8x8 pixel tile: loop over candidate faces
 //                   (all faces of the tile's mesh, or the tile's bin list),
 //                   cull per tile, test per pixel, keep the K nearest in
@@ -76,10 +76,14 @@ hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
     return hipGetLastError();
 }
 
-__global__ void face_setup_kernel(const float* __restrict__ verts, int64_t V, const int32_t* __restrict__ faces,
-                                  int64_t F, const int64_t* __restrict__ first, const int64_t* __restrict__ nf, int N,
-                                  float rb, int opts, FaceRec* __restrict__ recs, int* __restrict__ hdr) {
-    int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void face_setup_kernel(const float* __restrict__ verts, int64_t V,
+                                                         const int32_t* __restrict__ faces, int64_t F,
+                                                         const int64_t* __restrict__ first,
+                                                         const int64_t* __restrict__ nf, int N, float rb, int opts,
+                                                         FaceRec* __restrict__ recs, int* __restrict__ hdr) {
+    __shared__ FaceRec srec[256];
+    const int64_t f0 = (int64_t)blockIdx.x * blockDim.x;
+    int64_t f = f0 + threadIdx.x;
     if (first != nullptr && f < N) {
         // mesh range check: inside [0, F] and ascending without overlap
         int64_t a = first[f], c = nf[f];
@@ -87,23 +91,32 @@ __global__ void face_setup_kernel(const float* __restrict__ verts, int64_t V, co
         if (f > 0) bad = bad || a < first[f - 1] + nf[f - 1];
         if (bad) atomicOr(&hdr[kHdrStatus], kStatMesh);
     }
-    if (f >= F) return;
-    int mesh = first != nullptr ? find_mesh(first, nf, N, f) : 0;
-    int i0 = faces[3 * f + 0], i1 = faces[3 * f + 1], i2 = faces[3 * f + 2];
-    bool idx_ok = i0 >= 0 && i0 < V && i1 >= 0 && i1 < V && i2 >= 0 && i2 < V;
-    if (!idx_ok) {
-        atomicOr(&hdr[kHdrStatus], kStatMesh);
-        mesh = -1;
-        i0 = i1 = i2 = 0;
+    if (f0 >= F) return;  // (uniform over the workgroup)
+    if (f < F) {
+        int mesh = first != nullptr ? find_mesh(first, nf, N, f) : 0;
+        int i0 = faces[3 * f + 0], i1 = faces[3 * f + 1], i2 = faces[3 * f + 2];
+        bool idx_ok = i0 >= 0 && i0 < V && i1 >= 0 && i1 < V && i2 >= 0 && i2 < V;
+        if (!idx_ok) {
+            atomicOr(&hdr[kHdrStatus], kStatMesh);
+            mesh = -1;
+            i0 = i1 = i2 = 0;
+        }
+        if (V == 0) {
+            srec[threadIdx.x] = make_rec(0, 0, 0, 0, 0, 0, 0, 0, 0, rb, -1);
+        } else {
+            const float* a = verts + 3 * (int64_t)i0;
+            const float* b = verts + 3 * (int64_t)i1;
+            const float* c = verts + 3 * (int64_t)i2;
+            srec[threadIdx.x] = make_rec(a[0], a[1], a[2], b[0], b[1], b[2], c[0], c[1], c[2], rb, mesh, opts);
+        }
     }
-    if (V == 0) {
-        recs[f] = make_rec(0, 0, 0, 0, 0, 0, 0, 0, 0, rb, -1);
-        return;
-    }
-    const float* a = verts + 3 * (int64_t)i0;
-    const float* b = verts + 3 * (int64_t)i1;
-    const float* c = verts + 3 * (int64_t)i2;
-    recs[f] = make_rec(a[0], a[1], a[2], b[0], b[1], b[2], c[0], c[1], c[2], rb, mesh, opts);
+    __syncthreads();
+    // the workgroup's records are contiguous: coalesced 16-byte stores
+    const int n = (int)min((int64_t)blockDim.x, F - f0);
+    const float4* src = reinterpret_cast<const float4*>(srec);
+    float4* dst = reinterpret_cast<float4*>(recs + f0);
+    constexpr int W4 = sizeof(FaceRec) / sizeof(float4);
+    for (int i = threadIdx.x; i < n * W4; i += blockDim.x) dst[i] = src[i];
 }
 
 hipError_t launch_face_setup(const float* verts, int64_t V, const int32_t* faces, int64_t F, const int64_t* first,
@@ -121,7 +134,10 @@ hipError_t launch_face_setup(const float* verts, int64_t V, const int32_t* faces
 // global atomic per distinct bin then reserves room for all of the
 // workgroup's appends to it, and a second walk over the ranges hands out the
 // positions.  An append whose bin finds the table full reserves its own
-// position with a global atomic.
+// position with a global atomic.  The workgroup also records the largest
+// count it leaves in any of its bins (the last reservation in a bin ends at
+// its final count, so the maximum over workgroups is the largest bin count)
+// and flags a count above the capacity M.
 constexpr int kBinHash = 1024;  // LDS hash entries of the binning workgroup
 __device__ __forceinline__ uint32_t bin_hash(int64_t b) {
     return ((uint32_t)b * 2654435761u ^ (uint32_t)(b >> 32)) >> (32 - 10);
@@ -130,8 +146,9 @@ static_assert(kBinHash == 1024, "bin_hash yields 10 bits");
 
 __global__ __launch_bounds__(256) void bin_faces_kernel(const FaceRec* __restrict__ recs, int64_t F, int H, int W,
                                                         int bs, int nby, int nbx, int M, int* __restrict__ counts,
-                                                        int* __restrict__ lists) {
+                                                        int* __restrict__ lists, int* __restrict__ hdr) {
     __shared__ unsigned long long hkey[kBinHash];  // bin + 1 (0: empty)
+    __shared__ int wmax[4];
     __shared__ int hcnt[kBinHash];   // appends per bin, then the next rank to hand out
     __shared__ int hbase[kBinHash];  // the workgroup's reserved start in the bin
     for (int i = threadIdx.x; i < kBinHash; i += blockDim.x) {
@@ -173,10 +190,12 @@ __global__ __launch_bounds__(256) void bin_faces_kernel(const FaceRec* __restric
     }
     __syncthreads();
     // 2. one reservation per distinct bin
+    int top = 0;  // largest count this thread leaves in a bin
     for (int i = threadIdx.x; i < kBinHash; i += blockDim.x) {
         const unsigned long long key = hkey[i];
         if (key != 0ull) {
             hbase[i] = atomicAdd(&counts[key - 1], hcnt[i]);
+            top = max(top, hbase[i] + hcnt[i]);
             hcnt[i] = 0;
         }
     }
@@ -202,22 +221,23 @@ __global__ __launch_bounds__(256) void bin_faces_kernel(const FaceRec* __restric
                 if (key == 0ull) break;
                 h = (h + 1) & (kBinHash - 1);
             }
-            if (pos < 0) pos = atomicAdd(&counts[bin], 1);  // (the table was full)
+            if (pos < 0) {
+                pos = atomicAdd(&counts[bin], 1);  // (the table was full)
+                top = max(top, pos + 1);
+            }
             if (lists != nullptr && pos < M) lists[bin * M + pos] = (int)f;
         }
     }
-}
-
-__global__ void bin_max_kernel(const int* __restrict__ counts, int64_t nbins, int M, int* __restrict__ hdr) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int m = 0;
-    for (; i < nbins; i += stride) m = max(m, counts[i]);
-    // wave reduction, then one atomic per wave
-    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
-    if ((threadIdx.x & 63) == 0) {
-        atomicMax(&hdr[kHdrMaxCount], m);
-        if (M > 0 && m > M) atomicOr(&hdr[kHdrStatus], kStatOverflow);
+    // the workgroup's largest count: one word per wave, then one read and, only
+    // if larger, one atomic per workgroup (same-address atomics serialise)
+    for (int o = 32; o > 0; o >>= 1) top = max(top, __shfl_xor(top, o));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = top;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) top = max(top, wmax[w]);
+        if (top > __hip_atomic_load(&hdr[kHdrMaxCount], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&hdr[kHdrMaxCount], top);
+        if (M > 0 && top > M) atomicOr(&hdr[kHdrStatus], kStatOverflow);
     }
 }
 
@@ -229,11 +249,8 @@ hipError_t launch_binning(const FaceRec* recs, int64_t F, int N, int H, int W, i
     if (e != hipSuccess) return e;
     if (F > 0) {
         hipLaunchKernelGGL(bin_faces_kernel, dim3((unsigned)((F + 255) / 256)), dim3(256), 0, s, recs, F, H, W, bs, nby,
-                           nbx, M, counts, lists);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
+                           nbx, M, counts, lists, hdr);
     }
-    hipLaunchKernelGGL(bin_max_kernel, dim3(grid_for(nbins, 256)), dim3(256), 0, s, counts, nbins, M, hdr);
     return hipGetLastError();
 }
 
