@@ -280,11 +280,8 @@ struct FineArgs {
 };
 
 // LDS of one tile's wave: a chunk of up to 64 candidate faces that overlap the
-// tile, and per lane the indices (within the chunk) of the faces whose boxes
-// contain the lane's pixel.  The gather gives every lane one list entry, so a
-// chunk is exactly one wave wide.  The per-lane lists are bytes: a smaller LDS
-// block lets more tile waves share a CU, and the fine pass is latency-bound
-// enough for that to pay (measured).
+// tile (the gather gives every lane one list entry, so a chunk is exactly one
+// wave wide), and the room the write-out staging needs beyond them.
 constexpr int kChunk = tile_layout::kChunk;
 
 // A face as the tile pass keeps it in LDS: the geometry the pixel tests read
@@ -302,7 +299,7 @@ static_assert(sizeof(TileRec) == tile_layout::kTileRecBytes, "tile record layout
 
 struct TileLds {
     TileRec rec[kChunk];
-    unsigned char lst[tile_layout::kListBytes];  // entry i of lane l at [i * 64 + l]
+    unsigned char spare[tile_layout::kSpareBytes];  // (staging of the write-out)
 };
 static_assert(sizeof(TileLds) == tile_layout::kLdsBytes, "tile LDS layout");
 
@@ -477,14 +474,34 @@ __device__ __forceinline__ void write_fragments(const FineArgs& a, TileLds& L, c
     }
 }
 
+// Transpose of the 64x64 bit matrix whose row i is lane i's word: bit i of
+// lane p's result is bit p of lane i's word.  Six butterfly stages: at stage
+// j the lanes i and i ^ j exchange the off-diagonal j x j blocks of their
+// 2j x 2j block (the lane with bit j clear keeps its low groups of j bits
+// and takes the partner's low groups into its high ones, the other keeps its
+// high groups and takes the partner's high groups into its low ones).
+__device__ __forceinline__ uint64_t transpose64(uint64_t x, int lane) {
+    constexpr uint64_t kLow[6] = {0x5555555555555555ull, 0x3333333333333333ull, 0x0f0f0f0f0f0f0f0full,
+                                  0x00ff00ff00ff00ffull, 0x0000ffff0000ffffull, 0x00000000ffffffffull};
+#pragma unroll
+    for (int s = 5; s >= 0; --s) {
+        const int j = 1 << s;
+        const uint64_t m = kLow[s];
+        const uint64_t y = __shfl_xor(x, j);
+        x = (lane & j) ? ((x & ~m) | ((y & ~m) >> j)) : ((x & m) | ((y & m) << j));
+    }
+    return x;
+}
+
 // One wave rasterizes one 8x8 tile in three steps per chunk of 64 faces:
-//  1. gather the chunk's face records, keep those whose box overlaps the tile
-//     (wave ballot + prefix count compacts them into LDS);
-//  2. every lane tests its pixel against each kept face's box (a broadcast
-//     LDS read) and appends the hits to its own list;
-//  3. every lane walks only its own list, runs the full test and inserts the
-//     faces that count into its register top-K.
-// Step 3 is where the arithmetic is; compacting the (pixel, face) pairs first
+//  1. gather the chunk's face records, keep those whose box (narrowed by the
+//     edge lines) may cover a pixel of the tile (wave ballot + prefix count
+//     compacts them into LDS), each with its 64-bit mask of such pixels;
+//  2. transpose the kept faces' masks across the wave (lane j holds record
+//     j's mask), so that lane p holds the chunk's faces that may cover pixel p;
+//  3. every lane walks only its own faces, runs the full test and inserts
+//     the faces that count into its register top-K.
+// Step 3 is where the arithmetic is; gathering each pixel's candidates first
 // keeps lanes from idling on faces that miss their pixel.
 template <int KB, bool BINNED, bool EXACT, bool OPT>
 __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n, int tx, int ty) {
@@ -520,7 +537,6 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
         base = lo;
         cnt = hi > lo ? hi - lo : 0;
     }
-    unsigned char* mylst = L.lst + lane;
     for (int64_t c0 = 0; c0 < cnt; c0 += kChunk) {
         // 1. gather and compact the chunk's faces that overlap the tile
         const int64_t e = c0 + lane;
@@ -553,10 +569,12 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
                                   __uint_as_float((uint32_t)(pm >> 32)));  // il2, id, mask
         }
         __syncthreads();
-        // 2. per-lane lists of the faces whose boxes may contain the lane's pixel
-        int nl = 0;
-        for (int j = 0; j < m; ++j)
-            if ((L.rec[j].mask >> lane) & 1ull) mylst[64 * nl++] = (unsigned char)j;
+        // 2. per lane, the faces whose boxes may contain the lane's pixel: lane
+        //    j holds kept face j's pixel mask (row j of a 64x64 bit matrix);
+        //    the transpose gives lane p the faces of pixel p
+        uint64_t mine = lane < m ? L.rec[lane].mask : 0ull;
+        mine = transpose64(mine, lane);
+        const int nl = __popcll(mine);
         // 3. full test of the lane's own candidates, eight per round; the
         //    round count is the wave's longest list, so the loop is uniform
         //    and the queue stays in place across rounds
@@ -566,8 +584,9 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 uint64_t key = kEmptyKey;
-                if (i0 + u < nl) {
-                    const int j = mylst[64 * (i0 + u)];
+                if (mine != 0ull) {
+                    const int j = __ffsll((unsigned long long)mine) - 1;
+                    mine &= mine - 1;
                     float z;
                     if (face_counts_in_box(L.rec[j], p, a.blur, z, OPT ? a.opts : 0)) key = make_key(z, L.rec[j].fid);
                 }

@@ -3,12 +3,14 @@
 //
 // The model replays, for every lane of the wave, the offsets the tile pass
 // computes into its LDS block -- the compaction of a chunk's face records
-// (a lane's rank among the lanes that keep a face), the per-lane byte lists
-// (entry i of lane l at byte i * 64 + l), the records read back through those
-// lists, and the staging offsets of the fragment write-out for every queue
-// size -- against the block sizes of tile_layout.hpp, which the kernel uses
-// as well.  Every access goes through a checked accessor; the program is
-// built with AddressSanitizer and UndefinedBehaviorSanitizer.
+// (a lane's rank among the lanes that keep a face), lane j's read of record
+// j's pixel mask, the bit transpose across the wave (the same six butterfly
+// stages as the kernel's), the records read back through the bits of every
+// lane's word, and the staging offsets of the fragment write-out for every
+// queue size -- against the block sizes of tile_layout.hpp, which the kernel
+// uses as well.  The transpose is also checked against its definition.
+// Every access goes through a checked accessor; the program is built with
+// AddressSanitizer and UndefinedBehaviorSanitizer.
 //
 //   tile_lds_model [chunk]   chunk: faces per chunk (default: the kernel's);
 //                            a chunk narrower than the wave shows what goes
@@ -27,12 +29,25 @@ namespace tl = rast::tile_layout;
 struct Block {
     int chunk;           // records in the block
     size_t rec_bytes;    // chunk * kTileRecBytes
-    size_t list_bytes;   // chunk * kLanes
     std::vector<unsigned char> mem;
+    std::vector<uint64_t> mask;  // each record's pixel mask (a field of the record)
     explicit Block(int c)
-        : chunk(c), rec_bytes((size_t)c * tl::kTileRecBytes), list_bytes((size_t)c * tl::kLanes),
-          mem(rec_bytes + list_bytes) {}
+        : chunk(c), rec_bytes((size_t)c * tl::kTileRecBytes), mem(rec_bytes + tl::kSpareBytes), mask(c) {}
 };
+
+// The kernel's transpose: row i of the 64x64 bit matrix in lane i.
+static void transpose64(uint64_t (&x)[tl::kLanes]) {
+    static const uint64_t kLow[6] = {0x5555555555555555ull, 0x3333333333333333ull, 0x0f0f0f0f0f0f0f0full,
+                                     0x00ff00ff00ff00ffull, 0x0000ffff0000ffffull, 0x00000000ffffffffull};
+    for (int s = 5; s >= 0; --s) {
+        const int j = 1 << s;
+        const uint64_t m = kLow[s];
+        uint64_t y[tl::kLanes];
+        for (int l = 0; l < tl::kLanes; ++l) y[l] = x[l ^ j];
+        for (int l = 0; l < tl::kLanes; ++l)
+            x[l] = (l & j) ? ((x[l] & ~m) | ((y[l] & ~m) >> j)) : ((x[l] & m) | ((y[l] & m) << j));
+    }
+}
 
 static int fail(const char* what, long long idx, long long limit, int lane) {
     std::printf("OUT OF BOUNDS: %s index %lld, limit %lld (lane %d)\n", what, idx, limit, lane);
@@ -59,25 +74,32 @@ static int chunk_pass(Block& B, long long c0, long long cnt, std::mt19937_64& rn
         B.mem.at(off) = (unsigned char)dst;  // first byte of the record
     }
     const int m = __builtin_popcountll(kept);
-    // 2. per-lane byte lists of the kept faces whose boxes cover the lane's pixel
-    std::vector<std::vector<int>> cov(m, std::vector<int>(tl::kLanes));
-    for (int j = 0; j < m; ++j)
-        for (int lane = 0; lane < tl::kLanes; ++lane) cov[j][lane] = cov_d(rng);
-    std::vector<int> nl(tl::kLanes, 0);
-    for (int lane = 0; lane < tl::kLanes; ++lane) {
-        for (int j = 0; j < m; ++j) {
-            if (!cov[j][lane]) continue;
-            const long long off = (long long)tl::kLanes * nl[lane] + lane;
-            if (off >= (long long)B.list_bytes) return fail("lane list", off, (long long)B.list_bytes, lane);
-            B.mem.at(B.rec_bytes + (size_t)off) = (unsigned char)j;
-            ++nl[lane];
-        }
+    // 2. lane j < m reads record j's pixel mask; the transpose hands lane p
+    //    the faces whose masks hold pixel p
+    uint64_t row[tl::kLanes], word[tl::kLanes];
+    for (int j = 0; j < m; ++j) {
+        uint64_t mk = 0;
+        for (int lane = 0; lane < tl::kLanes; ++lane)
+            if (cov_d(rng)) mk |= 1ull << lane;
+        if (j >= B.chunk) return fail("record mask", j, B.chunk, j);
+        B.mask.at(j) = mk;
     }
-    // 3. read back: every list entry names a record of this chunk
     for (int lane = 0; lane < tl::kLanes; ++lane) {
-        for (int i = 0; i < nl[lane]; ++i) {
-            const int j = B.mem.at(B.rec_bytes + (size_t)tl::kLanes * i + lane);
-            if (j >= m) return fail("record named by a list", j, m, lane);
+        if (lane < m && lane >= B.chunk) return fail("record mask read", lane, B.chunk, lane);
+        row[lane] = word[lane] = lane < m ? B.mask.at(lane) : 0ull;
+    }
+    transpose64(word);
+    // 3. read back: every bit of a lane's word names a record of this chunk,
+    //    and the words are the transpose of the rows
+    for (int lane = 0; lane < tl::kLanes; ++lane) {
+        for (int i = 0; i < tl::kLanes; ++i) {
+            const bool bit = (word[lane] >> i) & 1ull;
+            if (bit != (bool)((row[i] >> lane) & 1ull)) {
+                std::printf("TRANSPOSE: lane %d bit %d\n", lane, i);
+                return 1;
+            }
+            if (bit && i >= m) return fail("record named by a lane's word", i, m, lane);
+            if (bit) (void)B.mem.at((size_t)i * tl::kTileRecBytes);  // the record the test reads
         }
     }
     return 0;
