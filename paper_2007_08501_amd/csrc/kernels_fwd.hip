@@ -134,11 +134,16 @@ hipError_t launch_face_setup(const float* verts, int64_t V, const int32_t* faces
 // global atomic per distinct bin then reserves room for all of the
 // workgroup's appends to it, and a second walk over the ranges hands out the
 // positions.  An append whose bin finds the table full reserves its own
-// position with a global atomic.  The workgroup also records the largest
+// position with a global atomic, and so does one whose bin is not within
+// kBinProbe slots of its hash position (both walks probe the same slots, so
+// they agree on which bins the table holds): a workgroup of large faces,
+// touching thousands of bins, then costs at most kBinProbe probes per
+// append.  The workgroup also records the largest
 // count it leaves in any of its bins (the last reservation in a bin ends at
 // its final count, so the maximum over workgroups is the largest bin count)
 // and flags a count above the capacity M.
 constexpr int kBinHash = 1024;  // LDS hash entries of the binning workgroup
+constexpr int kBinProbe = 32;   // slots probed per append
 __device__ __forceinline__ uint32_t bin_hash(int64_t b) {
     return ((uint32_t)b * 2654435761u ^ (uint32_t)(b >> 32)) >> (32 - 10);
 }
@@ -178,7 +183,7 @@ __global__ __launch_bounds__(256) void bin_faces_kernel(const FaceRec* __restric
             }
             const unsigned long long key = (unsigned long long)bin + 1ull;
             uint32_t h = bin_hash(bin);
-            for (int probe = 0; probe < kBinHash; ++probe) {
+            for (int probe = 0; probe < kBinProbe; ++probe) {
                 const unsigned long long prev = atomicCAS(&hkey[h], 0ull, key);
                 if (prev == 0ull || prev == key) {
                     atomicAdd(&hcnt[h], 1);
@@ -212,7 +217,7 @@ __global__ __launch_bounds__(256) void bin_faces_kernel(const FaceRec* __restric
             const unsigned long long want = (unsigned long long)bin + 1ull;
             uint32_t h = bin_hash(bin);
             int pos = -1;
-            for (int probe = 0; probe < kBinHash; ++probe) {
+            for (int probe = 0; probe < kBinProbe; ++probe) {
                 const unsigned long long key = hkey[h];
                 if (key == want) {
                     pos = hbase[h] + atomicAdd(&hcnt[h], 1);
@@ -222,7 +227,7 @@ __global__ __launch_bounds__(256) void bin_faces_kernel(const FaceRec* __restric
                 h = (h + 1) & (kBinHash - 1);
             }
             if (pos < 0) {
-                pos = atomicAdd(&counts[bin], 1);  // (the table was full)
+                pos = atomicAdd(&counts[bin], 1);  // (not in the table)
                 top = max(top, pos + 1);
             }
             if (lists != nullptr && pos < M) lists[bin * M + pos] = (int)f;
