@@ -447,6 +447,21 @@ struct TopK {
     }
 };
 
+// Work item of workgroup L of a T-workgroup grid, such that every XCD works
+// through one contiguous range of the items.  The hardware hands workgroups
+// to the chip's kXcds XCDs in turn (L to XCD L mod kXcds, the (L / kXcds)-th
+// there); each XCD has its own L2, so neighbouring items, which share their
+// input (a tile's faces are mostly its neighbours' faces too), hit in one L2
+// instead of being spread over all of them.  A bijection of [0, T): XCD x
+// takes items [x q + min(x, r), (x + 1) q + min(x + 1, r)) with q = T / kXcds,
+// r = T mod kXcds.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_item(int64_t L, int64_t T) {
+    const int64_t q = T / kXcds, r = T - q * kXcds;
+    const int64_t x = L % kXcds, k = L / kXcds;
+    return x * q + (x < r ? x : r) + k;
+}
+
 // Largest value of v over the wave.
 __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll

@@ -643,9 +643,10 @@ void bwd_bins_kernel(BwdArgs a, int rescue) {
     const int per_img = a.nby * a.nbx;
     const int64_t nbins = (int64_t)a.N * per_img;
     // kLoop: a grid smaller than the bin count (the rescue launch) walks the
-    // bins; otherwise the grid is one workgroup per bin (either way
-    // blockIdx.x < nbins)
-    int64_t bin = blockIdx.x;
+    // bins; otherwise the grid is one workgroup per bin, each XCD taking a
+    // contiguous range of bins (neighbouring bins gather mostly the same
+    // face records; xcd_item).  Either way the first bin is < nbins.
+    int64_t bin = kLoop ? (int64_t)blockIdx.x : xcd_item(blockIdx.x, nbins);
     do {
         const int n = (int)(bin / per_img);
         const int rem = (int)(bin - (int64_t)n * per_img);

@@ -605,10 +605,18 @@ __device__ __forceinline__ void raster_tile(const FineArgs& a, TileLds& L, int n
 }
 
 // EXACT: faces_per_pixel equals the queue size KB (chosen at launch).
+// The grid's workgroups are taken as tiles in image-major raster order, each
+// XCD a contiguous range of them (xcd_item).
 template <int KB, bool BINNED, bool EXACT, bool OPT>
 __global__ __launch_bounds__(64) void raster_tiles_kernel(FineArgs a) {
     __shared__ TileLds L;
-    raster_tile<KB, BINNED, EXACT, OPT>(a, L, blockIdx.z, blockIdx.x, blockIdx.y);
+    const int64_t per_img = (int64_t)a.tiles_x * a.tiles_y;
+    const int64_t wg = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+    const int64_t t = xcd_item(wg, per_img * a.N);
+    const int n = (int)(t / per_img);
+    const int rem = (int)(t - n * per_img);
+    const int ty = rem / a.tiles_x;
+    raster_tile<KB, BINNED, EXACT, OPT>(a, L, n, rem - ty * a.tiles_x, ty);
 }
 
 // Persistent form: a device-sized grid; each wave pulls the next tile id from
