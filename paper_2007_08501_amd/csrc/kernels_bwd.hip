@@ -914,14 +914,29 @@ __global__ __launch_bounds__(kBwdBlock) void bwd_face_sum_kernel(BwdArgs a) {
     }
 }
 
+// Zeroes grad_verts (n3v floats) and the row masks (nmask words), and the
+// recorded largest face sum.
+__global__ void bwd_prep_kernel(float* __restrict__ grad, int64_t n3v, int* __restrict__ mask, int64_t nmask,
+                                int* __restrict__ term) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = i0; i < n3v; i += stride) grad[i] = 0.0f;
+    for (int64_t i = i0; i < nmask; i += stride) mask[i] = 0;
+    if (i0 == 0) *term = 0;
+}
+
 hipError_t launch_backward(const float* verts, int64_t V, const int32_t* faces, int64_t F, const int64_t* first,
                            const int64_t* nf, int N, int H, int W, int K, float blur, int opts, int bs, int M,
                            const int32_t* p2f, const float* gz, const float* gb, const float* gd, float* grad,
                            int* hdr, FaceRec* recs, int* counts, int* lists, float* partial, int* big,
                            bool reuse, const BinSig& sig, hipStream_t s, hipEvent_t eb, hipEvent_t ee) {
     reuse = reuse && bs > 0;
-    hipError_t e = launch_fill_f32(grad, V * 3, 0.0f, s);
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    // the binned form clears grad_verts together with its row masks (below)
+    if (bs == 0 || F == 0) {
+        e = launch_fill_f32(grad, V * 3, 0.0f, s);
+        if (e != hipSuccess) return e;
+    }
     if (!reuse) {
         e = launch_fill_i32(hdr, kHdrWords, 0, s);
         if (e != hipSuccess) return e;
@@ -968,11 +983,9 @@ hipError_t launch_backward(const float* verts, int64_t V, const int32_t* faces, 
             if (e != hipSuccess) return e;
         }
         const int64_t nbins = (int64_t)N * a.nby * a.nbx;
-        e = launch_fill_i32(hdr + kHdrTermMax, 1, 0, s);
-        if (e != hipSuccess) return e;
-        // no partial row is written yet (F x 4 mask bytes = F words)
-        e = launch_fill_i32(big, F, 0, s);
-        if (e != hipSuccess) return e;
+        // grad_verts, the row masks (no partial row is written yet: F x 4 mask
+        // bytes = F words) and the recorded largest sum, in one launch
+        hipLaunchKernelGGL(bwd_prep_kernel, dim3(1024), dim3(256), 0, s, grad, V * 3, big, F, hdr + kHdrTermMax);
         if (eb) (void)hipEventRecord(eb, s);
         const bool o = (opts & (kOptPersp | kOptClip)) != 0;
         auto bins = o ? bwd_bins_kernel<true, false> : bwd_bins_kernel<false, false>;
