@@ -299,6 +299,34 @@ def test_autograd_matches_abi():
     torch.testing.assert_close(vv.grad, direct, rtol=0, atol=1e-5 * scale)
 
 
+def test_binning_large_faces_past_the_hash_table():
+    """600 large triangles over a 256x256 image in 8-pixel bins: a binning
+    workgroup's 256 faces touch more distinct bins than its LDS table holds,
+    so appends take the direct global path; the binned forward still equals
+    the single-pass one bitwise, the recorded largest count is exact (it
+    fits as the capacity, one less overflows)."""
+    rng = np.random.default_rng(7)
+    F = 600
+    c = rng.uniform(-0.8, 0.8, (F, 1, 2))
+    xy = (c + rng.normal(0, 0.35, (F, 3, 2))).reshape(-1, 2)
+    v = np.concatenate([xy, rng.uniform(1, 5, (3 * F, 1))], 1).astype(np.float32)
+    b = meshgen.Batch(name="large", verts=v, faces=np.arange(3 * F, dtype=np.int32).reshape(F, 3),
+                      first_idx=np.array([0]), num_faces=np.array([F]), verts_first_idx=np.array([0]),
+                      num_verts=np.array([3 * F]), image_size=(256, 256), faces_per_pixel=8, blur_radius=1e-4,
+                      bin_size=8, max_faces_per_bin=None)
+    d = to_dev(b)
+    naive, _ = run_fwd(b, 0, dev_inputs=d)
+    mx = bin_capacity(b, 8, d)
+    log("largest bin count", mx)
+    assert mx > 100
+    binned, _ = run_fwd(b, 8, M=mx, dev_inputs=d)
+    for x, y in zip(naive, binned):
+        assert torch.equal(x, y)
+    _, ws = run_fwd(b, 8, M=mx - 1, dev_inputs=d, check=False)
+    st, got = _lib.rast_query_status(ws)
+    assert st == _lib.RAST_EOVERFLOW and got == mx, (_lib.status_string(st), got, mx)
+
+
 # ----------------------------------------------------------------- edge cases
 
 def test_empty_and_offscreen_meshes():
