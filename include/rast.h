@@ -172,7 +172,10 @@ int rasterize_meshes_fwd_static(const float* verts_packed, int64_t V, const int3
  *   pix_to_face must come from rasterize_meshes_fwd with the same vertices,
  *   faces, mesh ranges, image size and blur_radius; bin_size and
  *   max_faces_per_bin are the forward's (bin_size 0: the backward walks each
- *   face's pixel box; > 0: it re-bins the faces and streams each bin's slots).
+ *   face's pixel box; > 0: it streams each bin's slots once, gathering the
+ *   faces they name, with the forward's bins for crowded bins).  In the
+ *   binned form a slot id outside [0, F), or naming a face that never counts
+ *   or one of another image, contributes nothing.
  *   A bin overflow sets RAST_EOVERFLOW in the workspace status and leaves
  *   grad_verts incomplete.
  *   flags: the forward's options, or-ed with RAST_BWD_REUSE_FORWARD or not;
