@@ -405,10 +405,10 @@ __global__ __launch_bounds__(kBwdBlock) void bwd_big_faces_kernel(BwdArgs a) {
 // ---------------------------------------------------------------------------
 constexpr int kP1Threads = 256;
 constexpr int kP1Chunk = 160;    // faces staged in LDS per pass over a bin's slots
-static_assert(kP1Chunk <= 256, "chunk indices are kept as bytes");
+static_assert(kP1Chunk <= kP1Threads, "a chunk's faces are gathered one per thread");
 constexpr int kP1Table = 512;    // LDS hash entries (>= 2 * kP1Chunk)
 constexpr int kP1Unroll = 4;     // slots per thread in one group of the bin's slots
-constexpr int kP1Group = kP1Unroll * kP1Threads;  // slots looked up before the found ones are recomputed
+constexpr int kP1Group = kP1Unroll * kP1Threads;  // slots the workgroup holds at once
 constexpr int kMaxPartials = 4;  // (the row masks are read as one uchar4)
 
 __device__ __forceinline__ uint32_t fhash(int f) { return ((uint32_t)f * 2654435761u) >> (32 - 9); }

@@ -76,6 +76,11 @@ hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
     return hipGetLastError();
 }
 
+// One thread per face builds the face's record (make_rec: mesh id, exact FP64
+// edge vectors, grown box); the workgroup's 256 records are staged in LDS and
+// stored with coalesced 16-byte writes (a lane storing its own 112 bytes
+// leaves each store instruction scattered over 64 lines).  The threads below
+// N also check the mesh ranges.
 __global__ __launch_bounds__(256) void face_setup_kernel(const float* __restrict__ verts, int64_t V,
                                                          const int32_t* __restrict__ faces, int64_t F,
                                                          const int64_t* __restrict__ first,
