@@ -263,6 +263,40 @@ def test_backward_crowded_bins(F):
     compare_grad(g0, ref, f"crowded F={F} per face")
 
 
+@pytest.mark.parametrize("bs", [0, 8])
+def test_backward_ignores_slots_no_face_of_the_image_can_fill(bs):
+    """Slot ids the forward cannot produce -- out of [0, F), a face of
+    another image, a degenerate face -- contribute nothing: the gradient
+    equals the one with those slots emptied."""
+    b = meshgen.make_config(2, n_override=3, level_override=3, image_override=64)
+    v = b.verts.copy()
+    f = b.faces.copy()
+    dead = int(b.first_idx[0])  # face 0 of image 0 made degenerate (never counts)
+    f[dead, 1] = f[dead, 0]
+    f[dead, 2] = f[dead, 0]
+    b.verts, b.faces = v, f
+    d = to_dev(b)
+    out, _ = run_fwd(b, 8, dev_inputs=d)
+    p2f = out.pix_to_face.clone()
+    filled = (p2f >= 0).nonzero()
+    sel = filled[torch.randperm(filled.shape[0], generator=torch.Generator().manual_seed(3))[:600].to(p2f.device)]
+    F = b.faces.shape[0]
+    bad = torch.empty(sel.shape[0], dtype=torch.int32, device=p2f.device)
+    third = sel.shape[0] // 3
+    bad[:third] = F + 5                                                  # out of range
+    img = sel[third:2 * third, 0]                                       # a face of the next image
+    bad[third:2 * third] = torch.from_numpy(b.first_idx).to(p2f.device)[(img + 1) % 3].int()
+    bad[2 * third:] = dead                                              # the degenerate face
+    corrupt = p2f.clone()
+    corrupt[sel[:, 0], sel[:, 1], sel[:, 2], sel[:, 3]] = bad
+    clean = p2f.clone()
+    clean[sel[:, 0], sel[:, 1], sel[:, 2], sel[:, 3]] = -1
+    gz, gb, gd = [torch.from_numpy(x).cuda() for x in meshgen.upstream_grads(b)]
+    g_bad = run_bwd(b, corrupt, gz, gb, gd, dev_inputs=d, bs=bs)
+    g_ref = run_bwd(b, clean, gz, gb, gd, dev_inputs=d, bs=bs)
+    torch.testing.assert_close(g_bad, g_ref, rtol=0, atol=1e-6 * float(g_ref.abs().max()))
+
+
 def test_backward_hand_case():
     # triangle T, pixel (2,2) of a 4x4 image; hand-derived gradients
     v = np.array([[-1.0, -1.0, 1.0], [1.0, -1.0, 2.0], [-1.0, 1.0, 3.0]], np.float32)
