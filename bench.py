@@ -77,6 +77,11 @@ class HipEvents:
 
 # sources of each measured kernel: a counter summary holds for them only while
 # these files are unchanged
+# The VALU figure is an issue rate, not a roofline of useful work: every
+# counted wave instruction is taken as 64 lane slots, masked lanes included.
+VALU_ISSUE_WHAT = ("VALU issue rate of the dominant kernel: SQ_INSTS_VALU x 64 lane slots / kernel time, masked "
+                   "lanes included (not a count of useful lane operations)")
+
 KERNEL_SOURCES = {
     "fine": ["paper_2007_08501_amd/csrc/kernels_fwd.hip", "paper_2007_08501_amd/csrc/device.hpp"],
     "backward": ["paper_2007_08501_amd/csrc/kernels_bwd.hip", "paper_2007_08501_amd/csrc/device.hpp"],
@@ -413,8 +418,9 @@ def points_main(args):
     valu = measured_valu(dom, 0, K, 0, path=os.path.join(ROOT, "profiles", f"kernels_pts3_K{K}.txt"))
     if valu is not None:
         lane_ops = valu * 64 / (dom_ms * 1e-3)
-        roofline["valu"] = {"lane_ops_per_s": float(f"{lane_ops:.4g}"), "peak": VALU_PEAK_LANE_OPS,
-                            "frac": round(lane_ops / VALU_PEAK_LANE_OPS, 4), "wave_instructions": int(valu)}
+        roofline["valu_issue"] = {"lane_slots_per_s": float(f"{lane_ops:.4g}"), "peak": VALU_PEAK_LANE_OPS,
+                                  "frac": round(lane_ops / VALU_PEAK_LANE_OPS, 4), "wave_instructions": int(valu),
+                                  "what": VALU_ISSUE_WHAT}
     roofline["traffic"] = measured_traffic(dom, "pts3", K, 0, path=os.path.join(
         ROOT, "profiles", f"traffic_{dom}_pts3_K{K}.txt"))
     if args.copy_probe:
@@ -614,12 +620,13 @@ def main():
                 "traffic": measured_traffic(dom, args.config, K, bs), "kernel_ms": round(dom_ms, 5),
                 "algorithmic_bytes": dom_bytes}
     # the same kernel against the VALU issue rate: its counted VALU instructions
-    # (64 lanes each) over the live kernel time
+    # (64 lane slots each, masked lanes included) over the live kernel time
     valu = measured_valu(dom, args.config, K, bs)
     if valu is not None:
         lane_ops = valu * 64 / (dom_ms * 1e-3)
-        roofline["valu"] = {"lane_ops_per_s": float(f"{lane_ops:.4g}"), "peak": VALU_PEAK_LANE_OPS,
-                            "frac": round(lane_ops / VALU_PEAK_LANE_OPS, 4), "wave_instructions": int(valu)}
+        roofline["valu_issue"] = {"lane_slots_per_s": float(f"{lane_ops:.4g}"), "peak": VALU_PEAK_LANE_OPS,
+                                  "frac": round(lane_ops / VALU_PEAK_LANE_OPS, 4), "wave_instructions": int(valu),
+                                  "what": VALU_ISSUE_WHAT}
 
     # ---------------------------------------------------------------- per-mesh forms
     per_mesh = None
