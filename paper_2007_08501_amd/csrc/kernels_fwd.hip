@@ -330,6 +330,22 @@ constexpr int kStageG2 = tile_layout::kStageG2;  // slots per pass for barycentr
 // fragment, a wave-uniform base.
 // OPT: the rasterizer options that change barycentrics and depth are on
 // (a separate instantiation, so that the default path carries no test for them).
+// Non-temporal 16-byte stores (the "nt" hint: streamed past the caches).
+// The id and depth passes write whole lines (a tile row of either array is
+// 8 K contiguous words), so streaming them leaves L2 to the face records the
+// tile waves share; the barycentric and distance passes write part lines
+// per pass and are stored normally, so that L2 completes their lines.
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef int nt_i4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void nt_store(int4 v, int* p) {
+    const nt_i4 w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<nt_i4*>(p));
+}
+__device__ __forceinline__ void nt_store(float4 v, float* p) {
+    const nt_f4 w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<nt_f4*>(p));
+}
+
 template <int KB, bool EXACT, bool OPT>
 __device__ __forceinline__ void write_fragments(const FineArgs& a, TileLds& L, const TopK<KB>& top, const Pix& p,
                                                 int n, int tx, int ty) {
@@ -377,8 +393,8 @@ __device__ __forceinline__ void write_fragments(const FineArgs& a, TileLds& L, c
                         const int o = r * rowK + c * K + g0 + 4 * q;
                         const int* si = sid + px * S + 4 * q;
                         const float* zi = sz + px * S + 4 * q;
-                        *reinterpret_cast<int4*>(p2f_t + o) = make_int4(si[0], si[1], si[2], si[3]);
-                        *reinterpret_cast<float4*>(zbuf_t + o) = make_float4(zi[0], zi[1], zi[2], zi[3]);
+                        nt_store(make_int4(si[0], si[1], si[2], si[3]), p2f_t + o);
+                        nt_store(make_float4(zi[0], zi[1], zi[2], zi[3]), zbuf_t + o);
                     }
                 }
             } else {
