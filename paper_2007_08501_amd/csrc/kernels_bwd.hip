@@ -76,20 +76,22 @@ struct FaceGrad {
     float gx[3], gy[3], gzv[3];
 };
 
-// Upstream gradients of slot s (zero for an absent array).
+// Upstream gradients of slot s (zero for an absent array).  They and the
+// slots' face ids are read once, so the binned pass loads them non-temporally
+// (the "nt" hint), leaving L2 to the face records that neighbouring bins share.
 struct SlotUp {
     float gz, gb0, gb1, gb2, gd;
 };
 __device__ __forceinline__ SlotUp load_up(const BwdArgs& a, int64_t s) {
     SlotUp u;
-    u.gz = a.gz ? a.gz[s] : 0.0f;
+    u.gz = a.gz ? __builtin_nontemporal_load(a.gz + s) : 0.0f;
     u.gb0 = u.gb1 = u.gb2 = 0.0f;
     if (a.gb) {
-        u.gb0 = a.gb[3 * s + 0];
-        u.gb1 = a.gb[3 * s + 1];
-        u.gb2 = a.gb[3 * s + 2];
+        u.gb0 = __builtin_nontemporal_load(a.gb + 3 * s + 0);
+        u.gb1 = __builtin_nontemporal_load(a.gb + 3 * s + 1);
+        u.gb2 = __builtin_nontemporal_load(a.gb + 3 * s + 2);
     }
-    u.gd = a.gd ? a.gd[s] : 0.0f;
+    u.gd = a.gd ? __builtin_nontemporal_load(a.gd + s) : 0.0f;
     return u;
 }
 
@@ -669,7 +671,8 @@ void bwd_bins_kernel(BwdArgs a, int rescue) {
                 rq[u] = r0 + w.pr;
                 cq[u] = c0 + w.pc;
                 int f = -1;
-                if (q < nslots) f = a.p2f[sbase + (int64_t)(w.pr * a.W + w.pc) * a.K + w.k];
+                if (q < nslots)
+                    f = __builtin_nontemporal_load(a.p2f + sbase + (int64_t)(w.pr * a.W + w.pc) * a.K + w.k);
                 fq[u] = (f >= 0 && f < a.F) ? f : -1;
                 w.next(a.K, cols);
             }
@@ -788,7 +791,7 @@ void bwd_bins_kernel(BwdArgs a, int rescue) {
                     sq[u] = 0;
                     if (q < nslots) {
                         sq[u] = sbase + ((int64_t)(w.pr * a.W + w.pc) * a.K + w.k);
-                        fq[u] = a.p2f[sq[u]];
+                        fq[u] = __builtin_nontemporal_load(a.p2f + sq[u]);
                     }
                     w.next(a.K, cols);
                 }
