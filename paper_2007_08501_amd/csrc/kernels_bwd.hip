@@ -761,8 +761,9 @@ void bwd_bins_kernel(BwdArgs a, int rescue) {
             for (int i = threadIdx.x; i < kP1Table; i += kP1Threads) tkey[i] = -1;
             for (int i = threadIdx.x; i < m * 9; i += kP1Threads) acci[i] = 0ull;
             __syncthreads();
-            if (threadIdx.x < m) {
-                const int j = threadIdx.x;
+            const int t = threadIdx.x;
+            if (t < m) {
+                const int j = t;
                 const int f = list[base + j];
                 const FaceRec& G = a.recs[f];
                 store_bin_rec(srec[j], G, f);
@@ -816,8 +817,7 @@ void bwd_bins_kernel(BwdArgs a, int rescue) {
             }
             __syncthreads();
             // flush: one partial per listed face (written and marked, zero or not)
-            if (threadIdx.x < m) flush_face(a, &acci[9 * threadIdx.x], sdst[threadIdx.x], srec[threadIdx.x].face, S,
-                                            track, &smax);
+            if (t < m) flush_face(a, &acci[9 * t], sdst[t], srec[t].face, S, track, &smax);
             __syncthreads();
         }
         __syncthreads();  // (a bin without chunks has no barrier of its own)
